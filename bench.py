@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the per-column multiple Arnoldi solve on one MI355X.
+
+One step = one ma_solve_columns call over every column of the workload: inner
+CG, S-orthonormal multiple-Krylov basis, Galerkin pair, reduced eigenproblem,
+chemical-potential bisection, Fermi-weighted rho/pi and the scalar band energy
+and electron count.  The system (H, S, regions) is built and resident in HBM
+before the timed region; its build time is reported separately.
+
+Prints one JSON line (rank 0).  Only one GPU is supported.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Green's-fn columns/s at fixed ρ_ij error; learned vs zero-start CG; HBM %peak"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_1202_0098_amd import synth
+    if name == "diamond4096":
+        return synth.config_diamond4096()
+    if name == "diamond64":
+        return synth.config_diamond64()
+    if name == "disordered8000":
+        return synth.config_disordered8000()
+    if name.startswith("fcc_spd"):
+        return synth.config_fcc_spd()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="diamond4096")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--cpu-sample", type=int, default=1024,
+                    help="columns of the oracle CPU baseline sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1202_0098_amd as ma
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    s = workload(args.workload)
+    log(f"workload {s.name}: atoms={s.n_atoms} M={s.M} blocks={s.nblk} p={s.p} q={s.q}")
+    ctx = ma.Context(0)
+    t0 = time.perf_counter()
+    ctx.build_tb(s)
+    build_s = time.perf_counter() - t0
+    info = ctx.info()
+    log(f"built in {build_s:.2f}s: {info}")
+    o = s.n_orb
+    nu = s.p + s.q
+    dev = "cuda"
+    rho = torch.zeros(s.nblk * o * o, dtype=torch.float64, device=dev)
+    pi = torch.zeros_like(rho)
+    stats = torch.zeros(s.M * 4, dtype=torch.int32, device=dev)
+    opts = ma.default_opts(precision=args.precision)
+
+    def step():
+        return ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts,
+                                 rho=rho, pi=pi, col_stats=stats)
+
+    for w in range(args.warmup):
+        r = step()
+        log(f"warmup {w}: {r.elapsed_ms:.2f} ms (kernel {r.kernel_ms:.2f} ms) E={r.energy:.6f} "
+            f"N={r.n_elec:.6f} mu={r.mu:.9f}")
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = step()
+        kernel_ms.append(r.kernel_ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    cols_per_s = s.M / (wall / args.steps)
+    st = stats.cpu().numpy().reshape(s.M, 4)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {cols_per_s:.4g} columns/s; "
+        f"nu_eff mean {st[:, 0].mean():.2f}, CG iters mean {st[:, 1].mean():.2f}")
+
+    # ---- roofline of the column kernel -------------------------------------
+    k_ms = float(np.mean(kernel_ms))
+    reg_atoms, loc_blocks = ctx.region_sizes(s.n_atoms)
+    counts = kernel_model(s, st, reg_atoms, loc_blocks, args.precision)
+    achieved_tflops = counts["flops"] / (k_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved_tflops, 4),
+        "peak": PEAK_FP64_VECTOR_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / PEAK_FP64_VECTOR_TFLOPS, 5),
+        "traffic": None,
+        "kernel": "k_solve",
+        "kernel_ms": round(k_ms, 4),
+        "model_bytes_GBs": round(counts["bytes"] / (k_ms * 1e-3) / 1e9, 2),
+    }
+
+    # ---- CPU baseline: the oracle on a bounded sample ----------------------
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+        cols = np.sort(np.random.default_rng(12345).choice(s.M, min(args.cpu_sample, s.M),
+                                                           replace=False)).astype(np.int32)
+        oracle.build()
+        t0 = time.perf_counter()
+        res = oracle.solve(s, cols=cols)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(len(cols) / dt, 2), "unit": "columns/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{len(cols)} seeded random columns of the same workload "
+                         f"(regions, CG, basis, eigensolve, bisection over the sample), "
+                         f"{dt:.1f} s"}
+        log(f"cpu oracle: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(cols_per_s, 2),
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": s.name, "atoms": s.n_atoms, "columns": s.M, "p": s.p, "q": s.q,
+                   "kT": s.kT, "mu": "bisected at half filling", "precision": args.precision,
+                   "build_s": round(build_s, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def kernel_model(s, st, reg_atoms, loc_blocks, precision):
+    """Algorithmic flops and operator bytes of one column-kernel launch.
+
+    Per column j with region dimension n = o * (atoms of the region), local
+    operator blocks nb (o x o each), nu_eff = L accepted basis vectors and c
+    operator applications in the CG (iterations plus FP64 residual checks):
+      operator applications  c (S) + 2 L (fused H and S on each candidate)
+                             + q (H on the chain vectors of block 2)
+      SpMV flops             2 o^2 nb per application
+      Gram-Schmidt, projection  ~ 6 n L^2 FP64 flops (two CGS passes, dots and
+                             updates, 4 n L^2 / 2 summed; H~ and S~ with both
+                             triangles, 4 n L^2 / 2)
+      operator bytes         nb (o^2 value bytes + 8 index bytes) per application
+    """
+    o = s.n_orb
+    a = np.arange(s.M) // o
+    L = st[:, 0].astype(float)
+    c = st[:, 1].astype(float) + st[:, 2].astype(float)
+    n = reg_atoms[a].astype(float) * o
+    nb = loc_blocks[a].astype(float)
+    apps = c + 2 * L + s.q
+    flops = float(np.sum(2 * o * o * nb * apps + 6 * n * L * L))
+    vbytes = 4 if precision == "mixed" else 8
+    bytes_ = float(np.sum(apps * nb * (o * o * vbytes + 8)))
+    return {"flops": flops, "bytes": bytes_}
+
+
+if __name__ == "__main__":
+    main()

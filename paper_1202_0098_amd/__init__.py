@@ -1,0 +1,239 @@
+"""MI355X-native multiple Arnoldi solver (arXiv:1202.0098): Python binding.
+
+A thin ctypes layer over ``libmarnoldi.so`` (HIP, gfx950), whose C interface
+is ``include/marnoldi.h``.  This module only marshals arguments: every step of
+the solve runs in the library's kernels.  PyTorch supplies device memory and
+the stream.  If the library has not been built, importing works but every
+call raises: there is no other code path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmarnoldi.so")
+
+MA_OK, MA_EINVAL, MA_ENOMEM, MA_EDEVICE, MA_ENOTPD, MA_ENOCONV, MA_ESTATE = 0, -1, -2, -3, -4, -5, -6
+REGION_MODES = {"all": 0, "radius": 1, "nearest": 2}
+PREC = {"fp64": 0, "mixed": 1}
+
+# the functions include/marnoldi.h declares
+API_FUNCTIONS = ("ma_version", "ma_default_opts", "ma_create", "ma_destroy", "ma_last_error",
+                 "ma_build_system", "ma_system_info", "ma_region_sizes", "ma_region_atoms",
+                 "ma_solve_columns")
+
+
+class MarnoldiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32),
+                ("blk_ptr", ctypes.c_void_p), ("blk_col", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("xyz", ctypes.c_void_p), ("box", ctypes.c_void_p)]
+
+
+class _Region(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("radius", ctypes.c_double),
+                ("n_rp", ctypes.c_int32), ("n_rp_atom", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("breakdown_tau", ctypes.c_double), ("spin", ctypes.c_double),
+                ("n_target", ctypes.c_double), ("start", ctypes.c_int32),
+                ("slots_per_cu", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("pi", ctypes.c_void_p), ("eps", ctypes.c_void_p),
+                ("wts", ctypes.c_void_p), ("col_stats", ctypes.c_void_p),
+                ("energy", ctypes.c_double), ("n_elec", ctypes.c_double),
+                ("mu", ctypes.c_double), ("elapsed_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_available() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+def load_library():
+    """Load libmarnoldi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MarnoldiError(MA_ESTATE, f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                            "(or python paper_1202_0098_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.ma_version.restype = ctypes.c_char_p
+    lib.ma_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    lib.ma_create.argtypes = [ctypes.POINTER(P), i32, P]
+    lib.ma_destroy.argtypes = [P]
+    lib.ma_last_error.argtypes = [P]
+    lib.ma_last_error.restype = ctypes.c_char_p
+    lib.ma_build_system.argtypes = [P, ctypes.POINTER(_System), ctypes.POINTER(_Region)]
+    lib.ma_system_info.argtypes = [P, P, P, P, P]
+    lib.ma_solve_columns.argtypes = [P, i64, P, i32, i32, f64, f64, ctypes.POINTER(_Opts),
+                                     ctypes.POINTER(_Result)]
+    lib.ma_region_sizes.argtypes = [P, P, P]
+    lib.ma_region_sizes.restype = ctypes.c_int
+    lib.ma_region_atoms.argtypes = [ctypes.POINTER(_System), ctypes.POINTER(_Region), i32, P, i64]
+    lib.ma_region_atoms.restype = ctypes.c_int64
+    for name in ("ma_create", "ma_destroy", "ma_build_system", "ma_system_info",
+                 "ma_solve_columns"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load_library().ma_version().decode()
+
+
+def default_opts(**kw) -> _Opts:
+    o = _Opts()
+    load_library().ma_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PREC[v]
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def region_atoms(tb, atom: int) -> np.ndarray:
+    """The library's region of `atom` for a TBSystem-like input (host only)."""
+    lib = load_library()
+    blk_ptr = np.ascontiguousarray(tb.blk_ptr, np.int64)
+    blk_col = np.ascontiguousarray(tb.blk_col, np.int32)
+    H = np.ascontiguousarray(tb.H, np.float64)
+    xyz = np.ascontiguousarray(tb.pos, np.float64)
+    box = np.ascontiguousarray(tb.box, np.float64)
+    nrp = None if tb.region_nrp is None else np.ascontiguousarray(tb.region_nrp, np.int32)
+    sysd = _System(tb.n_atoms, tb.n_orb, _ptr(blk_ptr), _ptr(blk_col), _ptr(H), _ptr(H),
+                   _ptr(xyz), _ptr(box))
+    reg = _Region(REGION_MODES[tb.region_mode], float(tb.region_radius), 0, _ptr(nrp))
+    out = np.zeros(tb.n_atoms, np.int32)
+    n = lib.ma_region_atoms(ctypes.byref(sysd), ctypes.byref(reg), int(atom), _ptr(out),
+                            tb.n_atoms)
+    if n < 0:
+        raise MarnoldiError(int(n), "ma_region_atoms: invalid arguments")
+    return out[:n].copy()
+
+
+@dataclass
+class SolveResult:
+    energy: float
+    n_elec: float
+    mu: float
+    elapsed_ms: float
+    kernel_ms: float
+
+
+class Context:
+    """One library context bound to a device and a stream (torch's current
+    stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load_library()
+        self._lib = lib
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib.ma_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != MA_OK:
+            raise MarnoldiError(st, "ma_create failed")
+        self._h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ma_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != MA_OK:
+            raise MarnoldiError(st, self._lib.ma_last_error(self._h).decode())
+
+    def build_system(self, n_atoms, n_orb, blk_ptr, blk_col, H, S, xyz=None, box=None,
+                     region="all", radius=0.0, n_rp=0, n_rp_atom=None):
+        """Upload a block-sparse pencil and build the regions (host arrays)."""
+        arrs = dict(blk_ptr=np.ascontiguousarray(blk_ptr, np.int64),
+                    blk_col=np.ascontiguousarray(blk_col, np.int32),
+                    H=np.ascontiguousarray(H, np.float64),
+                    S=np.ascontiguousarray(S, np.float64),
+                    xyz=None if xyz is None else np.ascontiguousarray(xyz, np.float64),
+                    box=None if box is None else np.ascontiguousarray(box, np.float64),
+                    nrp=None if n_rp_atom is None else np.ascontiguousarray(n_rp_atom, np.int32))
+        sysd = _System(int(n_atoms), int(n_orb), _ptr(arrs["blk_ptr"]), _ptr(arrs["blk_col"]),
+                       _ptr(arrs["H"]), _ptr(arrs["S"]), _ptr(arrs["xyz"]), _ptr(arrs["box"]))
+        reg = _Region(REGION_MODES[region], float(radius), int(n_rp), _ptr(arrs["nrp"]))
+        self._check(self._lib.ma_build_system(self._h, ctypes.byref(sysd), ctypes.byref(reg)))
+
+    def build_tb(self, tb):
+        """build_system from a :class:`synth.TBSystem`-like object."""
+        self.build_system(tb.n_atoms, tb.n_orb, tb.blk_ptr, tb.blk_col, tb.H, tb.S,
+                          xyz=tb.pos, box=tb.box, region=tb.region_mode,
+                          radius=tb.region_radius, n_rp=0, n_rp_atom=tb.region_nrp)
+
+    def info(self):
+        M, nblk = ctypes.c_int64(), ctypes.c_int64()
+        nmax, maxpat = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.ma_system_info(self._h, ctypes.byref(M), ctypes.byref(nblk),
+                                             ctypes.byref(nmax), ctypes.byref(maxpat)))
+        return dict(M=M.value, nblk=nblk.value, nmax=nmax.value, maxpat=maxpat.value)
+
+    def region_sizes(self, n_atoms: int):
+        """(atoms per region, local operator blocks) for every atom."""
+        ra = np.zeros(n_atoms, np.int32)
+        lb = np.zeros(n_atoms, np.int64)
+        self._check(self._lib.ma_region_sizes(self._h, _ptr(ra), _ptr(lb)))
+        return ra, lb
+
+    def solve_columns(self, cols, p, q, mu=math.nan, kT=0.1, opts=None, rho=None, pi=None,
+                      eps=None, wts=None, col_stats=None) -> SolveResult:
+        """Solve the listed columns (None = all).  rho/pi/eps/wts/col_stats are
+        optional torch device tensors (float64 / int32) written by the library."""
+        if cols is None:
+            cptr, n = None, 0
+        else:
+            cols = np.ascontiguousarray(cols, np.int32)
+            cptr, n = _ptr(cols), len(cols)
+        o = opts if opts is not None else default_opts()
+        res = _Result(_ptr(rho), _ptr(pi), _ptr(eps), _ptr(wts), _ptr(col_stats), 0.0, 0.0, 0.0,
+                      0.0, 0.0)
+        self._check(self._lib.ma_solve_columns(self._h, n, cptr, int(p), int(q), float(mu),
+                                               float(kT), ctypes.byref(o), ctypes.byref(res)))
+        return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, res.kernel_ms)

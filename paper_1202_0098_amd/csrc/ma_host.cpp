@@ -1,0 +1,775 @@
+// Host side of libmarnoldi: the C interface declared in include/marnoldi.h.
+//
+// ma_build_system validates the block-sparse pencil, builds the real-space
+// region of every atom (Sec. 3 of arXiv:1202.0098: H and S are projected on a
+// sphere, or the N_RP nearest atoms, around the atom of basis j), the local
+// block index of every region, and uploads FP64 and FP32 copies of H and S.
+// ma_solve_columns orders the columns largest region first, launches the
+// persistent column kernel, the chemical-potential bisection and the
+// Fermi-weighting pass, and reduces the scalars.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/marnoldi.h"
+#include "ma_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow to at least n bytes (contents are not preserved)
+    hipError_t reserve(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n ? n : 16);
+        if (e == hipSuccess) bytes = n ? n : 16;
+        return e;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+template <typename F>
+void parallel_for(int64_t n, F &&f)
+{
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (n < 64 || nt == 1) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::atomic<int64_t> next(0);
+    const int64_t chunk = std::max<int64_t>(1, n / (nt * 16));
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (;;) {
+                int64_t b = next.fetch_add(chunk);
+                if (b >= n) break;
+                f(b, std::min(n, b + chunk), (int)t);
+            }
+        });
+    for (auto &x : th) x.join();
+}
+
+}  // namespace
+
+struct ma_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err = "no error";
+    int cu_count = 0;
+    bool built = false;
+
+    // system sizes
+    int o = 0, n_atoms = 0;
+    int64_t nblk = 0, M = 0;
+    int nmax = 0, maxpat = 0;
+    std::vector<int32_t> reg_len_of_atom;   // host: region atoms per atom (for ordering)
+    std::vector<int64_t> lblk_of_atom;      // host: local operator blocks per atom
+
+    // device system
+    DevBuf blk_ptr, blk_col, Hd, Sd, Hf, Sf, reg_id, reg_off, reg_len, lrp_off, lrp, lblk, jloc,
+        blk_loc;
+
+    // device solve buffers
+    DevBuf cols, order, ws, eps, wts, amp, stats, ctl, lohi, partial, Ecol, Ncol, sums;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
+
+    ma_status fail(ma_status s, const char *fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+    ma_status hip_fail(hipError_t e, const char *what)
+    {
+        return fail(e == hipErrorOutOfMemory ? MA_ENOMEM : MA_EDEVICE, "%s: %s", what,
+                    hipGetErrorString(e));
+    }
+
+    ma::DevSystem dev_system() const
+    {
+        ma::DevSystem S;
+        S.o = o;
+        S.n_atoms = n_atoms;
+        S.nmax = nmax;
+        S.maxpat = maxpat;
+        S.blk_ptr = blk_ptr.as<int64_t>();
+        S.blk_col = blk_col.as<int32_t>();
+        S.Hd = Hd.as<double>();
+        S.Sd = Sd.as<double>();
+        S.Hf = Hf.as<float>();
+        S.Sf = Sf.as<float>();
+        S.reg_id = reg_id.as<int32_t>();
+        S.reg_off = reg_off.as<int64_t>();
+        S.reg_len = reg_len.as<int32_t>();
+        S.lrp_off = lrp_off.as<int64_t>();
+        S.lrp = lrp.as<int64_t>();
+        S.lblk = lblk.as<int2>();
+        S.jloc = jloc.as<int32_t>();
+        S.blk_loc = blk_loc.as<int32_t>();
+        return S;
+    }
+};
+
+#define HIPCHK(ctx, expr, what)                                 \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, what); \
+    } while (0)
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// regions
+// ---------------------------------------------------------------------------
+struct CellGrid {
+    bool periodic = false;
+    double box[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, cs[3] = {1, 1, 1};
+    int nc[3] = {1, 1, 1};
+    std::vector<int32_t> start, atoms;   // atoms sorted by cell
+
+    int cell_of(const double *x, int d) const
+    {
+        double f = (x[d] - lo[d]) / cs[d];
+        int c = (int)std::floor(f);
+        if (periodic) {
+            c %= nc[d];
+            if (c < 0) c += nc[d];
+        } else {
+            c = std::min(std::max(c, 0), nc[d] - 1);
+        }
+        return c;
+    }
+    void build(int n, const double *xyz, const double *bx, double cell_size)
+    {
+        periodic = bx != nullptr;
+        for (int d = 0; d < 3; ++d) {
+            double mn = 1e300, mx = -1e300;
+            if (periodic) {
+                mn = 0.0;
+                mx = bx[d];
+                box[d] = bx[d];
+            } else {
+                for (int a = 0; a < n; ++a) {
+                    mn = std::min(mn, xyz[3 * a + d]);
+                    mx = std::max(mx, xyz[3 * a + d]);
+                }
+                mx += 1e-9;
+            }
+            lo[d] = mn;
+            nc[d] = std::max(1, std::min(512, (int)std::floor((mx - mn) / cell_size)));
+            cs[d] = (mx - mn) / nc[d];
+            if (cs[d] <= 0) cs[d] = 1.0;
+        }
+        const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+        std::vector<int64_t> cid(n);
+        start.assign(ncell + 1, 0);
+        for (int a = 0; a < n; ++a) {
+            int64_t c = ((int64_t)cell_of(xyz + 3 * a, 0) * nc[1] + cell_of(xyz + 3 * a, 1)) * nc[2] +
+                        cell_of(xyz + 3 * a, 2);
+            cid[a] = c;
+            start[c + 1]++;
+        }
+        for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+        atoms.assign(n, 0);
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (int a = 0; a < n; ++a) atoms[fill[cid[a]]++] = a;
+    }
+};
+
+inline double min_image_d2(const double *xyz, const double *box, int a, int b)
+{
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        double v = xyz[3 * b + k] - xyz[3 * a + k];
+        if (box) v = v - box[k] * std::nearbyint(v / box[k]);
+        d[k] = v;
+    }
+    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+// Candidate atoms within squared distance r2 of atom a (all atoms if the
+// search sphere covers the whole grid).  Appends (d2, atom).
+void gather_within(const CellGrid &G, const double *xyz, const double *box, int n, int a, double r,
+                   std::vector<std::pair<double, int32_t>> &out)
+{
+    out.clear();
+    const double r2 = r * r;
+    int span[3], c0[3];
+    bool all = false;
+    for (int d = 0; d < 3; ++d) {
+        span[d] = (int)std::ceil(r / G.cs[d]);
+        if (2 * span[d] + 1 >= G.nc[d]) all = true;
+        c0[d] = G.cell_of(xyz + 3 * a, d);
+    }
+    if (all) {
+        for (int b = 0; b < n; ++b) {
+            double d2 = min_image_d2(xyz, box, a, b);
+            if (d2 < r2) out.emplace_back(d2, b);
+        }
+        return;
+    }
+    for (int dx = -span[0]; dx <= span[0]; ++dx)
+        for (int dy = -span[1]; dy <= span[1]; ++dy)
+            for (int dz = -span[2]; dz <= span[2]; ++dz) {
+                int c[3] = {c0[0] + dx, c0[1] + dy, c0[2] + dz};
+                bool skip = false;
+                for (int d = 0; d < 3; ++d) {
+                    if (G.periodic) {
+                        c[d] %= G.nc[d];
+                        if (c[d] < 0) c[d] += G.nc[d];
+                    } else if (c[d] < 0 || c[d] >= G.nc[d]) {
+                        skip = true;
+                    }
+                }
+                if (skip) continue;
+                const int64_t cc = ((int64_t)c[0] * G.nc[1] + c[1]) * G.nc[2] + c[2];
+                for (int32_t k = G.start[cc]; k < G.start[cc + 1]; ++k) {
+                    const int b = G.atoms[k];
+                    double d2 = min_image_d2(xyz, box, a, b);
+                    if (d2 < r2) out.emplace_back(d2, b);
+                }
+            }
+}
+
+// Region atom lists (ascending): one shared list for MA_REGION_ALL, else one
+// per atom.  Arguments are assumed validated.
+void compute_regions(const ma_system *sys, const ma_region *reg,
+                     std::vector<std::vector<int32_t>> &lists)
+{
+    const int n = sys->n_atoms;
+    const bool shared = reg->mode == MA_REGION_ALL;
+    lists.assign(shared ? 1 : n, {});
+    if (shared) {
+        lists[0].resize(n);
+        std::iota(lists[0].begin(), lists[0].end(), 0);
+    } else {
+        const double *xyz = sys->xyz, *box = sys->box;
+        double vol = 1.0;
+        double lo3[3], hi3[3];
+        for (int d = 0; d < 3; ++d) {
+            lo3[d] = 1e300;
+            hi3[d] = -1e300;
+            for (int a = 0; a < n; ++a) {
+                lo3[d] = std::min(lo3[d], xyz[3 * a + d]);
+                hi3[d] = std::max(hi3[d], xyz[3 * a + d]);
+            }
+            vol *= box ? box[d] : std::max(1.0, hi3[d] - lo3[d]);
+        }
+        const double dens = n / vol;
+        double rcell = reg->mode == MA_REGION_RADIUS ? reg->radius : 0.0;
+        if (reg->mode == MA_REGION_NEAREST) {
+            int kmax = 0;
+            for (int a = 0; a < n; ++a) kmax = std::max(kmax, reg->n_rp_atom ? reg->n_rp_atom[a] : reg->n_rp);
+            rcell = std::cbrt(3.0 * kmax / (4.0 * M_PI * dens));
+        }
+        CellGrid G;
+        G.build(n, xyz, box, std::max(rcell, 1e-6) * 0.5);
+        parallel_for(n, [&](int64_t a0, int64_t a1, int) {
+            std::vector<std::pair<double, int32_t>> cand;
+            for (int64_t a = a0; a < a1; ++a) {
+                std::vector<int32_t> &L = lists[a];
+                if (reg->mode == MA_REGION_RADIUS) {
+                    gather_within(G, xyz, box, n, (int)a, reg->radius, cand);
+                    // strict d2 < radius^2 as in gather_within
+                    L.resize(cand.size());
+                    for (size_t i = 0; i < cand.size(); ++i) L[i] = cand[i].second;
+                } else {
+                    const int k = reg->n_rp_atom ? reg->n_rp_atom[a] : reg->n_rp;
+                    double r = std::cbrt(3.0 * k / (4.0 * M_PI * dens)) * 1.3 + 1e-9;
+                    for (;;) {
+                        gather_within(G, xyz, box, n, (int)a, r, cand);
+                        if ((int)cand.size() >= k) break;
+                        r *= 1.25;
+                    }
+                    std::partial_sort(cand.begin(), cand.begin() + k, cand.end());  // (d2, atom) order
+                    L.resize(k);
+                    for (int i = 0; i < k; ++i) L[i] = cand[i].second;
+                }
+                std::sort(L.begin(), L.end());
+            }
+        });
+    }
+
+}
+
+// Validation of the region arguments shared by the entry points.
+const char *check_region(const ma_system *sys, const ma_region *reg)
+{
+    const int n = sys->n_atoms;
+    if (reg->mode != MA_REGION_ALL && reg->mode != MA_REGION_RADIUS && reg->mode != MA_REGION_NEAREST)
+        return "unknown region mode";
+    if (reg->mode != MA_REGION_ALL && !sys->xyz)
+        return "positions are required for radius or nearest regions";
+    if (sys->box)
+        for (int d = 0; d < 3; ++d)
+            if (!(sys->box[d] > 0)) return "box lengths must be positive";
+    if (reg->mode == MA_REGION_RADIUS && !(reg->radius > 0)) return "region radius must be positive";
+    if (reg->mode == MA_REGION_NEAREST)
+        for (int a = 0; a < n; ++a) {
+            const int k = reg->n_rp_atom ? reg->n_rp_atom[a] : reg->n_rp;
+            if (k < 1 || k > n) return "n_rp out of range";
+        }
+    return nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public interface
+// ---------------------------------------------------------------------------
+extern "C" {
+
+MA_API const char *ma_version(void) { return "marnoldi 0.1 (gfx950)"; }
+
+MA_API void ma_default_opts(ma_opts *o)
+{
+    if (!o) return;
+    o->precision = MA_PREC_FP64;
+    o->cg_tol = 1e-12;
+    o->inner_tol = 1e-6;
+    o->max_refine = 8;
+    o->breakdown_tau = 1e-10;
+    o->spin = 2.0;
+    o->n_target = NAN;
+    o->start = MA_START_ZERO;
+    o->slots_per_cu = 0;
+}
+
+MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
+{
+    if (!out) return MA_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MA_EDEVICE;
+    ma_ctx *c = new (std::nothrow) ma_ctx;
+    if (!c) return MA_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->evk0) != hipSuccess || hipEventCreate(&c->evk1) != hipSuccess) {
+        delete c;
+        return MA_EDEVICE;
+    }
+    *out = c;
+    return MA_OK;
+}
+
+MA_API ma_status ma_destroy(ma_ctx *ctx)
+{
+    if (!ctx) return MA_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->evk0) (void)hipEventDestroy(ctx->evk0);
+    if (ctx->evk1) (void)hipEventDestroy(ctx->evk1);
+    delete ctx;
+    return MA_OK;
+}
+
+MA_API const char *ma_last_error(const ma_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+MA_API ma_status ma_system_info(const ma_ctx *ctx, int64_t *M, int64_t *nblk, int32_t *nmax,
+                                int32_t *maxpat)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built) return MA_ESTATE;
+    if (M) *M = ctx->M;
+    if (nblk) *nblk = ctx->nblk;
+    if (nmax) *nmax = ctx->nmax;
+    if (maxpat) *maxpat = ctx->maxpat;
+    return MA_OK;
+}
+
+MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_region *reg)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!sys || !reg) return ctx->fail(MA_EINVAL, "null system or region");
+    ctx->built = false;
+    const int n = sys->n_atoms, o = sys->n_orb;
+    if (n < 1) return ctx->fail(MA_EINVAL, "n_atoms must be >= 1");
+    if (o < 1 || o > MA_MAX_ORB) return ctx->fail(MA_EINVAL, "n_orb must be in 1..%d", MA_MAX_ORB);
+    if (!sys->blk_ptr || !sys->blk_col || !sys->H || !sys->S)
+        return ctx->fail(MA_EINVAL, "null matrix array");
+    const int64_t *bp = sys->blk_ptr;
+    const int32_t *bc = sys->blk_col;
+    if (bp[0] != 0) return ctx->fail(MA_EINVAL, "blk_ptr[0] must be 0");
+    for (int a = 0; a < n; ++a)
+        if (bp[a + 1] < bp[a]) return ctx->fail(MA_EINVAL, "blk_ptr not monotone at atom %d", a);
+    const int64_t nblk = bp[n];
+    if (nblk > INT_MAX) return ctx->fail(MA_EINVAL, "more than 2^31 blocks");
+    const int oo = o * o;
+    // pattern: ascending columns in range, diagonal present
+    for (int a = 0; a < n; ++a) {
+        bool diag = false;
+        for (int64_t k = bp[a]; k < bp[a + 1]; ++k) {
+            if (bc[k] < 0 || bc[k] >= n) return ctx->fail(MA_EINVAL, "blk_col out of range in row %d", a);
+            if (k > bp[a] && bc[k] <= bc[k - 1])
+                return ctx->fail(MA_EINVAL, "blk_col not strictly ascending in row %d", a);
+            if (bc[k] == a) diag = true;
+        }
+        if (!diag) return ctx->fail(MA_EINVAL, "diagonal block missing in row %d", a);
+    }
+    // values finite, pattern and values symmetric
+    std::atomic<int64_t> bad(-1);
+    std::atomic<int> bad_kind(0);
+    parallel_for(n, [&](int64_t a0, int64_t a1, int) {
+        for (int64_t a = a0; a < a1; ++a)
+            for (int64_t k = bp[a]; k < bp[a + 1]; ++k) {
+                for (int e = 0; e < oo; ++e)
+                    if (!std::isfinite(sys->H[k * oo + e]) || !std::isfinite(sys->S[k * oo + e])) {
+                        bad = a;
+                        bad_kind = 1;
+                        return;
+                    }
+                const int b = bc[k];
+                const int32_t *lo = bc + bp[b], *hi = bc + bp[b + 1];
+                const int32_t *f = std::lower_bound(lo, hi, (int32_t)a);
+                if (f == hi || *f != a) {
+                    bad = a;
+                    bad_kind = 2;
+                    return;
+                }
+                const int64_t kt = f - bc;
+                for (int r = 0; r < o; ++r)
+                    for (int c = 0; c < o; ++c) {
+                        const double h1 = sys->H[k * oo + r * o + c], h2 = sys->H[kt * oo + c * o + r];
+                        const double s1 = sys->S[k * oo + r * o + c], s2 = sys->S[kt * oo + c * o + r];
+                        if (std::fabs(h1 - h2) > 1e-12 * std::max(1.0, std::fabs(h1)) ||
+                            std::fabs(s1 - s2) > 1e-12 * std::max(1.0, std::fabs(s1))) {
+                            bad = a;
+                            bad_kind = 3;
+                            return;
+                        }
+                    }
+            }
+    });
+    if (bad >= 0) {
+        static const char *what[] = {"", "non-finite value", "asymmetric block pattern",
+                                     "asymmetric H or S values"};
+        return ctx->fail(MA_EINVAL, "%s in block-row %lld", what[bad_kind.load()], (long long)bad.load());
+    }
+
+    // ---- regions ----
+    if (const char *why = check_region(sys, reg)) return ctx->fail(MA_EINVAL, "%s", why);
+    const bool shared = reg->mode == MA_REGION_ALL;
+    const int nreg = shared ? 1 : n;
+    std::vector<std::vector<int32_t>> lists;
+    compute_regions(sys, reg, lists);
+    // ---- local block index per region, pattern check ----
+    std::vector<int32_t> h_reg_id(n), h_reg_len(nreg), h_jloc(n), h_blk_loc(nblk);
+    std::vector<int64_t> h_reg_off(nreg + 1), h_lrp_off(nreg + 1), cnt(nreg + 1, 0);
+    h_reg_off[0] = 0;
+    for (int r = 0; r < nreg; ++r) {
+        h_reg_len[r] = (int32_t)lists[r].size();
+        h_reg_off[r + 1] = h_reg_off[r] + h_reg_len[r];
+    }
+    for (int a = 0; a < n; ++a) h_reg_id[a] = shared ? 0 : a;
+    h_lrp_off[0] = 0;
+    for (int r = 0; r < nreg; ++r) h_lrp_off[r + 1] = h_lrp_off[r] + h_reg_len[r] + 1;
+    std::vector<int32_t> h_reg_atoms(h_reg_off[nreg]);
+    for (int r = 0; r < nreg; ++r)
+        std::copy(lists[r].begin(), lists[r].end(), h_reg_atoms.begin() + h_reg_off[r]);
+    // count local blocks per region
+    const unsigned nthr = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<std::vector<int32_t>> locs(nthr, std::vector<int32_t>(n, -1));
+    parallel_for(nreg, [&](int64_t r0, int64_t r1, int t) {
+        std::vector<int32_t> &loc = locs[t];
+        for (int64_t r = r0; r < r1; ++r) {
+            const auto &L = lists[r];
+            for (size_t i = 0; i < L.size(); ++i) loc[L[i]] = (int32_t)i;
+            int64_t c = 0;
+            for (int32_t b : L)
+                for (int64_t k = bp[b]; k < bp[b + 1]; ++k)
+                    if (loc[bc[k]] >= 0) ++c;
+            cnt[r + 1] = c;
+            for (int32_t b : L) loc[b] = -1;
+        }
+    });
+    std::vector<int64_t> lblk_off(nreg + 1, 0);
+    for (int r = 0; r < nreg; ++r) lblk_off[r + 1] = lblk_off[r] + cnt[r + 1];
+    std::vector<int64_t> h_lrp(h_lrp_off[nreg]);
+    std::vector<int2> h_lblk(std::max<int64_t>(1, lblk_off[nreg]));
+    std::atomic<int64_t> bad_region(-1);
+    parallel_for(nreg, [&](int64_t r0, int64_t r1, int t) {
+        std::vector<int32_t> &loc = locs[t];
+        for (int64_t r = r0; r < r1; ++r) {
+            const auto &L = lists[r];
+            for (size_t i = 0; i < L.size(); ++i) loc[L[i]] = (int32_t)i;
+            int64_t cur = lblk_off[r];
+            int64_t *rp = h_lrp.data() + h_lrp_off[r];
+            for (size_t i = 0; i < L.size(); ++i) {
+                rp[i] = cur;
+                const int32_t b = L[i];
+                for (int64_t k = bp[b]; k < bp[b + 1]; ++k) {
+                    const int32_t lc = loc[bc[k]];
+                    if (lc >= 0) h_lblk[cur++] = make_int2(lc, (int)k);
+                }
+            }
+            rp[L.size()] = cur;
+            // atoms served by this region: all (shared) or atom r
+            const int a0 = shared ? 0 : (int)r, a1 = shared ? n : (int)r + 1;
+            for (int a = a0; a < a1; ++a) {
+                if (loc[a] < 0) bad_region = a;
+                h_jloc[a] = loc[a];
+                for (int64_t k = bp[a]; k < bp[a + 1]; ++k) {
+                    h_blk_loc[k] = loc[bc[k]];
+                    if (loc[bc[k]] < 0) bad_region = a;
+                }
+            }
+            for (int32_t b : L) loc[b] = -1;
+        }
+    });
+    if (bad_region >= 0)
+        return ctx->fail(MA_EINVAL, "region of atom %lld does not contain its block-row pattern",
+                         (long long)bad_region.load());
+    int nmax = 0, maxpat = 0;
+    for (int r = 0; r < nreg; ++r) nmax = std::max(nmax, h_reg_len[r] * o);
+    for (int a = 0; a < n; ++a) maxpat = std::max(maxpat, (int)(bp[a + 1] - bp[a]) * o);
+    if (nmax > 8 * ma::kThreads)
+        return ctx->fail(MA_EINVAL, "region dimension %d exceeds the supported %d", nmax,
+                         8 * ma::kThreads);
+
+    // ---- upload ----
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    std::vector<float> Hf(nblk * oo), Sf(nblk * oo);
+    for (int64_t e = 0; e < nblk * oo; ++e) {
+        Hf[e] = (float)sys->H[e];
+        Sf[e] = (float)sys->S[e];
+    }
+    auto up = [&](DevBuf &b, const void *src, size_t bytes, const char *what) -> ma_status {
+        hipError_t e = b.reserve(bytes);
+        if (e != hipSuccess) return ctx->hip_fail(e, what);
+        if (bytes) {
+            e = hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+            if (e != hipSuccess) return ctx->hip_fail(e, what);
+        }
+        return MA_OK;
+    };
+    ma_status s;
+#define UP(buf, vec, what)                                                              \
+    if ((s = up(ctx->buf, (vec), sizeof(*(vec)) * (size_t)(count_), what)) != MA_OK) return s;
+    int64_t count_;
+    count_ = n + 1;       UP(blk_ptr, bp, "blk_ptr")
+    count_ = nblk;        UP(blk_col, bc, "blk_col")
+    count_ = nblk * oo;   UP(Hd, sys->H, "H")
+    count_ = nblk * oo;   UP(Sd, sys->S, "S")
+    count_ = nblk * oo;   UP(Hf, Hf.data(), "H fp32")
+    count_ = nblk * oo;   UP(Sf, Sf.data(), "S fp32")
+    count_ = n;           UP(reg_id, h_reg_id.data(), "reg_id")
+    count_ = nreg + 1;    UP(reg_off, h_reg_off.data(), "reg_off")
+    count_ = nreg;        UP(reg_len, h_reg_len.data(), "reg_len")
+    count_ = nreg + 1;    UP(lrp_off, h_lrp_off.data(), "lrp_off")
+    count_ = (int64_t)h_lrp.size();  UP(lrp, h_lrp.data(), "lrp")
+    count_ = (int64_t)h_lblk.size(); UP(lblk, h_lblk.data(), "lblk")
+    count_ = n;           UP(jloc, h_jloc.data(), "jloc")
+    count_ = nblk;        UP(blk_loc, h_blk_loc.data(), "blk_loc")
+#undef UP
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "upload");
+    ctx->o = o;
+    ctx->n_atoms = n;
+    ctx->nblk = nblk;
+    ctx->M = (int64_t)n * o;
+    ctx->nmax = nmax;
+    ctx->maxpat = maxpat;
+    ctx->reg_len_of_atom.resize(n);
+    ctx->lblk_of_atom.resize(n);
+    for (int a = 0; a < n; ++a) {
+        ctx->reg_len_of_atom[a] = h_reg_len[h_reg_id[a]];
+        ctx->lblk_of_atom[a] = cnt[h_reg_id[a] + 1];
+    }
+    ctx->built = true;
+    return MA_OK;
+}
+
+MA_API ma_status ma_region_sizes(const ma_ctx *ctx, int32_t *region_atoms, int64_t *local_blocks)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built) return MA_ESTATE;
+    if (region_atoms) std::copy(ctx->reg_len_of_atom.begin(), ctx->reg_len_of_atom.end(), region_atoms);
+    if (local_blocks) std::copy(ctx->lblk_of_atom.begin(), ctx->lblk_of_atom.end(), local_blocks);
+    return MA_OK;
+}
+
+MA_API int64_t ma_region_atoms(const ma_system *sys, const ma_region *reg, int32_t atom,
+                                int32_t *out, int64_t cap)
+{
+    if (!sys || !reg || sys->n_atoms < 1 || atom < 0 || atom >= sys->n_atoms) return MA_EINVAL;
+    if (check_region(sys, reg)) return MA_EINVAL;
+    ma_system one = *sys;
+    std::vector<std::vector<int32_t>> lists;
+    if (reg->mode == MA_REGION_ALL) {
+        compute_regions(&one, reg, lists);
+    } else {
+        // the same construction, restricted to one atom
+        std::vector<std::vector<int32_t>> all;
+        compute_regions(&one, reg, all);
+        lists.assign(1, std::move(all[atom]));
+    }
+    const auto &L = lists[0];
+    for (int64_t i = 0; i < (int64_t)L.size() && i < cap; ++i) out[i] = L[i];
+    return (int64_t)L.size();
+}
+
+MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
+                                  int32_t q, double mu, double kT, const ma_opts *opts_in,
+                                  ma_result *out)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built) return ctx->fail(MA_ESTATE, "ma_build_system has not succeeded");
+    if (!out) return ctx->fail(MA_EINVAL, "null result");
+    ma_opts opts;
+    ma_default_opts(&opts);
+    if (opts_in) opts = *opts_in;
+    if (p < 1 || q < 0 || p + q > MA_MAX_NU)
+        return ctx->fail(MA_EINVAL, "need p >= 1, q >= 0, p + q <= %d", MA_MAX_NU);
+    if (!(kT > 0) || !std::isfinite(kT)) return ctx->fail(MA_EINVAL, "kT must be positive");
+    if (std::isinf(mu)) return ctx->fail(MA_EINVAL, "mu must be finite or NaN");
+    if (opts.precision != MA_PREC_FP64 && opts.precision != MA_PREC_MIXED)
+        return ctx->fail(MA_EINVAL, "unknown precision %d", opts.precision);
+    if (!(opts.cg_tol > 0) || !(opts.breakdown_tau >= 0) || !(opts.inner_tol > 0) || opts.max_refine < 0)
+        return ctx->fail(MA_EINVAL, "invalid tolerances");
+    if (opts.start == MA_START_LEARNED)
+        return ctx->fail(MA_EINVAL, "no start model is set");
+    if (cols == nullptr) ncols = ctx->M;
+    if (ncols < 1 || ncols > INT_MAX) return ctx->fail(MA_EINVAL, "ncols out of range");
+    std::vector<int32_t> hcols(ncols);
+    for (int64_t c = 0; c < ncols; ++c) {
+        hcols[c] = cols ? cols[c] : (int32_t)c;
+        if (hcols[c] < 0 || hcols[c] >= ctx->M)
+            return ctx->fail(MA_EINVAL, "column %lld out of range", (long long)hcols[c]);
+    }
+    const double n_target = std::isnan(opts.n_target) ? 0.5 * (double)ncols : opts.n_target;
+    // largest region first (longest-processing-time order), stable
+    std::vector<int32_t> order(ncols);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return ctx->reg_len_of_atom[hcols[a] / ctx->o] > ctx->reg_len_of_atom[hcols[b] / ctx->o];
+    });
+    const int nu = p + q;
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+
+    ma::DevSystem S = ctx->dev_system();
+    ma::DevJob J{};
+    J.ncols = (int)ncols;
+    J.p = p;
+    J.q = q;
+    J.nu = nu;
+    J.precision = opts.precision;
+    J.cg_tol = opts.cg_tol;
+    J.inner_tol = opts.inner_tol;
+    J.tau = opts.breakdown_tau;
+    J.max_refine = opts.max_refine;
+    J.ws_stride = (int64_t)(3 * nu + q) * ctx->nmax;
+
+    int bpc = 0;
+    HIPCHK(ctx, ma::solve_occupancy(S, J, &bpc), "occupancy");
+    if (bpc < 1) return ctx->fail(MA_EINVAL, "column kernel does not fit on a compute unit (nu=%d, nmax=%d)", nu, ctx->nmax);
+    if (opts.slots_per_cu > 0) bpc = std::min(bpc, opts.slots_per_cu);
+    int slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, ncols);
+
+    HIPCHK(ctx, ctx->cols.reserve(sizeof(int32_t) * ncols), "cols");
+    HIPCHK(ctx, ctx->order.reserve(sizeof(int32_t) * ncols), "order");
+    HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * slots), "workspace");
+    HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * nu), "eps");
+    HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * nu), "wts");
+    HIPCHK(ctx, ctx->amp.reserve(sizeof(double) * (size_t)ncols * ctx->maxpat * nu), "amplitudes");
+    HIPCHK(ctx, ctx->stats.reserve(sizeof(int32_t) * (size_t)ncols * 4), "stats");
+    HIPCHK(ctx, ctx->ctl.reserve(sizeof(int) * 4), "ctl");
+    HIPCHK(ctx, ctx->lohi.reserve(sizeof(double) * 2), "lohi");
+    HIPCHK(ctx, ctx->partial.reserve(sizeof(double) * ma::kCountBlocks * ma::kBisectTrials), "partial");
+    HIPCHK(ctx, ctx->Ecol.reserve(sizeof(double) * ncols), "Ecol");
+    HIPCHK(ctx, ctx->Ncol.reserve(sizeof(double) * ncols), "Ncol");
+    HIPCHK(ctx, ctx->sums.reserve(sizeof(double) * 2), "sums");
+    hipStream_t st = ctx->stream;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "order");
+
+    J.cols = ctx->cols.as<int32_t>();
+    J.order = ctx->order.as<int32_t>();
+    J.queue = ctx->ctl.as<int>();
+    J.fail = ctx->ctl.as<int>() + 1;
+    J.ws = ctx->ws.as<double>();
+    J.eps = out->eps ? out->eps : ctx->eps.as<double>();
+    J.wts = out->wts ? out->wts : ctx->wts.as<double>();
+    J.amp = ctx->amp.as<double>();
+    J.stats = out->col_stats ? out->col_stats : ctx->stats.as<int32_t>();
+    J.x0 = nullptr;
+
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, st), "event");
+    HIPCHK(ctx, ma::launch_reset(J.queue, J.fail, st), "reset");
+    HIPCHK(ctx, hipEventRecord(ctx->evk0, st), "event");
+    HIPCHK(ctx, ma::launch_solve(S, J, slots, st), "column kernel");
+    HIPCHK(ctx, hipEventRecord(ctx->evk1, st), "event");
+    const bool bisect = std::isnan(mu);
+    if (bisect) {
+        HIPCHK(ctx, ma::launch_minmax(J.eps, J.stats, J.ncols, nu, kT, ctx->lohi.as<double>(), st), "minmax");
+        HIPCHK(ctx, ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, nu, kT, n_target,
+                                      ctx->lohi.as<double>(), ctx->partial.as<double>(), st), "bisection");
+    }
+    HIPCHK(ctx, ma::launch_rho(S, J, bisect ? ctx->lohi.as<double>() : nullptr, mu, kT, out->rho,
+                               out->pi, ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), st), "rho");
+    HIPCHK(ctx, ma::launch_sum2(ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), J.ncols,
+                                ctx->sums.as<double>(), st), "sums");
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
+    double sums[2] = {0, 0}, lohi[2] = {0, 0};
+    int ctl[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(sums, ctx->sums.p, sizeof sums, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipMemcpyAsync(ctl, ctx->ctl.p, sizeof ctl, hipMemcpyDeviceToHost, st), "copy");
+    if (bisect) HIPCHK(ctx, hipMemcpyAsync(lohi, ctx->lohi.p, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipStreamSynchronize(st), "solve");
+    float ms = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "elapsed");
+    out->elapsed_ms = ms;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evk0, ctx->evk1), "elapsed");
+    out->kernel_ms = ms;
+    out->energy = opts.spin * sums[0];
+    out->n_elec = opts.spin * sums[1];
+    out->mu = bisect ? 0.5 * (lohi[0] + lohi[1]) : mu;
+    if (ctl[1] != INT_MAX) {
+        const int c = ctl[1];
+        int32_t st4[4] = {0, 0, 0, 0};
+        HIPCHK(ctx, hipMemcpy(st4, J.stats + (int64_t)c * 4, sizeof st4, hipMemcpyDeviceToHost), "copy");
+        const ma_status s = st4[3] == -4 ? MA_ENOTPD : MA_ENOCONV;
+        return ctx->fail(s, "column %d (output row %d): %s after %d CG iterations", hcols[c], c,
+                         s == MA_ENOTPD ? "S_A not positive definite" : "CG did not converge",
+                         st4[1]);
+    }
+    return MA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the host side (ma_host.cpp) and the
+// kernels (ma_kernels.hip) of libmarnoldi.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ma {
+
+constexpr int kThreads = 256;            // workgroup size of the column kernel
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxNu = 64;
+constexpr int kBisectTrials = 63;        // trial potentials per bisection pass
+constexpr int kBisectPasses = 9;         // 64^9 narrows any bracket below 1e-15
+constexpr int kCountBlocks = 256;        // fixed grid of the electron-count kernel
+
+// Device view of a built system.
+struct DevSystem {
+    int o;                     // orbitals per atom
+    int n_atoms;
+    int nmax;                  // largest region dimension (orbitals)
+    int maxpat;                // largest pattern rows of a column (blocks * o)
+    const int64_t *blk_ptr;    // n_atoms + 1
+    const int32_t *blk_col;    // nblk
+    const double *Hd, *Sd;     // FP64 values, nblk * o * o
+    const float *Hf, *Sf;      // FP32 copies
+    // regions: atom A uses region rid = reg_id[A]; its atoms are
+    // reg_atoms[reg_off[rid] .. reg_off[rid] + reg_len[rid]) (ascending) and
+    // its local block rows are lrp[lrp_off[rid] .. + reg_len[rid] + 1)
+    // (absolute offsets into lblk, entries (local column atom, global block)).
+    const int32_t *reg_id;
+    const int64_t *reg_off;
+    const int32_t *reg_len;
+    const int64_t *lrp_off;
+    const int64_t *lrp;
+    const int2 *lblk;
+    const int32_t *jloc;       // local position of atom A inside its region
+    const int32_t *blk_loc;    // per global block: local position of its column atom
+                               // inside the region of its row atom
+};
+
+// One solve.
+struct DevJob {
+    int ncols;
+    const int32_t *cols;       // global column per output row c
+    const int32_t *order;      // processing order (LPT): order[idx] = c
+    int p, q, nu;
+    int precision;             // 0 FP64, 1 mixed
+    double cg_tol, inner_tol, tau;
+    int max_refine;
+    int *queue;                // work counter (reset before launch)
+    int *fail;                 // [0] = first failing c (INT_MAX none), [1] = its status
+    double *ws;                // workspace, slots * ws_stride doubles
+    int64_t ws_stride;
+    // per column outputs
+    double *eps;               // ncols * nu
+    double *wts;               // ncols * nu
+    double *amp;               // ncols * maxpat * nu: v_ia v_ja at pattern rows
+    int32_t *stats;            // ncols * 4
+    const float *x0;           // optional CG start vectors (ncols * nmax), local numbering
+};
+
+// Shared-memory bytes the column kernel needs.
+size_t solve_smem_bytes(int nmax, int nu);
+
+// Launchers (all asynchronous on `st`).
+hipError_t launch_reset(int *queue, int *fail, hipStream_t st);
+hipError_t launch_solve(const DevSystem &S, const DevJob &J, int slots, hipStream_t st);
+int solve_rows_per_thread(int nmax);
+hipError_t solve_occupancy(const DevSystem &S, const DevJob &J, int *blocks_per_cu);
+
+// Fermi weighting, chemical potential, reductions.
+hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int nu,
+                         double kT, double *lohi, hipStream_t st);
+hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *stats,
+                         int ncols, int nu, double kT, double n_target, double *lohi,
+                         double *partial, hipStream_t st);
+hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr, double mu,
+                      double kT, double *rho, double *pi, double *Ecol, double *Ncol,
+                      hipStream_t st);
+hipError_t launch_sum2(const double *a, const double *b, int n, double *out, hipStream_t st);
+
+}  // namespace ma

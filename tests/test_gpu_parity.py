@@ -1,0 +1,175 @@
+"""Parity of the HIP library (through its C interface) with the CPU oracle.
+
+FP64 mode: max-abs rho/pi <= 1e-10, relative band energy <= 1e-12 (both sides
+at CG tolerance 1e-12).  Mixed mode (FP32 SpMV/CG, FP64 Gram-Schmidt,
+projection and eigensolve): relative band energy <= 1e-6, max-abs rho <= 1e-5.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1202_0098_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_RHO_TOL = 1e-10
+FP64_E_TOL = 1e-12
+MIXED_RHO_TOL = 1e-5
+MIXED_E_TOL = 1e-6
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    import paper_1202_0098_amd as ma
+    c = ma.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_solve(ctx, torch, s, cols, p, q, mu, kT, **opt):
+    import paper_1202_0098_amd as ma
+    o = s.n_orb
+    ncols = s.M if cols is None else len(cols)
+    nu = p + q
+    rho = torch.zeros(s.nblk * o * o, dtype=torch.float64, device="cuda")
+    pi = torch.zeros_like(rho)
+    eps = torch.zeros(ncols * nu, dtype=torch.float64, device="cuda")
+    wts = torch.zeros_like(eps)
+    st = torch.zeros(ncols * 4, dtype=torch.int32, device="cuda")
+    res = ctx.solve_columns(cols, p, q, mu=mu, kT=kT, opts=ma.default_opts(**opt),
+                            rho=rho, pi=pi, eps=eps, wts=wts, col_stats=st)
+    torch.cuda.synchronize()
+    return (res, rho.cpu().numpy().reshape(s.nblk, o, o), pi.cpu().numpy().reshape(s.nblk, o, o),
+            eps.cpu().numpy().reshape(ncols, nu), wts.cpu().numpy().reshape(ncols, nu),
+            st.cpu().numpy().reshape(ncols, 4))
+
+
+def _compare(s, ora, cols, gpu, rho_tol, e_tol, mu_tol=1e-9):
+    import oracle
+    res, rho, pi, eps, wts, st = gpu
+    raw = ora["raw"]
+    assert np.array_equal(st[:, 0], raw["nu_eff"]), "nu_eff differs"
+    assert np.all(st[:, 3] == 0)
+    rho_o = oracle.scatter_slots(s, raw["cols"], ora["rho"])
+    pi_o = oracle.scatter_slots(s, raw["cols"], ora["pi"])
+    d_rho = np.abs(rho - rho_o).max()
+    d_pi = np.abs(pi - pi_o).max()
+    d_e = abs(res.energy - ora["energy"]) / abs(ora["energy"])
+    _say(f"max|drho|={d_rho:.3e} max|dpi|={d_pi:.3e} rel dE={d_e:.3e} "
+         f"mu gpu={res.mu:.15f} oracle={ora['mu']:.15f} cg_iters={int(st[:, 1].mean())}")
+    assert abs(res.mu - ora["mu"]) <= mu_tol * max(1.0, abs(ora["mu"]))
+    assert d_rho <= rho_tol
+    assert d_pi <= rho_tol * max(1.0, np.abs(pi_o).max())
+    assert d_e <= e_tol
+    return d_rho, d_e
+
+
+def test_fp64_diamond64_all_columns_bisected(ctx, torch_cuda):
+    import oracle
+    s = synth.config_diamond64()
+    _say("diamond64 fp64 build")
+    ctx.build_tb(s)
+    _say("diamond64 fp64 solve, 256 columns, mu bisected")
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT)
+    ora = oracle.solve(s)
+    _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL, mu_tol=1e-10)
+    # Ritz values and weights per column
+    eps, wts = gpu[3], gpu[4]
+    assert np.allclose(eps, ora["raw"]["eps"], atol=1e-10, rtol=0, equal_nan=True)
+    assert np.abs(wts - oracle.column_weights(ora["raw"])).max() < 1e-10
+
+
+@pytest.mark.parametrize("n_atoms,o,seed,p,q", [(3, 4, 1, 8, 4), (2, 9, 4, 12, 6),
+                                                (5, 1, 6, 3, 2), (6, 4, 3, 15, 9)])
+def test_fp64_random_pencils(ctx, torch_cuda, n_atoms, o, seed, p, q):
+    import oracle
+    s = synth.random_pencil(n_atoms, o, seed=seed)
+    _say(f"pencil n={s.M} o={o} p={p} q={q}")
+    ctx.build_tb(s)
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, p, q, 0.2, 0.25)
+    ora = oracle.solve(s, mu=0.2, kT=0.25, p=p, q=q)
+    _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
+
+
+def test_fp64_breakdown_identity_overlap(ctx, torch_cuda):
+    import oracle
+    s = synth.random_pencil(6, 4, seed=31, s_scale=0.0)
+    _say("pencil S=I breakdown")
+    ctx.build_tb(s)
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, 6, 4, 0.0, 0.3)
+    assert np.all(gpu[5][:, 0] == 6)
+    ora = oracle.solve(s, mu=0.0, kT=0.3, p=6, q=4)
+    _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
+
+
+def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda):
+    """Full-size 4,096-atom system, regions of 120 atoms (480 orbitals),
+    p = q = 15, a seeded sample of columns spanning every orbital type."""
+    import oracle
+    s = synth.config_diamond4096()
+    _say("diamond4096 build")
+    ctx.build_tb(s)
+    cols = np.sort(np.random.default_rng(7).choice(s.M, 192, replace=False)).astype(np.int32)
+    _say("diamond4096 fp64 solve 192 sampled columns")
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT)
+    ora = oracle.solve(s, cols=cols, mu=0.95)
+    _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
+
+
+def test_mixed_diamond64(ctx, torch_cuda):
+    import oracle
+    s = synth.config_diamond64()
+    ctx.build_tb(s)
+    _say("diamond64 mixed")
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, precision="mixed")
+    ora = oracle.solve(s)
+    _compare(s, ora, None, gpu, MIXED_RHO_TOL, MIXED_E_TOL, mu_tol=1e-5)
+
+
+def test_mixed_diamond4096_sampled(ctx, torch_cuda):
+    import oracle
+    s = synth.config_diamond4096()
+    ctx.build_tb(s)
+    cols = np.sort(np.random.default_rng(8).choice(s.M, 192, replace=False)).astype(np.int32)
+    _say("diamond4096 mixed 192 columns")
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT, precision="mixed")
+    ora = oracle.solve(s, cols=cols, mu=0.95)
+    _compare(s, ora, cols, gpu, MIXED_RHO_TOL, MIXED_E_TOL)
+
+
+def test_invalid_arguments_rejected(ctx, torch_cuda):
+    import paper_1202_0098_amd as ma
+    s = synth.config_diamond64()
+    ctx.build_tb(s)
+    for args in [dict(p=0, q=1), dict(p=40, q=30), dict(p=4, q=-1)]:
+        with pytest.raises(ma.MarnoldiError) as ei:
+            ctx.solve_columns(np.array([0], np.int32), args["p"], args["q"], mu=0.0, kT=0.1)
+        assert ei.value.status == ma.MA_EINVAL
+    with pytest.raises(ma.MarnoldiError):
+        ctx.solve_columns(np.array([s.M], np.int32), 4, 4, mu=0.0, kT=0.1)
+    with pytest.raises(ma.MarnoldiError):
+        ctx.solve_columns(np.array([0], np.int32), 4, 4, mu=0.0, kT=0.0)
+    bad = synth.config_diamond4096(nrp=3)
+    with pytest.raises(ma.MarnoldiError) as ei:
+        ctx.build_tb(bad)
+    assert ei.value.status == ma.MA_EINVAL
+    H = s.H.copy()
+    H[7, 0, 1] += 1.0
+    with pytest.raises(ma.MarnoldiError):
+        ctx.build_system(s.n_atoms, s.n_orb, s.blk_ptr, s.blk_col, H, s.S, s.pos, s.box)
