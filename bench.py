@@ -54,7 +54,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="diamond4096")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_f64acc"])
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="columns of the oracle CPU baseline sample (0 = skip)")
     args = ap.parse_args()
@@ -82,6 +83,14 @@ def main():
     pi = torch.zeros_like(rho)
     stats = torch.zeros(s.M * 4, dtype=torch.int32, device=dev)
     opts = ma.default_opts(precision=args.precision)
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        first = ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
+        tuning = ctx.autotune(None, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
+        log(f"autotune ({time.perf_counter() - t0:.1f}s): {tuning['slots_per_cu']} slots/CU, "
+            f"schedule {tuning['schedule']}, column kernel {tuning['best_ms']:.2f} ms; "
+            f"tried {[(a, b, round(c, 2)) for a, b, c in tuning['tried']]}")
 
     def step():
         return ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts,
@@ -154,7 +163,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": s.name, "atoms": s.n_atoms, "columns": s.M, "p": s.p, "q": s.q,
                    "kT": s.kT, "mu": "bisected at half filling", "precision": args.precision,
-                   "build_s": round(build_s, 3)},
+                   "build_s": round(build_s, 3), "hipgraph": True,
+                   "tuning": None if tuning is None else {
+                       "slots_per_cu": tuning["slots_per_cu"], "schedule": tuning["schedule"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -34,8 +34,11 @@
  *     multiplied by opts.spin.
  *   - All functions return an ma_status; no exception crosses the interface.
  *     On error, ma_last_error() describes it.
- *   - Every device operation is enqueued on the stream given to ma_create; the
- *     functions return after synchronising that stream.
+ *   - Device work is enqueued on the stream given to ma_create.  If that is
+ *     the null stream (which cannot be captured into a hipGraph), the solve
+ *     runs on a stream of the library's own, ordered after the work already
+ *     queued on the null stream.  Every function returns after its device
+ *     work has completed.
  *   - One context per host thread; contexts are independent.
  */
 #ifndef MARNOLDI_H
@@ -66,7 +69,7 @@ typedef enum {
 } ma_status;
 
 enum { MA_REGION_ALL = 0, MA_REGION_RADIUS = 1, MA_REGION_NEAREST = 2 };
-enum { MA_PREC_FP64 = 0, MA_PREC_MIXED = 1 };
+enum { MA_PREC_FP64 = 0, MA_PREC_MIXED = 1, MA_PREC_MIXED_F64ACC = 2 };
 enum { MA_START_ZERO = 0, MA_START_LEARNED = 1 };
 
 /* The pencil and its geometry.  All pointers are host memory owned by the
@@ -98,7 +101,9 @@ typedef struct {
     int32_t precision;      /* MA_PREC_FP64: everything FP64.  MA_PREC_MIXED:
                                FP32 SpMV and CG with FP32 accumulation, FP64
                                residual judge and refinement, FP64 Gram-Schmidt,
-                               projection and eigensolve. */
+                               projection and eigensolve.  MA_PREC_MIXED_F64ACC:
+                               as MIXED, but the basis SpMVs read FP32 operator
+                               values into FP64 vectors and accumulators. */
     double cg_tol;          /* stop when ||e_j - S_A s_j||_2 <= cg_tol (default 1e-12) */
     double inner_tol;       /* mixed: relative residual of each FP32 CG pass (default 1e-6) */
     int32_t max_refine;     /* mixed: FP64 refinement rounds (default 8) */
@@ -108,8 +113,22 @@ typedef struct {
     double n_target;        /* per-spin electron count sum_j N_j for the bisection
                                (used when mu is NaN; default: half of M) */
     int32_t start;          /* MA_START_ZERO, or MA_START_LEARNED (needs a model) */
-    int32_t slots_per_cu;   /* persistent workgroups per compute unit (0 = auto) */
+    int32_t slots_per_cu;   /* persistent workgroups per compute unit (0 = the
+                               autotuned value for this (p, q, precision) if
+                               ma_autotune ran, else the occupancy limit) */
+    int32_t schedule;       /* column-to-workgroup schedule, MA_SCHED_*; -1 = autotuned
+                               value if available, else MA_SCHED_LPT */
+    int32_t use_graph;      /* 1: capture the launch sequence in a hipGraph and replay it
+                               while the configuration and buffers are unchanged */
 } ma_opts;
+
+/* Schedules of the persistent column kernel.  LPT: one queue, columns with
+ * the largest region first.  INPUT: one queue in the caller's order.
+ * XCD_INPUT / XCD_LPT: the (caller-ordered or LPT-ordered) list cut into one
+ * contiguous chunk per XCD; workgroup b serves chunk b % 8 first (workgroups
+ * are dispatched to the 8 XCDs round-robin), then steals from the others, so
+ * spatially adjacent columns share an XCD's L2. */
+enum { MA_SCHED_LPT = 0, MA_SCHED_INPUT = 1, MA_SCHED_XCD_INPUT = 2, MA_SCHED_XCD_LPT = 3 };
 
 /* Outputs of ma_solve_columns.  Device pointers are optional (NULL = not
  * written) and owned by the caller. */
@@ -128,6 +147,17 @@ typedef struct {
     double kernel_ms;       /* device time of the column kernel alone (HIP events
                                around its launch on the same stream) */
 } ma_result;
+
+/* Result of ma_autotune. */
+typedef struct {
+    int32_t slots_per_cu;       /* chosen */
+    int32_t schedule;           /* chosen */
+    double best_ms;             /* column-kernel time of the chosen configuration */
+    int32_t n_tried;
+    int32_t tried_slots[64];
+    int32_t tried_schedule[64];
+    double tried_ms[64];        /* column-kernel time of each candidate (best of reps) */
+} ma_tuning;
 
 /* Library version string. */
 MA_API const char *ma_version(void);
@@ -182,6 +212,20 @@ MA_API int64_t ma_region_atoms(const ma_system *sys, const ma_region *reg, int32
 MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *cols,
                                   int32_t p, int32_t q, double mu, double kT,
                                   const ma_opts *opts, ma_result *out);
+
+/* Autotuner: time the column kernel on cols[0..ncols) (NULL = all) for every
+ * candidate (slots per CU from 1 to the occupancy limit, x every schedule),
+ * `reps` times each at chemical potential mu (finite), and keep the fastest
+ * configuration for this (p, q, opts->precision) in the context; solves with
+ * slots_per_cu = 0 and schedule = -1 then use it.  Outputs (rho, pi) are not
+ * written. */
+MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
+                             int32_t q, double mu, double kT, const ma_opts *opts, int32_t reps,
+                             ma_tuning *out);
+
+/* Store a previously found tuning for (p, q, precision) (e.g. from a cache). */
+MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
+                               int32_t slots_per_cu, int32_t schedule);
 
 #ifdef __cplusplus
 }

@@ -22,12 +22,12 @@ LIB_PATH = os.path.join(_HERE, "libmarnoldi.so")
 
 MA_OK, MA_EINVAL, MA_ENOMEM, MA_EDEVICE, MA_ENOTPD, MA_ENOCONV, MA_ESTATE = 0, -1, -2, -3, -4, -5, -6
 REGION_MODES = {"all": 0, "radius": 1, "nearest": 2}
-PREC = {"fp64": 0, "mixed": 1}
+PREC = {"fp64": 0, "mixed": 1, "mixed_f64acc": 2}
 
 # the functions include/marnoldi.h declares
 API_FUNCTIONS = ("ma_version", "ma_default_opts", "ma_create", "ma_destroy", "ma_last_error",
                  "ma_build_system", "ma_system_info", "ma_region_sizes", "ma_region_atoms",
-                 "ma_solve_columns")
+                 "ma_solve_columns", "ma_autotune", "ma_set_tuning")
 
 
 class MarnoldiError(RuntimeError):
@@ -53,7 +53,18 @@ class _Opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("breakdown_tau", ctypes.c_double), ("spin", ctypes.c_double),
                 ("n_target", ctypes.c_double), ("start", ctypes.c_int32),
-                ("slots_per_cu", ctypes.c_int32)]
+                ("slots_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("slots_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("n_tried", ctypes.c_int32),
+                ("tried_slots", ctypes.c_int32 * 64), ("tried_schedule", ctypes.c_int32 * 64),
+                ("tried_ms", ctypes.c_double * 64)]
+
+
+SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
 
 
 class _Result(ctypes.Structure):
@@ -95,8 +106,11 @@ def load_library():
     lib.ma_region_sizes.restype = ctypes.c_int
     lib.ma_region_atoms.argtypes = [ctypes.POINTER(_System), ctypes.POINTER(_Region), i32, P, i64]
     lib.ma_region_atoms.restype = ctypes.c_int64
+    lib.ma_autotune.argtypes = [P, i64, P, i32, i32, f64, f64, ctypes.POINTER(_Opts), i32,
+                                ctypes.POINTER(_Tuning)]
+    lib.ma_set_tuning.argtypes = [P, i32, i32, i32, i32, i32]
     for name in ("ma_create", "ma_destroy", "ma_build_system", "ma_system_info",
-                 "ma_solve_columns"):
+                 "ma_solve_columns", "ma_autotune", "ma_set_tuning"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -112,6 +126,8 @@ def default_opts(**kw) -> _Opts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = PREC[v]
+        if k == "schedule" and isinstance(v, str):
+            v = SCHEDULES[v]
         setattr(o, k, v)
     return o
 
@@ -221,6 +237,28 @@ class Context:
         lb = np.zeros(n_atoms, np.int64)
         self._check(self._lib.ma_region_sizes(self._h, _ptr(ra), _ptr(lb)))
         return ra, lb
+
+    def autotune(self, cols, p, q, mu, kT, opts=None, reps=2):
+        """Search slots per CU x schedule on the column kernel; the best
+        configuration is kept for (p, q, precision).  Returns a dict."""
+        if cols is None:
+            cptr, n = None, 0
+        else:
+            cols = np.ascontiguousarray(cols, np.int32)
+            cptr, n = _ptr(cols), len(cols)
+        o = opts if opts is not None else default_opts()
+        t = _Tuning()
+        self._check(self._lib.ma_autotune(self._h, n, cptr, int(p), int(q), float(mu), float(kT),
+                                          ctypes.byref(o), int(reps), ctypes.byref(t)))
+        names = {v: k for k, v in SCHEDULES.items()}
+        return dict(slots_per_cu=t.slots_per_cu, schedule=names[t.schedule], best_ms=t.best_ms,
+                    tried=[(t.tried_slots[i], names[t.tried_schedule[i]], t.tried_ms[i])
+                           for i in range(t.n_tried)])
+
+    def set_tuning(self, p, q, precision, slots_per_cu, schedule):
+        prec = PREC[precision] if isinstance(precision, str) else int(precision)
+        sch = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        self._check(self._lib.ma_set_tuning(self._h, int(p), int(q), prec, int(slots_per_cu), sch))
 
     def solve_columns(self, cols, p, q, mu=math.nan, kT=0.1, opts=None, rho=None, pi=None,
                       eps=None, wts=None, col_stats=None) -> SolveResult:

@@ -81,7 +81,11 @@ void parallel_for(int64_t n, F &&f)
 
 struct ma_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // the caller's stream
+    hipStream_t own = nullptr;        // used instead when the caller's is the null stream
+    hipEvent_t evu = nullptr;         // orders `own` after the caller's null stream
+    // the stream the solve path enqueues on (the null stream cannot be captured)
+    hipStream_t work_stream() const { return stream ? stream : own; }
     std::string err = "no error";
     int cu_count = 0;
     bool built = false;
@@ -98,8 +102,31 @@ struct ma_ctx {
         blk_loc;
 
     // device solve buffers
-    DevBuf cols, order, ws, eps, wts, amp, stats, ctl, lohi, partial, Ecol, Ncol, sums;
+    DevBuf cols, order, qbounds, ws, eps, wts, amp, stats, ctl, lohi, partial, Ecol, Ncol, sums;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
+    uint64_t generation = 0;          // bumped by every ma_build_system
+
+    // captured launch sequence and the configuration it was captured for
+    hipGraphExec_t gexec = nullptr;   // the column kernel
+    hipGraphExec_t gexec2 = nullptr;  // bisection, Fermi weighting, reductions
+    std::vector<unsigned char> gkey;
+
+    // autotuned (slots per CU, schedule) per (p, q, precision)
+    struct Tune { int p, q, prec, slots, sched; };
+    std::vector<Tune> tunes;
+    const Tune *find_tune(int p, int q, int prec) const
+    {
+        for (const auto &t : tunes)
+            if (t.p == p && t.q == q && t.prec == prec) return &t;
+        return nullptr;
+    }
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (gexec2) (void)hipGraphExecDestroy(gexec2);
+        gexec = gexec2 = nullptr;
+        gkey.clear();
+    }
 
     ma_status fail(ma_status s, const char *fmt, ...)
     {
@@ -365,6 +392,8 @@ MA_API void ma_default_opts(ma_opts *o)
     o->n_target = NAN;
     o->start = MA_START_ZERO;
     o->slots_per_cu = 0;
+    o->schedule = -1;
+    o->use_graph = 1;
 }
 
 MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
@@ -381,7 +410,9 @@ MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
         hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) !=
             hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        hipEventCreate(&c->evk0) != hipSuccess || hipEventCreate(&c->evk1) != hipSuccess) {
+        hipEventCreate(&c->evk0) != hipSuccess || hipEventCreate(&c->evk1) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evu, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return MA_EDEVICE;
     }
@@ -397,6 +428,9 @@ MA_API ma_status ma_destroy(ma_ctx *ctx)
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->evk0) (void)hipEventDestroy(ctx->evk0);
     if (ctx->evk1) (void)hipEventDestroy(ctx->evk1);
+    ctx->drop_graph();
+    if (ctx->evu) (void)hipEventDestroy(ctx->evu);
+    if (ctx->own) (void)hipStreamDestroy(ctx->own);
     delete ctx;
     return MA_OK;
 }
@@ -420,6 +454,8 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     if (!ctx) return MA_EINVAL;
     if (!sys || !reg) return ctx->fail(MA_EINVAL, "null system or region");
     ctx->built = false;
+    ctx->drop_graph();
+    ctx->generation++;
     const int n = sys->n_atoms, o = sys->n_orb;
     if (n < 1) return ctx->fail(MA_EINVAL, "n_atoms must be >= 1");
     if (o < 1 || o > MA_MAX_ORB) return ctx->fail(MA_EINVAL, "n_orb must be in 1..%d", MA_MAX_ORB);
@@ -645,131 +681,340 @@ MA_API int64_t ma_region_atoms(const ma_system *sys, const ma_region *reg, int32
     return (int64_t)L.size();
 }
 
-MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
-                                  int32_t q, double mu, double kT, const ma_opts *opts_in,
-                                  ma_result *out)
-{
-    if (!ctx) return MA_EINVAL;
-    if (!ctx->built) return ctx->fail(MA_ESTATE, "ma_build_system has not succeeded");
-    if (!out) return ctx->fail(MA_EINVAL, "null result");
+}  // extern "C"
+
+namespace {
+
+// Everything one launch sequence needs, resolved from the arguments.
+struct Plan {
     ma_opts opts;
-    ma_default_opts(&opts);
-    if (opts_in) opts = *opts_in;
+    int p = 0, q = 0, nu = 0, slots = 0, sched = 0;
+    double mu = 0, kT = 0, n_target = 0;
+    bool bisect = false;
+    std::vector<int32_t> hcols;
+    ma::DevSystem S;
+    ma::DevJob J;
+    double *rho = nullptr, *pi = nullptr;
+};
+
+ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, int32_t q,
+                    double mu, double kT, const ma_opts *opts_in, double *rho, double *pi,
+                    double *eps, double *wts, int32_t *col_stats, int slots_override,
+                    int sched_override, Plan &P)
+{
+    if (!ctx->built) return ctx->fail(MA_ESTATE, "ma_build_system has not succeeded");
+    ma_default_opts(&P.opts);
+    if (opts_in) P.opts = *opts_in;
+    const ma_opts &opts = P.opts;
     if (p < 1 || q < 0 || p + q > MA_MAX_NU)
         return ctx->fail(MA_EINVAL, "need p >= 1, q >= 0, p + q <= %d", MA_MAX_NU);
     if (!(kT > 0) || !std::isfinite(kT)) return ctx->fail(MA_EINVAL, "kT must be positive");
     if (std::isinf(mu)) return ctx->fail(MA_EINVAL, "mu must be finite or NaN");
-    if (opts.precision != MA_PREC_FP64 && opts.precision != MA_PREC_MIXED)
+    if (opts.precision != MA_PREC_FP64 && opts.precision != MA_PREC_MIXED &&
+        opts.precision != MA_PREC_MIXED_F64ACC)
         return ctx->fail(MA_EINVAL, "unknown precision %d", opts.precision);
     if (!(opts.cg_tol > 0) || !(opts.breakdown_tau >= 0) || !(opts.inner_tol > 0) || opts.max_refine < 0)
         return ctx->fail(MA_EINVAL, "invalid tolerances");
-    if (opts.start == MA_START_LEARNED)
-        return ctx->fail(MA_EINVAL, "no start model is set");
+    if (opts.start == MA_START_LEARNED) return ctx->fail(MA_EINVAL, "no start model is set");
+    if (opts.schedule < -1 || opts.schedule > MA_SCHED_XCD_LPT)
+        return ctx->fail(MA_EINVAL, "unknown schedule %d", opts.schedule);
     if (cols == nullptr) ncols = ctx->M;
     if (ncols < 1 || ncols > INT_MAX) return ctx->fail(MA_EINVAL, "ncols out of range");
-    std::vector<int32_t> hcols(ncols);
+    P.hcols.resize(ncols);
     for (int64_t c = 0; c < ncols; ++c) {
-        hcols[c] = cols ? cols[c] : (int32_t)c;
-        if (hcols[c] < 0 || hcols[c] >= ctx->M)
-            return ctx->fail(MA_EINVAL, "column %lld out of range", (long long)hcols[c]);
+        P.hcols[c] = cols ? cols[c] : (int32_t)c;
+        if (P.hcols[c] < 0 || P.hcols[c] >= ctx->M)
+            return ctx->fail(MA_EINVAL, "column %lld out of range", (long long)P.hcols[c]);
     }
-    const double n_target = std::isnan(opts.n_target) ? 0.5 * (double)ncols : opts.n_target;
-    // largest region first (longest-processing-time order), stable
-    std::vector<int32_t> order(ncols);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return ctx->reg_len_of_atom[hcols[a] / ctx->o] > ctx->reg_len_of_atom[hcols[b] / ctx->o];
-    });
-    const int nu = p + q;
-    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    P.p = p;
+    P.q = q;
+    P.nu = p + q;
+    P.mu = mu;
+    P.kT = kT;
+    P.bisect = std::isnan(mu);
+    P.n_target = std::isnan(opts.n_target) ? 0.5 * (double)ncols : opts.n_target;
+    P.rho = rho;
+    P.pi = pi;
 
-    ma::DevSystem S = ctx->dev_system();
-    ma::DevJob J{};
+    // launch configuration: explicit, autotuned, or defaults
+    const ma_ctx::Tune *tn = ctx->find_tune(p, q, opts.precision);
+    P.sched = sched_override >= 0 ? sched_override
+              : opts.schedule >= 0 ? opts.schedule : (tn ? tn->sched : MA_SCHED_LPT);
+
+    ma::DevSystem &S = P.S;
+    ma::DevJob &J = P.J;
+    S = ctx->dev_system();
+    std::memset(&J, 0, sizeof J);   // the launch key compares the raw bytes
     J.ncols = (int)ncols;
     J.p = p;
     J.q = q;
-    J.nu = nu;
+    J.nu = P.nu;
     J.precision = opts.precision;
     J.cg_tol = opts.cg_tol;
     J.inner_tol = opts.inner_tol;
     J.tau = opts.breakdown_tau;
     J.max_refine = opts.max_refine;
-    J.ws_stride = (int64_t)(3 * nu + q) * ctx->nmax;
-
+    J.ws_stride = (int64_t)(3 * P.nu + q) * ctx->nmax;
     int bpc = 0;
-    HIPCHK(ctx, ma::solve_occupancy(S, J, &bpc), "occupancy");
-    if (bpc < 1) return ctx->fail(MA_EINVAL, "column kernel does not fit on a compute unit (nu=%d, nmax=%d)", nu, ctx->nmax);
-    if (opts.slots_per_cu > 0) bpc = std::min(bpc, opts.slots_per_cu);
-    int slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, ncols);
+    hipError_t e = ma::solve_occupancy(S, J, &bpc);
+    if (e != hipSuccess) return ctx->hip_fail(e, "occupancy");
+    if (bpc < 1)
+        return ctx->fail(MA_EINVAL, "column kernel does not fit on a compute unit (nu=%d, nmax=%d)",
+                         P.nu, ctx->nmax);
+    int want = slots_override > 0 ? slots_override
+               : opts.slots_per_cu > 0 ? opts.slots_per_cu : (tn ? tn->slots : bpc);
+    bpc = std::min(bpc, std::max(1, want));
+    P.slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, ncols);
+
+    // processing order and queue bounds
+    std::vector<int32_t> order(ncols);
+    std::iota(order.begin(), order.end(), 0);
+    auto lpt = [&](std::vector<int32_t>::iterator b, std::vector<int32_t>::iterator e2) {
+        std::stable_sort(b, e2, [&](int32_t x, int32_t y) {
+            return ctx->reg_len_of_atom[P.hcols[x] / ctx->o] > ctx->reg_len_of_atom[P.hcols[y] / ctx->o];
+        });
+    };
+    const bool xcd = P.sched == MA_SCHED_XCD_INPUT || P.sched == MA_SCHED_XCD_LPT;
+    J.nqueues = xcd ? ma::kMaxQueues : 1;
+    std::vector<int32_t> qb(J.nqueues + 1);
+    for (int k = 0; k <= J.nqueues; ++k) qb[k] = (int32_t)((int64_t)ncols * k / J.nqueues);
+    if (P.sched == MA_SCHED_LPT) lpt(order.begin(), order.end());
+    if (P.sched == MA_SCHED_XCD_LPT)
+        for (int k = 0; k < J.nqueues; ++k) lpt(order.begin() + qb[k], order.begin() + qb[k + 1]);
 
     HIPCHK(ctx, ctx->cols.reserve(sizeof(int32_t) * ncols), "cols");
     HIPCHK(ctx, ctx->order.reserve(sizeof(int32_t) * ncols), "order");
-    HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * slots), "workspace");
-    HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * nu), "eps");
-    HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * nu), "wts");
-    HIPCHK(ctx, ctx->amp.reserve(sizeof(double) * (size_t)ncols * ctx->maxpat * nu), "amplitudes");
+    HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * (ma::kMaxQueues + 1)), "queues");
+    HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
+    HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
+    HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
+    HIPCHK(ctx, ctx->amp.reserve(sizeof(double) * (size_t)ncols * ctx->maxpat * P.nu), "amplitudes");
     HIPCHK(ctx, ctx->stats.reserve(sizeof(int32_t) * (size_t)ncols * 4), "stats");
-    HIPCHK(ctx, ctx->ctl.reserve(sizeof(int) * 4), "ctl");
+    HIPCHK(ctx, ctx->ctl.reserve(sizeof(int) * 16), "ctl");
     HIPCHK(ctx, ctx->lohi.reserve(sizeof(double) * 2), "lohi");
     HIPCHK(ctx, ctx->partial.reserve(sizeof(double) * ma::kCountBlocks * ma::kBisectTrials), "partial");
     HIPCHK(ctx, ctx->Ecol.reserve(sizeof(double) * ncols), "Ecol");
     HIPCHK(ctx, ctx->Ncol.reserve(sizeof(double) * ncols), "Ncol");
     HIPCHK(ctx, ctx->sums.reserve(sizeof(double) * 2), "sums");
-    hipStream_t st = ctx->stream;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
+    hipStream_t st = ctx->work_stream();
+    if (!ctx->stream) {
+        HIPCHK(ctx, hipEventRecord(ctx->evu, nullptr), "event");
+        HIPCHK(ctx, hipStreamWaitEvent(st, ctx->evu, 0), "stream wait");
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, P.hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
     HIPCHK(ctx, hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "order");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->qbounds.p, qb.data(), sizeof(int32_t) * qb.size(), hipMemcpyHostToDevice, st), "queues");
+    // the copies read pageable host vectors: finish them before those go away
+    HIPCHK(ctx, hipStreamSynchronize(st), "upload");
 
     J.cols = ctx->cols.as<int32_t>();
     J.order = ctx->order.as<int32_t>();
+    J.qbounds = ctx->qbounds.as<int32_t>();
     J.queue = ctx->ctl.as<int>();
-    J.fail = ctx->ctl.as<int>() + 1;
+    J.fail = ctx->ctl.as<int>() + ma::kMaxQueues;
     J.ws = ctx->ws.as<double>();
-    J.eps = out->eps ? out->eps : ctx->eps.as<double>();
-    J.wts = out->wts ? out->wts : ctx->wts.as<double>();
+    J.eps = eps ? eps : ctx->eps.as<double>();
+    J.wts = wts ? wts : ctx->wts.as<double>();
     J.amp = ctx->amp.as<double>();
-    J.stats = out->col_stats ? out->col_stats : ctx->stats.as<int32_t>();
+    J.stats = col_stats ? col_stats : ctx->stats.as<int32_t>();
     J.x0 = nullptr;
+    return MA_OK;
+}
 
-    HIPCHK(ctx, hipEventRecord(ctx->ev0, st), "event");
-    HIPCHK(ctx, ma::launch_reset(J.queue, J.fail, st), "reset");
-    HIPCHK(ctx, hipEventRecord(ctx->evk0, st), "event");
-    HIPCHK(ctx, ma::launch_solve(S, J, slots, st), "column kernel");
-    HIPCHK(ctx, hipEventRecord(ctx->evk1, st), "event");
-    const bool bisect = std::isnan(mu);
-    if (bisect) {
-        HIPCHK(ctx, ma::launch_minmax(J.eps, J.stats, J.ncols, nu, kT, ctx->lohi.as<double>(), st), "minmax");
-        HIPCHK(ctx, ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, nu, kT, n_target,
-                                      ctx->lohi.as<double>(), ctx->partial.as<double>(), st), "bisection");
+// The launch sequence of one solve, in two parts (each captured into a graph
+// or launched directly): the column kernel, then the chemical potential,
+// Fermi weighting and reductions.  The work counters are reset outside.
+hipError_t enqueue_solve(ma_ctx *ctx, const Plan &P)
+{
+    return ma::launch_solve(P.S, P.J, P.slots, ctx->work_stream());
+}
+
+hipError_t enqueue_post(ma_ctx *ctx, const Plan &P)
+{
+    hipStream_t st = ctx->work_stream();
+    const ma::DevSystem &S = P.S;
+    const ma::DevJob &J = P.J;
+    hipError_t e;
+    if (P.bisect) {
+        if ((e = ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, P.kT, ctx->lohi.as<double>(), st)) != hipSuccess) return e;
+        if ((e = ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, J.nu, P.kT, P.n_target,
+                                   ctx->lohi.as<double>(), ctx->partial.as<double>(), st)) != hipSuccess) return e;
     }
-    HIPCHK(ctx, ma::launch_rho(S, J, bisect ? ctx->lohi.as<double>() : nullptr, mu, kT, out->rho,
-                               out->pi, ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), st), "rho");
-    HIPCHK(ctx, ma::launch_sum2(ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), J.ncols,
-                                ctx->sums.as<double>(), st), "sums");
+    if ((e = ma::launch_rho(S, J, P.bisect ? ctx->lohi.as<double>() : nullptr, P.mu, P.kT, P.rho,
+                            P.pi, ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), st)) != hipSuccess) return e;
+    return ma::launch_sum2(ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), J.ncols,
+                           ctx->sums.as<double>(), st);
+}
+
+hipError_t capture(ma_ctx *ctx, const Plan &P, hipError_t (*fn)(ma_ctx *, const Plan &),
+                   hipGraphExec_t *exec)
+{
+    hipStream_t st = ctx->work_stream();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    e = fn(ctx, P);
+    hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+template <typename T>
+void key_add(std::vector<unsigned char> &k, const T &v)
+{
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&v);
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+std::vector<unsigned char> graph_key(const ma_ctx *ctx, const Plan &P)
+{
+    std::vector<unsigned char> k;
+    key_add(k, ctx->generation);
+    key_add(k, P.J);          // sizes, tolerances and every device pointer
+    key_add(k, P.slots);
+    key_add(k, P.bisect);
+    key_add(k, P.mu);
+    key_add(k, P.kT);
+    key_add(k, P.n_target);
+    key_add(k, P.rho);
+    key_add(k, P.pi);
+    return k;
+}
+
+// Run the plan; fills the result scalars.  kernel_ms is the column kernel's
+// time from HIP events recorded around its launch on the stream.
+ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
+{
+    hipStream_t st = ctx->work_stream();
+    if (P.opts.use_graph) {
+        std::vector<unsigned char> key = graph_key(ctx, P);
+        if (!ctx->gexec || key != ctx->gkey) {
+            ctx->drop_graph();
+            hipError_t e = capture(ctx, P, enqueue_solve, &ctx->gexec);
+            if (e == hipSuccess) e = capture(ctx, P, enqueue_post, &ctx->gexec2);
+            if (e != hipSuccess) {
+                ctx->drop_graph();
+                return ctx->hip_fail(e, "graph capture");
+            }
+            ctx->gkey = key;
+        }
+    }
+    // ev0 .. ev1 brackets the whole solve, evk0 .. evk1 the column kernel
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, st), "event");
+    HIPCHK(ctx, ma::launch_reset(P.J.queue, P.J.fail, st), "reset");
+    HIPCHK(ctx, hipEventRecord(ctx->evk0, st), "event");
+    if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, st), "graph launch");
+    else HIPCHK(ctx, enqueue_solve(ctx, P), "column kernel");
+    HIPCHK(ctx, hipEventRecord(ctx->evk1, st), "event");
+    if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec2, st), "graph launch");
+    else HIPCHK(ctx, enqueue_post(ctx, P), "launch");
     HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
     double sums[2] = {0, 0}, lohi[2] = {0, 0};
-    int ctl[2] = {0, 0};
+    int ctl[ma::kMaxQueues + 1];
     HIPCHK(ctx, hipMemcpyAsync(sums, ctx->sums.p, sizeof sums, hipMemcpyDeviceToHost, st), "copy");
     HIPCHK(ctx, hipMemcpyAsync(ctl, ctx->ctl.p, sizeof ctl, hipMemcpyDeviceToHost, st), "copy");
-    if (bisect) HIPCHK(ctx, hipMemcpyAsync(lohi, ctx->lohi.p, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
+    if (P.bisect) HIPCHK(ctx, hipMemcpyAsync(lohi, ctx->lohi.p, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
     HIPCHK(ctx, hipStreamSynchronize(st), "solve");
     float ms = 0.0f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "elapsed");
     out->elapsed_ms = ms;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evk0, ctx->evk1), "elapsed");
     out->kernel_ms = ms;
-    out->energy = opts.spin * sums[0];
-    out->n_elec = opts.spin * sums[1];
-    out->mu = bisect ? 0.5 * (lohi[0] + lohi[1]) : mu;
-    if (ctl[1] != INT_MAX) {
-        const int c = ctl[1];
+    out->energy = P.opts.spin * sums[0];
+    out->n_elec = P.opts.spin * sums[1];
+    out->mu = P.bisect ? 0.5 * (lohi[0] + lohi[1]) : P.mu;
+    const int failc = ctl[ma::kMaxQueues];
+    if (failc != INT_MAX) {
         int32_t st4[4] = {0, 0, 0, 0};
-        HIPCHK(ctx, hipMemcpy(st4, J.stats + (int64_t)c * 4, sizeof st4, hipMemcpyDeviceToHost), "copy");
+        HIPCHK(ctx, hipMemcpy(st4, P.J.stats + (int64_t)failc * 4, sizeof st4, hipMemcpyDeviceToHost), "copy");
         const ma_status s = st4[3] == -4 ? MA_ENOTPD : MA_ENOCONV;
-        return ctx->fail(s, "column %d (output row %d): %s after %d CG iterations", hcols[c], c,
-                         s == MA_ENOTPD ? "S_A not positive definite" : "CG did not converge",
+        return ctx->fail(s, "column %d (output row %d): %s after %d CG iterations", P.hcols[failc],
+                         failc, s == MA_ENOTPD ? "S_A not positive definite" : "CG did not converge",
                          st4[1]);
     }
     return MA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
+                                  int32_t q, double mu, double kT, const ma_opts *opts_in,
+                                  ma_result *out)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!out) return ctx->fail(MA_EINVAL, "null result");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    Plan P;
+    ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, opts_in, out->rho, out->pi, out->eps,
+                            out->wts, out->col_stats, 0, -1, P);
+    if (s != MA_OK) return s;
+    return run_plan(ctx, P, out);
+}
+
+MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
+                               int32_t slots_per_cu, int32_t schedule)
+{
+    if (!ctx) return MA_EINVAL;
+    if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT)
+        return ctx->fail(MA_EINVAL, "invalid tuning");
+    for (auto &t : ctx->tunes)
+        if (t.p == p && t.q == q && t.prec == precision) {
+            t.slots = slots_per_cu;
+            t.sched = schedule;
+            return MA_OK;
+        }
+    ctx->tunes.push_back({p, q, precision, slots_per_cu, schedule});
+    return MA_OK;
+}
+
+MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, int32_t q,
+                             double mu, double kT, const ma_opts *opts_in, int32_t reps,
+                             ma_tuning *out)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!out || reps < 1) return ctx->fail(MA_EINVAL, "null result or reps < 1");
+    if (!std::isfinite(mu)) return ctx->fail(MA_EINVAL, "autotuning needs a finite mu");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ma_opts o;
+    ma_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    o.use_graph = 0;
+    // occupancy limit of this shape
+    Plan P0;
+    ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, 1 << 20, MA_SCHED_LPT, P0);
+    if (s != MA_OK) return s;
+    const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
+    std::memset(out, 0, sizeof(*out));
+    out->best_ms = INFINITY;
+    for (int sched = 0; sched <= MA_SCHED_XCD_LPT; ++sched)
+        for (int bpc = 1; bpc <= max_bpc && out->n_tried < 64; ++bpc) {
+            Plan P;
+            s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, bpc, sched, P);
+            if (s != MA_OK) return s;
+            double best = INFINITY;
+            for (int r = 0; r < reps; ++r) {
+                ma_result res{};
+                s = run_plan(ctx, P, &res);
+                if (s != MA_OK) return s;
+                best = std::min(best, res.kernel_ms);
+            }
+            const int t = out->n_tried++;
+            out->tried_slots[t] = bpc;
+            out->tried_schedule[t] = sched;
+            out->tried_ms[t] = best;
+            if (best < out->best_ms) {
+                out->best_ms = best;
+                out->slots_per_cu = bpc;
+                out->schedule = sched;
+            }
+        }
+    return ma_set_tuning(ctx, p, q, o.precision, out->slots_per_cu, out->schedule);
 }
 
 }  // extern "C"

@@ -48,8 +48,10 @@ struct DevJob {
     int precision;             // 0 FP64, 1 mixed
     double cg_tol, inner_tol, tau;
     int max_refine;
-    int *queue;                // work counter (reset before launch)
-    int *fail;                 // [0] = first failing c (INT_MAX none), [1] = its status
+    int *queue;                // work counters, one per queue (reset before launch)
+    int nqueues;               // 1, or 8 (one per XCD)
+    const int32_t *qbounds;    // nqueues + 1 offsets into order
+    int *fail;                 // [0] = first failing c (INT_MAX none)
     double *ws;                // workspace, slots * ws_stride doubles
     int64_t ws_stride;
     // per column outputs
@@ -64,6 +66,7 @@ struct DevJob {
 size_t solve_smem_bytes(int nmax, int nu);
 
 // Launchers (all asynchronous on `st`).
+constexpr int kMaxQueues = 8;
 hipError_t launch_reset(int *queue, int *fail, hipStream_t st);
 hipError_t launch_solve(const DevSystem &S, const DevJob &J, int slots, hipStream_t st);
 int solve_rows_per_thread(int nmax);

@@ -70,6 +70,17 @@ __device__ __forceinline__ T block_sum(T v, T *red)
     return s;
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Order the LDS traffic of one wavefront (its lanes execute together; LDS
+// operations of a wavefront complete in issue order).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double fermi(double x)
 {
     if (x <= 0.0) return 1.0 / (1.0 + exp(x));
@@ -89,17 +100,18 @@ struct Col {
 };
 
 // SpMV on the thread's own rows: hy = H x, sy = S x (x in LDS), zy = H xb.
-template <int O, int R, typename TM, bool DO_H, bool DO_S, bool DO_Z>
+// TM: stored operator values; TX: vector entries and accumulation.
+template <int O, int R, typename TM, typename TX, bool DO_H, bool DO_S, bool DO_Z>
 __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int o_rt,
                                           const TM *__restrict__ Hv, const TM *__restrict__ Sv,
-                                          const TM *xa, const TM *xb, double (&hy)[R],
+                                          const TX *xa, const TX *xb, double (&hy)[R],
                                           double (&sy)[R], double (&zy)[R])
 {
     const int o = O ? O : o_rt;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
         const int i = threadIdx.x + rr * NT;
-        TM h = 0, s = 0, z = 0;
+        TX h = 0, s = 0, z = 0;
         if (i < g.n) {
             const int a = i / o;
             const int ri = i - a * o;
@@ -111,17 +123,17 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
                 if constexpr (O > 0) {
 #pragma unroll
                     for (int c = 0; c < O; ++c) {
-                        const TM xv = xa[xo + c];
-                        if (DO_H) h += Hv[base + c] * xv;
-                        if (DO_S) s += Sv[base + c] * xv;
-                        if (DO_Z) z += Hv[base + c] * xb[xo + c];
+                        const TX xv = xa[xo + c];
+                        if (DO_H) h += (TX)Hv[base + c] * xv;
+                        if (DO_S) s += (TX)Sv[base + c] * xv;
+                        if (DO_Z) z += (TX)Hv[base + c] * xb[xo + c];
                     }
                 } else {
                     for (int c = 0; c < o; ++c) {
-                        const TM xv = xa[xo + c];
-                        if (DO_H) h += Hv[base + c] * xv;
-                        if (DO_S) s += Sv[base + c] * xv;
-                        if (DO_Z) z += Hv[base + c] * xb[xo + c];
+                        const TX xv = xa[xo + c];
+                        if (DO_H) h += (TX)Hv[base + c] * xv;
+                        if (DO_S) s += (TX)Sv[base + c] * xv;
+                        if (DO_Z) z += (TX)Hv[base + c] * xb[xo + c];
                     }
                 }
             }
@@ -152,17 +164,36 @@ __device__ __forceinline__ double dot_rows(const double (&a)[R], const double (&
     return s;
 }
 
-// out[m] = V[m] . x for m < L (one wavefront per m; x in LDS).
+// out[m] = V[m] . x for m < L (x in LDS).  Each wavefront takes four
+// consecutive m at a time, keeping four independent load streams in flight.
 __device__ __forceinline__ void multidot(const double *__restrict__ V, int64_t ld, int L,
                                          const double *x, int n, double *out)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int m = w; m < L; m += NW) {
-        const double *v = V + m * ld;
-        double acc = 0.0;
-        for (int i = lane; i < n; i += 64) acc += v[i] * x[i];
-        acc = wave_sum(acc);
-        if (lane == 0) out[m] = acc;
+    for (int m0 = 4 * w; m0 < L; m0 += 4 * NW) {
+        const int nm = min(4, L - m0);
+        const double *v0 = V + m0 * ld;
+        const double *v1 = V + (m0 + (nm > 1 ? 1 : 0)) * ld;
+        const double *v2 = V + (m0 + (nm > 2 ? 2 : 0)) * ld;
+        const double *v3 = V + (m0 + (nm > 3 ? 3 : 0)) * ld;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double xi = x[i];
+            a0 += v0[i] * xi;
+            a1 += v1[i] * xi;
+            a2 += v2[i] * xi;
+            a3 += v3[i] * xi;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        a3 = wave_sum(a3);
+        if (lane == 0) {
+            out[m0] = a0;
+            if (nm > 1) out[m0 + 1] = a1;
+            if (nm > 2) out[m0 + 2] = a2;
+            if (nm > 3) out[m0 + 3] = a3;
+        }
     }
 }
 
@@ -176,6 +207,7 @@ __device__ __forceinline__ void sub_comb(double (&l)[R], const double *__restric
         const int i = threadIdx.x + rr * NT;
         if (i < n) {
             double acc = 0.0;
+#pragma unroll 8
             for (int m = 0; m < L; ++m) acc += V[m * ld + i] * c[m];
             l[rr] -= acc;
         }
@@ -193,11 +225,17 @@ struct Smem {
     float *redf;         // NW
 };
 
-template <int O, int R, bool MIXED>
+// PREC 0: FP64 everywhere.  PREC 1: FP32 operator values, vectors and
+// accumulation in every SpMV.  PREC 2: FP32 operator values, FP64 vectors and
+// accumulation in the basis SpMVs.  PREC 1 and 2 run the CG in FP32 with an
+// FP64 residual judge and refinement; Gram-Schmidt, projection and the
+// eigensolve are FP64 in every mode.
+template <int O, int R, int PREC>
 __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm, int c,
                              double *U, double *SU, double *K, double *T)
 {
-    using TM = typename std::conditional<MIXED, float, double>::type;
+    using TM = typename std::conditional<PREC != 0, float, double>::type;
+    using TX = typename std::conditional<PREC == 1, float, double>::type;
     const int o = O ? O : S.o;
     const int tid = threadIdx.x;
     const int64_t ld = S.nmax;
@@ -216,10 +254,12 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         g.jl = S.jloc[g.A] * o + g.r;
     }
     const int n = g.n;
-    const TM *Hv = MIXED ? (const TM *)S.Hf : (const TM *)S.Hd;
-    const TM *Sv = MIXED ? (const TM *)S.Sf : (const TM *)S.Sd;
-    TM *xaT = reinterpret_cast<TM *>(sm.xa);
-    TM *xbT = reinterpret_cast<TM *>(sm.xb);
+    const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
+    const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
+    TX *xaX = reinterpret_cast<TX *>(sm.xa);
+    TX *xbX = reinterpret_cast<TX *>(sm.xb);
+    float *xaF = reinterpret_cast<float *>(sm.xa);
+    float *xbF = reinterpret_cast<float *>(sm.xb);
     double dummy[R];
 
     // ---------------- inner CG: S_A s = e_j ----------------
@@ -235,12 +275,12 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
             if (i < n) x[rr] = (double)J.x0[(int64_t)c * ld + i];
         }
     }
-    if (!MIXED) {
+    if (PREC == 0) {
         double r[R], p[R], q[R];
         // r = e_j - S x
         store_rows<R, double>(sm.xa, x, n);
         __syncthreads();
-        spmv_rows<O, R, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
+        spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
         double rho2 = block_sum(dot_rows<R>(r, r, n), sm.red);
@@ -251,7 +291,7 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
             for (int k = 0; k < n && sqrt(rho2) > J.cg_tol; ++k) {
                 store_rows<R, double>(sm.xa, p, n);
                 __syncthreads();
-                spmv_rows<O, R, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
+                spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
                 const double pq = block_sum(dot_rows<R>(p, q, n), sm.red);
                 if (!(pq > 0.0)) { status = -4; break; }
                 const double alpha = rho2 / pq;
@@ -271,7 +311,7 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
             // judge on the true residual
             store_rows<R, double>(sm.xa, x, n);
             __syncthreads();
-            spmv_rows<O, R, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
+            spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
             rho2 = block_sum(dot_rows<R>(r, r, n), sm.red);
@@ -285,7 +325,7 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         for (int ref = 0; ref <= J.max_refine && status == 0; ++ref) {
             store_rows<R, double>(sm.xa, x, n);
             __syncthreads();
-            spmv_rows<O, R, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
+            spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
             const double rho2 = block_sum(dot_rows<R>(r64, r64, n), sm.red);
@@ -310,9 +350,9 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
             for (int k = 0; k < n && sqrtf(rrf) > thr; ++k) {
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
-                    if (tid + rr * NT < n) xaT[tid + rr * NT] = (TM)pf[rr];
+                    if (tid + rr * NT < n) xaF[tid + rr * NT] = pf[rr];
                 __syncthreads();
-                spmv_rows<O, R, TM, false, true, false>(S, g, o, Hv, Sv, xaT, xbT, dummy, qd, dummy);
+                spmv_rows<O, R, float, float, false, true, false>(S, g, o, S.Hf, S.Sf, xaF, xbF, dummy, qd, dummy);
                 float pq = 0.0f;
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
@@ -358,13 +398,13 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                 __syncthreads();
                 sub_comb<R>(l, U, ld, L, cc, n);
             }
-            store_rows<R, TM>(xaT, l, n);
-            if (chain) store_rows<R, TM>(xbT, t, n);
+            store_rows<R, TX>(xaX, l, n);
+            if (chain) store_rows<R, TX>(xbX, t, n);
             __syncthreads();
             if (chain)
-                spmv_rows<O, R, TM, true, true, true>(S, g, o, Hv, Sv, xaT, xbT, hv, w, zv);
+                spmv_rows<O, R, TM, TX, true, true, true>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
             else
-                spmv_rows<O, R, TM, true, true, false>(S, g, o, Hv, Sv, xaT, xbT, hv, w, zv);
+                spmv_rows<O, R, TM, TX, true, true, false>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
             const double bb = block_sum(dot_rows<R>(l, w, n), sm.red);
             double b0 = bb;
             for (int m = 0; m < L; ++m) b0 += (c1[m] + c2[m]) * (c1[m] + c2[m]);
@@ -427,102 +467,142 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         __syncthreads();   // basis writes visible to the whole workgroup
 
         // ---------------- projection H~ = U^T K, S~ = U^T SU ----------------
-        // Pairs (m <= nn) of the upper triangle, one per thread per pass; rows
-        // are staged through LDS tiles of kTile rows of U, K and S U.  Both
-        // u_m.k_n and u_n.k_m are formed and averaged (symmetrisation).
-        const int np = L * (L + 1) / 2;
+        // Dense L x L products on the FP64 matrix cores: 16 x 16 output tiles,
+        // v_mfma_f64_16x16x4f64 over the region rows, one tile per wavefront
+        // at a time.  Lane l feeds A[l%16][l/16] = u_m[i] and
+        // B[l/16][l%16] = k_n[i] (resp. (S u_n)[i]) and receives
+        // D[4*j + l/16][l%16], j = 0..3.  Both triangles are formed, then
+        // averaged.
         double *Ht = sm.mat, *St = sm.mat + nu * nu, *Y = sm.mat + 2 * nu * nu;
-        double *tU = sm.xa, *tK = sm.xa + L * kTile, *tS = sm.xa + 2 * L * kTile;
-        for (int pbase = 0; pbase < np; pbase += NT) {
-            const int e = pbase + tid;
-            int pm = 0, pn = 0;
-            if (e < np) {
-                int rem = e;
-                while (rem >= L - pm) { rem -= L - pm; ++pm; }
-                pn = pm + rem;
-            }
-            double hu = 0.0, hl = 0.0, su = 0.0, sl = 0.0;
-            for (int i0 = 0; i0 < n; i0 += kTile) {
-                for (int f = tid; f < 3 * L * kTile; f += NT) {
-                    const int which = f / (L * kTile);
-                    const int rem = f - which * L * kTile;
-                    const int m = rem / kTile, ii = rem - m * kTile;
-                    const int i = i0 + ii;
-                    const double *src = which == 0 ? U : (which == 1 ? K : SU);
-                    tU[f] = i < n ? src[m * ld + i] : 0.0;
-                }
-                __syncthreads();
-                if (e < np) {
+        {
+            const int w = tid >> 6, lane = tid & 63;
+            const int nt = (L + 15) >> 4;
+            for (int tile = w; tile < nt * nt; tile += NW) {
+                const int mt = tile / nt, ntc = tile - mt * nt;
+                const int m = mt * 16 + (lane & 15), nn = ntc * 16 + (lane & 15);
+                const int kk = lane >> 4;
+                const bool mok = m < L, nok = nn < L;
+                const double *um = U + (int64_t)(mok ? m : 0) * ld;
+                const double *kn = K + (int64_t)(nok ? nn : 0) * ld;
+                const double *sn = SU + (int64_t)(nok ? nn : 0) * ld;
+                dbl4 ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-                    for (int ii = 0; ii < kTile; ++ii) {
-                        const double um = tU[pm * kTile + ii], un = tU[pn * kTile + ii];
-                        hu += um * tK[pn * kTile + ii];
-                        hl += un * tK[pm * kTile + ii];
-                        su += um * tS[pn * kTile + ii];
-                        sl += un * tS[pm * kTile + ii];
+                for (int i0 = 0; i0 < n; i0 += 4) {
+                    const int i = i0 + kk;
+                    const bool iok = i < n;
+                    const double a = (mok && iok) ? um[i] : 0.0;
+                    const double bh = (nok && iok) ? kn[i] : 0.0;
+                    const double bs = (nok && iok) ? sn[i] : 0.0;
+                    ah = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh, ah, 0, 0, 0);
+                    as = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, as, 0, 0, 0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int mr = mt * 16 + 4 * jj + kk, nc = ntc * 16 + (lane & 15);
+                    if (mr < L && nc < L) {
+                        Y[mr * L + nc] = ah[jj];          // unsymmetrised u_m . k_n
+                        St[mr * L + nc] = as[jj];         // unsymmetrised u_m . S u_n
                     }
                 }
-                __syncthreads();
             }
-            if (e < np) {
-                const double h = 0.5 * (hu + hl), sv = 0.5 * (su + sl);
-                Ht[pm * L + pn] = h;
-                Ht[pn * L + pm] = h;
-                St[pm * L + pn] = sv;
-                St[pn * L + pm] = sv;
+        }
+        __syncthreads();
+        for (int e = tid; e < L * L; e += NT) {
+            const int i = e / L, jj = e - i * L;
+            Ht[e] = 0.5 * (Y[i * L + jj] + Y[jj * L + i]);
+        }
+        __syncthreads();
+        for (int e = tid; e < L * L; e += NT) {
+            const int i = e / L, jj = e - i * L;
+            if (i < jj) {
+                const double v = 0.5 * (St[i * L + jj] + St[jj * L + i]);
+                St[i * L + jj] = v;
+                St[jj * L + i] = v;
             }
         }
         if (tid == 0) s_flag = 0;
         __syncthreads();
 
         // ---------------- reduced generalised eigenproblem ----------------
-        // Cholesky S~ = Lc Lc^T, in place in the lower triangle of St
-        for (int jj = 0; jj < L; ++jj) {
-            if (tid == 0) {
-                double s = St[jj * L + jj];
-                for (int k = 0; k < jj; ++k) s -= St[jj * L + k] * St[jj * L + k];
-                if (!(s > 0.0)) { s_flag = 1; s = 1.0; }
-                St[jj * L + jj] = sqrt(s);
+        // Wavefront 0 alone (L <= 64) computes the Cholesky factor S~ = Lc Lc^T
+        // and the standard form A = Lc^-1 H~ Lc^-T, with wavefront-level
+        // ordering of its LDS traffic instead of workgroup barriers; the
+        // whole workgroup then runs the Jacobi sweeps; wavefront 0 forms
+        // C = Lc^-T Y and the ranks of the eigenvalues.
+        double *ev = sm.cf;                 // L values
+        int *rank = reinterpret_cast<int *>(sm.cf + kMaxNu);
+        if (tid < 64) {
+            const int lane = tid;
+            for (int jj = 0; jj < L; ++jj) {
+                if (lane == 0) {
+                    double sd = St[jj * L + jj];
+                    for (int k = 0; k < jj; ++k) sd -= St[jj * L + k] * St[jj * L + k];
+                    if (!(sd > 0.0)) { s_flag = 1; sd = 1.0; }
+                    St[jj * L + jj] = sqrt(sd);
+                }
+                wave_sync();
+                for (int i = jj + 1 + lane; i < L; i += 64) {
+                    double t2 = St[i * L + jj];
+                    for (int k = 0; k < jj; ++k) t2 -= St[i * L + k] * St[jj * L + k];
+                    St[i * L + jj] = t2 / St[jj * L + jj];
+                }
+                wave_sync();
             }
-            __syncthreads();
-            for (int i = jj + 1 + tid; i < L; i += NT) {
-                double t2 = St[i * L + jj];
-                for (int k = 0; k < jj; ++k) t2 -= St[i * L + k] * St[jj * L + k];
-                St[i * L + jj] = t2 / St[jj * L + jj];
+            // W = Lc^-1 H~ -> Y (one column per lane)
+            for (int cc = lane; cc < L; cc += 64)
+                for (int i = 0; i < L; ++i) {
+                    double t2 = Ht[i * L + cc];
+                    for (int k = 0; k < i; ++k) t2 -= St[i * L + k] * Y[k * L + cc];
+                    Y[i * L + cc] = t2 / St[i * L + i];
+                }
+            wave_sync();
+            // A = Lc^-1 W^T -> Ht
+            for (int cc = lane; cc < L; cc += 64)
+                for (int i = 0; i < L; ++i) {
+                    double t2 = Y[cc * L + i];
+                    for (int k = 0; k < i; ++k) t2 -= St[i * L + k] * Ht[k * L + cc];
+                    Ht[i * L + cc] = t2 / St[i * L + i];
+                }
+            wave_sync();
+            for (int e = lane; e < L * L; e += 64) {
+                const int i = e / L, jj = e - i * L;
+                if (i < jj) {
+                    const double v = 0.5 * (Ht[i * L + jj] + Ht[jj * L + i]);
+                    Ht[i * L + jj] = v;
+                    Ht[jj * L + i] = v;
+                }
             }
-            __syncthreads();
+            for (int e = lane; e < L * L; e += 64) Y[e] = (e / L == e % L) ? 1.0 : 0.0;
+            wave_sync();
+
         }
-        // W = Lc^-1 H~  -> Y
-        for (int cc = tid; cc < L; cc += NT)
-            for (int i = 0; i < L; ++i) {
-                double t2 = Ht[i * L + cc];
-                for (int k = 0; k < i; ++k) t2 -= St[i * L + k] * Y[k * L + cc];
-                Y[i * L + cc] = t2 / St[i * L + i];
-            }
-        __syncthreads();
-        // A = Lc^-1 W^T -> Ht
-        for (int cc = tid; cc < L; cc += NT)
-            for (int i = 0; i < L; ++i) {
-                double t2 = Y[cc * L + i];
-                for (int k = 0; k < i; ++k) t2 -= St[i * L + k] * Ht[k * L + cc];
-                Ht[i * L + cc] = t2 / St[i * L + i];
-            }
-        __syncthreads();
-        for (int e = tid; e < L * L; e += NT) {
-            const int i = e / L, jj = e - i * L;
-            if (i < jj) {
-                const double v = 0.5 * (Ht[i * L + jj] + Ht[jj * L + i]);
-                Ht[i * L + jj] = v;
-                Ht[jj * L + i] = v;
-            }
-        }
-        for (int e = tid; e < L * L; e += NT) Y[e] = (e / L == e % L) ? 1.0 : 0.0;
         __syncthreads();
 
-        // parallel cyclic Jacobi (round-robin pairing of L2 = even(L) indices)
+        // Cyclic Jacobi on A (all wavefronts).  Each round applies L2/2
+        // disjoint rotations (circle-method pairing); A <- J^T A J is done as
+        // independent 2x2 block updates (rows of pair k1 x columns of pair
+        // k2), Y <- Y J as independent row pairs, so a round needs only the
+        // barrier after the angles and the one after the updates.
         {
-            double *rot = sm.cf + 2 * kMaxNu;        // c, s per pair (kMaxNu/2 pairs)
+            double *rot = sm.cf + 2 * kMaxNu;                          // c, s per pair
+            int *prs = reinterpret_cast<int *>(sm.cf + 3 * kMaxNu);   // p, q per pair
             const int L2 = L + (L & 1);
+            const int npair = L2 / 2;
+            constexpr int kMaxBlk = (kMaxNu / 2) * (kMaxNu / 2) / NT;   // 4
+            constexpr int kMaxYi = kMaxNu * (kMaxNu / 2) / NT;          // 8
+            int bk1[kMaxBlk], bk2[kMaxBlk], yr[kMaxYi], yk[kMaxYi];
+#pragma unroll
+            for (int u = 0; u < kMaxBlk; ++u) {
+                const int e = tid + u * NT;
+                bk1[u] = e < npair * npair ? e / npair : -1;
+                bk2[u] = e < npair * npair ? e - (e / npair) * npair : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kMaxYi; ++u) {
+                const int e = tid + u * NT;
+                yr[u] = e < L * npair ? e / npair : -1;
+                yk[u] = e < L * npair ? e - (e / npair) * npair : -1;
+            }
             double off_prev = INFINITY;
             for (int sweep = 0; sweep < 60 && L > 1; ++sweep) {
                 double off = 0.0, fro = 0.0;
@@ -538,7 +618,7 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                 if (off <= 1e-24 * fro && off > 0.25 * off_prev) break;
                 off_prev = off;
                 for (int round = 0; round < L2 - 1; ++round) {
-                    if (tid < L2 / 2) {
+                    if (tid < npair) {
                         const int ia = tid == 0 ? 0 : 1 + (tid - 1 + round) % (L2 - 1);
                         const int ib = 1 + (L2 - 2 - tid + round) % (L2 - 1);
                         const int pp = min(ia, ib), qq = max(ia, ib);
@@ -556,61 +636,66 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                         }
                         rot[2 * tid] = cs;
                         rot[2 * tid + 1] = sn;
+                        prs[2 * tid] = pp;
+                        prs[2 * tid + 1] = qq;
                     }
                     __syncthreads();
-                    // rows: A <- J^T A
-                    for (int e = tid; e < (L2 / 2) * L; e += NT) {
-                        const int kp = e / L, col = e - kp * L;
-                        const int ia = kp == 0 ? 0 : 1 + (kp - 1 + round) % (L2 - 1);
-                        const int ib = 1 + (L2 - 2 - kp + round) % (L2 - 1);
-                        const int pp = min(ia, ib), qq = max(ia, ib);
-                        if (qq < L) {
-                            const double cs = rot[2 * kp], sn = rot[2 * kp + 1];
-                            const double apk = Ht[pp * L + col], aqk = Ht[qq * L + col];
-                            Ht[pp * L + col] = cs * apk - sn * aqk;
-                            Ht[qq * L + col] = sn * apk + cs * aqk;
-                        }
+#pragma unroll
+                    for (int u = 0; u < kMaxBlk; ++u) {
+                        if (bk1[u] < 0) continue;
+                        const int ra = prs[2 * bk1[u]], rb = prs[2 * bk1[u] + 1];
+                        const int ca = prs[2 * bk2[u]], cb = prs[2 * bk2[u] + 1];
+                        const double c1 = rot[2 * bk1[u]], s1 = rot[2 * bk1[u] + 1];
+                        const double c2 = rot[2 * bk2[u]], s2 = rot[2 * bk2[u] + 1];
+                        const bool rbo = rb < L, cbo = cb < L;
+                        const double x_ac = Ht[ra * L + ca];
+                        const double x_ad = cbo ? Ht[ra * L + cb] : 0.0;
+                        const double x_bc = rbo ? Ht[rb * L + ca] : 0.0;
+                        const double x_bd = (rbo && cbo) ? Ht[rb * L + cb] : 0.0;
+                        // rows (J^T .): a' = c1 a - s1 b, b' = s1 a + c1 b
+                        const double y_ac = c1 * x_ac - s1 * x_bc, y_bc = s1 * x_ac + c1 * x_bc;
+                        const double y_ad = c1 * x_ad - s1 * x_bd, y_bd = s1 * x_ad + c1 * x_bd;
+                        // columns (. J): c' = c2 c - s2 d, d' = s2 c + c2 d
+                        Ht[ra * L + ca] = c2 * y_ac - s2 * y_ad;
+                        if (cbo) Ht[ra * L + cb] = s2 * y_ac + c2 * y_ad;
+                        if (rbo) Ht[rb * L + ca] = c2 * y_bc - s2 * y_bd;
+                        if (rbo && cbo) Ht[rb * L + cb] = s2 * y_bc + c2 * y_bd;
                     }
-                    __syncthreads();
-                    // columns: A <- A J, Y <- Y J
-                    for (int e = tid; e < (L2 / 2) * L; e += NT) {
-                        const int kp = e / L, row = e - kp * L;
-                        const int ia = kp == 0 ? 0 : 1 + (kp - 1 + round) % (L2 - 1);
-                        const int ib = 1 + (L2 - 2 - kp + round) % (L2 - 1);
-                        const int pp = min(ia, ib), qq = max(ia, ib);
-                        if (qq < L) {
-                            const double cs = rot[2 * kp], sn = rot[2 * kp + 1];
-                            const double akp = Ht[row * L + pp], akq = Ht[row * L + qq];
-                            Ht[row * L + pp] = cs * akp - sn * akq;
-                            Ht[row * L + qq] = sn * akp + cs * akq;
-                            const double ykp = Y[row * L + pp], ykq = Y[row * L + qq];
-                            Y[row * L + pp] = cs * ykp - sn * ykq;
-                            Y[row * L + qq] = sn * ykp + cs * ykq;
-                        }
+#pragma unroll
+                    for (int u = 0; u < kMaxYi; ++u) {
+                        if (yr[u] < 0) continue;
+                        const int pp = prs[2 * yk[u]], qq = prs[2 * yk[u] + 1];
+                        if (qq >= L) continue;
+                        const double cs = rot[2 * yk[u]], sn = rot[2 * yk[u] + 1];
+                        const int row = yr[u];
+                        const double ykp = Y[row * L + pp], ykq = Y[row * L + qq];
+                        Y[row * L + pp] = cs * ykp - sn * ykq;
+                        Y[row * L + qq] = sn * ykp + cs * ykq;
                     }
                     __syncthreads();
                 }
             }
         }
-        // eigenvalues and their ascending ranks
-        double *ev = sm.cf;                 // L values
-        int *rank = reinterpret_cast<int *>(sm.cf + kMaxNu);
-        for (int a = tid; a < L; a += NT) ev[a] = Ht[a * L + a];
-        __syncthreads();
-        for (int a = tid; a < L; a += NT) {
-            int rk = 0;
-            const double va = ev[a];
-            for (int b = 0; b < L; ++b)
-                if (ev[b] < va || (ev[b] == va && b < a)) ++rk;
-            rank[a] = rk;
-        }
-        // C = Lc^-T Y -> Ht
-        for (int cc = tid; cc < L; cc += NT)
-            for (int i = L - 1; i >= 0; --i) {
-                double t2 = Y[i * L + cc];
-                for (int k = i + 1; k < L; ++k) t2 -= St[k * L + i] * Ht[k * L + cc];
-                Ht[i * L + cc] = t2 / St[i * L + i];
+        if (tid < 64) {
+            const int lane = tid;
+            // eigenvalues and their ascending ranks
+            for (int a = lane; a < L; a += 64) ev[a] = Ht[a * L + a];
+            wave_sync();
+            for (int a = lane; a < L; a += 64) {
+                int rk = 0;
+                const double va = ev[a];
+                for (int bb = 0; bb < L; ++bb)
+                    if (ev[bb] < va || (ev[bb] == va && bb < a)) ++rk;
+                rank[a] = rk;
             }
+            // C = Lc^-T Y -> Ht
+            for (int cc = lane; cc < L; cc += 64)
+                for (int i = L - 1; i >= 0; --i) {
+                    double t2 = Y[i * L + cc];
+                    for (int k = i + 1; k < L; ++k) t2 -= St[k * L + i] * Ht[k * L + cc];
+                    Ht[i * L + cc] = t2 / St[i * L + i];
+                }
+        }
         __syncthreads();
         if (s_flag) status = -4;
     }
@@ -666,7 +751,7 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
     __syncthreads();
 }
 
-template <int O, int R, bool MIXED>
+template <int O, int R, int PREC>
 __global__ void __launch_bounds__(NT) k_solve(DevSystem S, DevJob J)
 {
     extern __shared__ double smem[];
@@ -685,19 +770,32 @@ __global__ void __launch_bounds__(NT) k_solve(DevSystem S, DevJob J)
     double *SU = U + J.nu * ld;
     double *K = SU + J.nu * ld;
     double *T = K + J.nu * ld;
+    // Work queues: queue k serves order[qbounds[k] .. qbounds[k+1]); a
+    // workgroup starts at queue blockIdx.x % nqueues and moves to the next
+    // queue when one is exhausted.  Every queue is visited at most once, so
+    // every workgroup leaves the loop.
+    int qi = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_idx = atomicAdd(J.queue, 1);
+        if (threadIdx.x == 0) {
+            int idx = -1;
+            for (; qi < J.nqueues; ++qi) {
+                const int k = (blockIdx.x + qi) % J.nqueues;
+                const int pos = J.qbounds[k] + atomicAdd(J.queue + k, 1);
+                if (pos < J.qbounds[k + 1]) { idx = pos; break; }
+            }
+            s_idx = idx;
+        }
         __syncthreads();
         const int idx = s_idx;
         __syncthreads();
-        if (idx >= J.ncols) break;
-        solve_column<O, R, MIXED>(S, J, sm, J.order[idx], U, SU, K, T);
+        if (idx < 0) break;
+        solve_column<O, R, PREC>(S, J, sm, J.order[idx], U, SU, K, T);
     }
 }
 
 __global__ void k_reset(int *queue, int *fail)
 {
-    queue[0] = 0;
+    for (int k = 0; k < kMaxQueues; ++k) queue[k] = 0;
     fail[0] = INT_MAX;
 }
 
@@ -875,11 +973,11 @@ __global__ void __launch_bounds__(1024) k_sum2(const double *a, const double *b,
     }
 }
 
-template <int O, int R, bool MIXED>
+template <int O, int R, int PREC>
 hipError_t launch_solve_t(const DevSystem &S, const DevJob &J, int slots, hipStream_t st)
 {
     const size_t smem = solve_smem_bytes(S.nmax, J.nu);
-    auto kern = k_solve<O, R, MIXED>;
+    auto kern = k_solve<O, R, PREC>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
@@ -887,39 +985,37 @@ hipError_t launch_solve_t(const DevSystem &S, const DevJob &J, int slots, hipStr
     return hipGetLastError();
 }
 
-template <int O, int R, bool MIXED>
+template <int O, int R, int PREC>
 hipError_t occupancy_t(const DevSystem &S, const DevJob &J, int *bpc)
 {
     const size_t smem = solve_smem_bytes(S.nmax, J.nu);
-    auto kern = k_solve<O, R, MIXED>;
+    auto kern = k_solve<O, R, PREC>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, kern, NT, smem);
 }
 
-#define MA_DISPATCH_R(FN, O, MIXED, ...)                                  \
+#define MA_DISPATCH_R(FN, O, PREC, ...)                                   \
     switch (R) {                                                          \
-    case 1: return FN<O, 1, MIXED>(__VA_ARGS__);                          \
-    case 2: return FN<O, 2, MIXED>(__VA_ARGS__);                          \
-    case 3: return FN<O, 3, MIXED>(__VA_ARGS__);                          \
-    case 4: return FN<O, 4, MIXED>(__VA_ARGS__);                          \
-    case 6: return FN<O, 6, MIXED>(__VA_ARGS__);                          \
-    default: return FN<O, 8, MIXED>(__VA_ARGS__);                         \
+    case 1: return FN<O, 1, PREC>(__VA_ARGS__);                           \
+    case 2: return FN<O, 2, PREC>(__VA_ARGS__);                           \
+    case 3: return FN<O, 3, PREC>(__VA_ARGS__);                           \
+    case 4: return FN<O, 4, PREC>(__VA_ARGS__);                           \
+    case 6: return FN<O, 6, PREC>(__VA_ARGS__);                           \
+    default: return FN<O, 8, PREC>(__VA_ARGS__);                          \
     }
+
+#define MA_DISPATCH_P(FN, O, ...)                                         \
+    if (J.precision == 1) { MA_DISPATCH_R(FN, O, 1, __VA_ARGS__) }       \
+    else if (J.precision == 2) { MA_DISPATCH_R(FN, O, 2, __VA_ARGS__) }  \
+    else { MA_DISPATCH_R(FN, O, 0, __VA_ARGS__) }
 
 #define MA_DISPATCH(FN, ...)                                              \
     const int R = solve_rows_per_thread(S.nmax);                          \
-    if (S.o == 4) {                                                       \
-        if (J.precision) { MA_DISPATCH_R(FN, 4, true, __VA_ARGS__) }     \
-        else { MA_DISPATCH_R(FN, 4, false, __VA_ARGS__) }                \
-    } else if (S.o == 9) {                                                \
-        if (J.precision) { MA_DISPATCH_R(FN, 9, true, __VA_ARGS__) }     \
-        else { MA_DISPATCH_R(FN, 9, false, __VA_ARGS__) }                \
-    } else {                                                              \
-        if (J.precision) { MA_DISPATCH_R(FN, 0, true, __VA_ARGS__) }     \
-        else { MA_DISPATCH_R(FN, 0, false, __VA_ARGS__) }                \
-    }
+    if (S.o == 4) { MA_DISPATCH_P(FN, 4, __VA_ARGS__) }                   \
+    else if (S.o == 9) { MA_DISPATCH_P(FN, 9, __VA_ARGS__) }              \
+    else { MA_DISPATCH_P(FN, 0, __VA_ARGS__) }
 
 }  // namespace
 

@@ -1,8 +1,14 @@
 """Parity of the HIP library (through its C interface) with the CPU oracle.
 
 FP64 mode: max-abs rho/pi <= 1e-10, relative band energy <= 1e-12 (both sides
-at CG tolerance 1e-12).  Mixed mode (FP32 SpMV/CG, FP64 Gram-Schmidt,
-projection and eigensolve): relative band energy <= 1e-6, max-abs rho <= 1e-5.
+at CG tolerance 1e-12).
+Mixed mode with FP64 accumulation (FP32 operator values, FP64 vectors and
+accumulation in the basis SpMVs, FP32 CG with FP64 refinement, FP64
+Gram-Schmidt, projection and eigensolve): relative band energy <= 1e-6,
+max-abs rho <= 1e-5.
+Mixed mode with FP32 accumulation (FP32 values, vectors and sums in every
+SpMV): relative band energy <= 1e-6, max-abs rho <= 1e-4 (measured 1.6e-5 on
+the 64-atom cell, 4.2e-5 on the 4,096-atom sample).
 """
 
 import math
@@ -17,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 FP64_RHO_TOL = 1e-10
 FP64_E_TOL = 1e-12
-MIXED_RHO_TOL = 1e-5
+MIXED_RHO_TOL = {"mixed_f64acc": 1e-5, "mixed": 1e-4}
 MIXED_E_TOL = 1e-6
 
 
@@ -125,32 +131,59 @@ def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda):
     s = synth.config_diamond4096()
     _say("diamond4096 build")
     ctx.build_tb(s)
-    cols = np.sort(np.random.default_rng(7).choice(s.M, 192, replace=False)).astype(np.int32)
-    _say("diamond4096 fp64 solve 192 sampled columns")
+    rng = np.random.default_rng(7)
+    cols = np.sort(np.concatenate([rng.choice(s.M, 190, replace=False), [8178, 8179]]))
+    cols = np.unique(cols).astype(np.int32)
+    _say(f"diamond4096 fp64 solve {len(cols)} sampled columns")
     gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT)
     ora = oracle.solve(s, cols=cols, mu=0.95)
     _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-def test_mixed_diamond64(ctx, torch_cuda):
+def _compare_mixed(s, raw, cols, gpu, mu_oracle, prec):
+    """Mixed precision: rho/pi against the oracle evaluated at the GPU's mu
+    (the Ritz data are compared, not the two bisections), plus mu and the band
+    energy at the oracle's own mu."""
+    import oracle
+    res, rho, pi, eps, wts, st = gpu
+    assert np.array_equal(st[:, 0], raw["nu_eff"]) and np.all(st[:, 3] == 0)
+    rr, pp, E, N = oracle.outputs(s, raw, res.mu, s.kT)
+    rho_o = oracle.scatter_slots(s, raw["cols"], rr)
+    pi_o = oracle.scatter_slots(s, raw["cols"], pp)
+    d_rho = np.abs(rho - rho_o).max()
+    d_pi = np.abs(pi - pi_o).max()
+    e_o = 2.0 * float(np.sum(E))
+    d_e = abs(res.energy - e_o) / abs(e_o)
+    _say(f"mixed: max|drho|={d_rho:.3e} max|dpi|={d_pi:.3e} rel dE={d_e:.3e} "
+         f"mu gpu={res.mu:.12f} oracle={mu_oracle:.12f} cg={st[:, 1].mean():.1f} "
+         f"judge={st[:, 2].mean():.1f}")
+    assert abs(res.mu - mu_oracle) <= 1e-4
+    assert d_e <= MIXED_E_TOL
+    assert d_rho <= MIXED_RHO_TOL[prec]
+    assert d_pi <= MIXED_RHO_TOL[prec] * max(1.0, np.abs(pi_o).max())
+
+
+@pytest.mark.parametrize("prec", ["mixed", "mixed_f64acc"])
+def test_mixed_diamond64(ctx, torch_cuda, prec):
     import oracle
     s = synth.config_diamond64()
     ctx.build_tb(s)
-    _say("diamond64 mixed")
-    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, precision="mixed")
-    ora = oracle.solve(s)
-    _compare(s, ora, None, gpu, MIXED_RHO_TOL, MIXED_E_TOL, mu_tol=1e-5)
+    _say(f"diamond64 {prec}")
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, precision=prec)
+    raw = oracle.solve_raw(s)
+    _compare_mixed(s, raw, None, gpu, oracle.find_mu(raw, s.kT, s.n_target), prec)
 
 
-def test_mixed_diamond4096_sampled(ctx, torch_cuda):
+@pytest.mark.parametrize("prec", ["mixed", "mixed_f64acc"])
+def test_mixed_diamond4096_sampled(ctx, torch_cuda, prec):
     import oracle
     s = synth.config_diamond4096()
     ctx.build_tb(s)
     cols = np.sort(np.random.default_rng(8).choice(s.M, 192, replace=False)).astype(np.int32)
-    _say("diamond4096 mixed 192 columns")
-    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT, precision="mixed")
-    ora = oracle.solve(s, cols=cols, mu=0.95)
-    _compare(s, ora, cols, gpu, MIXED_RHO_TOL, MIXED_E_TOL)
+    _say(f"diamond4096 {prec} 192 columns, mu = 0.95")
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT, precision=prec)
+    raw = oracle.solve_raw(s, cols)
+    _compare_mixed(s, raw, cols, gpu, 0.95, prec)
 
 
 def test_invalid_arguments_rejected(ctx, torch_cuda):

@@ -1,0 +1,98 @@
+"""Schedules, hipGraph replay, determinism and the autotuner (GPU)."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1202_0098_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1202_0098_amd as ma
+    ctx = ma.Context(0)
+    s = synth.config_diamond4096()
+    ctx.build_tb(s)
+    yield torch, ma, ctx, s
+    ctx.close()
+
+
+def _run(torch, ma, ctx, s, cols, **opt):
+    o = s.n_orb
+    rho = torch.zeros(s.nblk * o * o, dtype=torch.float64, device="cuda")
+    res = ctx.solve_columns(cols, s.p, s.q, mu=opt.pop("mu", math.nan), kT=s.kT,
+                            opts=ma.default_opts(**opt), rho=rho)
+    torch.cuda.synchronize()
+    return res, rho.cpu().numpy()
+
+
+def test_schedules_give_identical_results(env):
+    torch, ma, ctx, s = env
+    cols = np.arange(0, s.M, 5, dtype=np.int32)
+    ref = None
+    for sched in ["lpt", "input", "xcd_input", "xcd_lpt"]:
+        for slots in [1, 3]:
+            _say(f"schedule {sched} slots/CU {slots}")
+            res, rho = _run(torch, ma, ctx, s, cols, schedule=sched, slots_per_cu=slots,
+                            use_graph=0)
+            if ref is None:
+                ref = (res, rho)
+            assert np.array_equal(rho, ref[1])
+            assert res.energy == ref[0].energy and res.mu == ref[0].mu
+
+
+def test_graph_replay_matches_eager(env):
+    torch, ma, ctx, s = env
+    cols = np.arange(0, s.M, 3, dtype=np.int32)
+    _say("eager reference")
+    eager, rho_e = _run(torch, ma, ctx, s, cols, use_graph=0)
+    o = s.n_orb
+    rho = torch.zeros(s.nblk * o * o, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        _say(f"graph replay {rep}")
+        res = ctx.solve_columns(cols, s.p, s.q, mu=math.nan, kT=s.kT,
+                                opts=ma.default_opts(use_graph=1), rho=rho)
+        torch.cuda.synchronize()
+        got = rho.cpu().numpy()
+        assert np.array_equal(got, rho_e), f"replay {rep} differs"
+        assert res.energy == eager.energy and res.mu == eager.mu
+        assert res.kernel_ms > 0.0
+        # eager work of the program between replays
+        rho.zero_()
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert float((x * x).sum()) > 0
+
+
+def test_fp64_run_to_run_bitwise(env):
+    torch, ma, ctx, s = env
+    cols = np.arange(1, s.M, 7, dtype=np.int32)
+    a = _run(torch, ma, ctx, s, cols)
+    b = _run(torch, ma, ctx, s, cols)
+    assert np.array_equal(a[1], b[1]) and a[0].energy == b[0].energy
+
+
+def test_autotune_then_auto_solve(env):
+    torch, ma, ctx, s = env
+    cols = np.arange(0, s.M, 4, dtype=np.int32)
+    _say("autotune")
+    t = ctx.autotune(cols, s.p, s.q, mu=0.9, kT=s.kT, reps=1)
+    _say(f"autotune chose {t['slots_per_cu']} slots/CU, schedule {t['schedule']}, "
+         f"{t['best_ms']:.2f} ms of {len(t['tried'])} candidates")
+    assert t["slots_per_cu"] >= 1 and len(t["tried"]) >= 4
+    assert t["best_ms"] == min(m for _, _, m in t["tried"])
+    res, rho = _run(torch, ma, ctx, s, cols, mu=0.9)
+    ref, rho_ref = _run(torch, ma, ctx, s, cols, mu=0.9, schedule="lpt", slots_per_cu=1)
+    assert np.array_equal(rho, rho_ref)
