@@ -81,7 +81,7 @@ def main():
     dev = "cuda"
     rho = torch.zeros(s.nblk * o * o, dtype=torch.float64, device=dev)
     pi = torch.zeros_like(rho)
-    stats = torch.zeros(s.M * 4, dtype=torch.int32, device=dev)
+    stats = torch.zeros(s.M * ma.STATS, dtype=torch.int32, device=dev)
     opts = ma.default_opts(precision=args.precision)
     tuning = None
     if not args.no_autotune:
@@ -110,7 +110,7 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
     cols_per_s = s.M / (wall / args.steps)
-    st = stats.cpu().numpy().reshape(s.M, 4)
+    st = stats.cpu().numpy().reshape(s.M, ma.STATS)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {cols_per_s:.4g} columns/s; "
         f"nu_eff mean {st[:, 0].mean():.2f}, CG iters mean {st[:, 1].mean():.2f}")
 

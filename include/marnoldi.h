@@ -138,14 +138,20 @@ typedef struct {
     double *pi;             /* device, same layout */
     double *eps;            /* device, ncols*(p+q): Ritz values ascending, NaN padded */
     double *wts;            /* device, ncols*(p+q): w_a = v_ja (S v_a)_j */
-    int32_t *col_stats;     /* device, ncols*4: nu_eff, CG iterations,
-                               FP64 residual evaluations, status */
+    int32_t *col_stats;     /* device, ncols*8: nu_eff, CG iterations, FP64
+                               residual evaluations, status, start used (0 zero,
+                               1 learned, 2 learned but rejected by the residual
+                               judge), 3 reserved */
     double energy;          /* spin * sum_j E_j over the solved columns */
     double n_elec;          /* spin * sum_j N_j over the solved columns */
     double mu;              /* chemical potential used */
     double elapsed_ms;      /* device time of the whole solve on the stream */
     double kernel_ms;       /* device time of the column kernel alone (HIP events
                                around its launch on the same stream) */
+    float *sj_near;         /* device, ncols*12*o, optional: the converged s_j on the
+                               orbitals of the 12 atoms nearest to atom(j), nearest
+                               first (atom(j) itself first), the start network's
+                               training target */
 } ma_result;
 
 /* Result of ma_autotune. */
@@ -212,6 +218,51 @@ MA_API int64_t ma_region_atoms(const ma_system *sys, const ma_region *reg, int32
 MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *cols,
                                   int32_t p, int32_t q, double mu, double kT,
                                   const ma_opts *opts, ma_result *out);
+
+/* ------------------------------------------------------------------------
+ * Learned CG start (callers that want fewer CG iterations).  A 3-layer
+ * perceptron (width 256, SiLU) maps a column's descriptor -- for each of the
+ * 48 atoms nearest to atom(j), excluding it, nearest first: |d|/5 A and the
+ * unit vector d/|d| -- plus the one-hot orbital of j (n_in = 192 + o) to the
+ * coefficients of s_j on the orbitals of the 12 atoms nearest to atom(j)
+ * (n_out = 12 o).  Inference runs in BF16 on the matrix cores with FP32
+ * accumulation; training runs in FP32.  In a solve with MA_START_LEARNED the
+ * prediction is the CG start unless the FP64 residual ||S_A x0 - e_j|| is
+ * not below ||e_j|| = 1, in which case the column starts from zero.
+ * Descriptors need positions in ma_system.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_in, n_hidden, n_out;
+    int64_t n_params;   /* W1 (n_in x n_hidden), b1, W2 (n_hidden^2), b2, W3 (n_hidden x n_out), b3 */
+} ma_mlp_shape;
+
+/* Shape of the start network for the built system. */
+MA_API ma_status ma_mlp_shape_of(const ma_ctx *ctx, ma_mlp_shape *out);
+
+/* Random initial weights (He-scaled normal, zero biases, seeded) and zeroed
+ * Adam state; the network becomes the context's start model. */
+MA_API ma_status ma_mlp_init(ma_ctx *ctx, uint64_t seed);
+
+/* Copy the parameters (host, FP32, the packed order of ma_mlp_shape) in/out. */
+MA_API ma_status ma_mlp_set_params(ma_ctx *ctx, const float *params, int64_t count);
+MA_API ma_status ma_mlp_get_params(const ma_ctx *ctx, float *params, int64_t count);
+
+/* Descriptors of cols[0..ncols) (host list) into feat (device, ncols * n_in). */
+MA_API ma_status ma_column_features(ma_ctx *ctx, int64_t ncols, const int32_t *cols, float *feat);
+
+/* y = net(x) for n rows (device arrays, n * n_in -> n * n_out); bf16 = 1 uses
+ * the inference kernel, 0 the FP32 training path. */
+MA_API ma_status ma_mlp_forward(ma_ctx *ctx, const float *x, int64_t n, float *y, int32_t bf16);
+
+/* Mean squared error over n rows (rows idx[i] of x and t if idx != NULL) and
+ * its gradient (host, n_params floats, may be NULL). */
+MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
+                                  int64_t n, double *loss, float *grad);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of the
+ * n rows idx[i] (device int32, NULL = rows 0..n-1) of x and t (device). */
+MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
+                                   int64_t n, float lr, double *loss);
 
 /* Autotuner: time the column kernel on cols[0..ncols) (NULL = all) for every
  * candidate (slots per CU from 1 to the occupancy limit, x every schedule),

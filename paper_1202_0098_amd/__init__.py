@@ -27,7 +27,9 @@ PREC = {"fp64": 0, "mixed": 1, "mixed_f64acc": 2}
 # the functions include/marnoldi.h declares
 API_FUNCTIONS = ("ma_version", "ma_default_opts", "ma_create", "ma_destroy", "ma_last_error",
                  "ma_build_system", "ma_system_info", "ma_region_sizes", "ma_region_atoms",
-                 "ma_solve_columns", "ma_autotune", "ma_set_tuning")
+                 "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
+                 "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
+                 "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step")
 
 
 class MarnoldiError(RuntimeError):
@@ -72,7 +74,15 @@ class _Result(ctypes.Structure):
                 ("wts", ctypes.c_void_p), ("col_stats", ctypes.c_void_p),
                 ("energy", ctypes.c_double), ("n_elec", ctypes.c_double),
                 ("mu", ctypes.c_double), ("elapsed_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("sj_near", ctypes.c_void_p)]
+
+
+class _MlpShape(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("n_params", ctypes.c_int64)]
+
+
+STATS = 8   # per-column statistics (see ma_result.col_stats)
 
 
 _lib = None
@@ -109,8 +119,21 @@ def load_library():
     lib.ma_autotune.argtypes = [P, i64, P, i32, i32, f64, f64, ctypes.POINTER(_Opts), i32,
                                 ctypes.POINTER(_Tuning)]
     lib.ma_set_tuning.argtypes = [P, i32, i32, i32, i32, i32]
+    lib.ma_mlp_shape_of.argtypes = [P, ctypes.POINTER(_MlpShape)]
+    lib.ma_mlp_init.argtypes = [P, ctypes.c_uint64]
+    lib.ma_mlp_set_params.argtypes = [P, P, i64]
+    lib.ma_mlp_get_params.argtypes = [P, P, i64]
+    lib.ma_column_features.argtypes = [P, i64, P, P]
+    lib.ma_mlp_forward.argtypes = [P, P, i64, P, i32]
+    lib.ma_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, P]
+    lib.ma_mlp_train_step.argtypes = [P, P, P, P, i64, ctypes.c_float, P]
+    for name in ("ma_mlp_shape_of", "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params",
+                 "ma_column_features", "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("ma_create", "ma_destroy", "ma_build_system", "ma_system_info",
-                 "ma_solve_columns", "ma_autotune", "ma_set_tuning"):
+                 "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
+                 "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
+                 "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -128,6 +151,8 @@ def default_opts(**kw) -> _Opts:
             v = PREC[v]
         if k == "schedule" and isinstance(v, str):
             v = SCHEDULES[v]
+        if k == "start" and isinstance(v, str):
+            v = {"zero": 0, "learned": 1}[v]
         setattr(o, k, v)
     return o
 
@@ -260,8 +285,47 @@ class Context:
         sch = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         self._check(self._lib.ma_set_tuning(self._h, int(p), int(q), prec, int(slots_per_cu), sch))
 
+    # ---- learned CG start ----------------------------------------------------
+    def mlp_shape(self):
+        sh = _MlpShape()
+        self._check(self._lib.ma_mlp_shape_of(self._h, ctypes.byref(sh)))
+        return dict(n_in=sh.n_in, n_hidden=sh.n_hidden, n_out=sh.n_out, n_params=sh.n_params)
+
+    def mlp_init(self, seed: int = 0):
+        self._check(self._lib.ma_mlp_init(self._h, ctypes.c_uint64(seed)))
+
+    def mlp_set_params(self, params):
+        params = np.ascontiguousarray(params, np.float32)
+        self._check(self._lib.ma_mlp_set_params(self._h, _ptr(params), len(params)))
+
+    def mlp_get_params(self):
+        n = self.mlp_shape()["n_params"]
+        out = np.zeros(n, np.float32)
+        self._check(self._lib.ma_mlp_get_params(self._h, _ptr(out), n))
+        return out
+
+    def column_features(self, cols, feat):
+        cols = np.ascontiguousarray(cols, np.int32)
+        self._check(self._lib.ma_column_features(self._h, len(cols), _ptr(cols), _ptr(feat)))
+
+    def mlp_forward(self, x, n, y, bf16=True):
+        self._check(self._lib.ma_mlp_forward(self._h, _ptr(x), int(n), _ptr(y), int(bool(bf16))))
+
+    def mlp_loss_grad(self, x, t, n, idx=None, want_grad=True):
+        loss = ctypes.c_double()
+        g = np.zeros(self.mlp_shape()["n_params"], np.float32) if want_grad else None
+        self._check(self._lib.ma_mlp_loss_grad(self._h, _ptr(x), _ptr(t), _ptr(idx), int(n),
+                                               ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def mlp_train_step(self, x, t, n, lr, idx=None):
+        loss = ctypes.c_double()
+        self._check(self._lib.ma_mlp_train_step(self._h, _ptr(x), _ptr(t), _ptr(idx), int(n),
+                                                ctypes.c_float(lr), ctypes.byref(loss)))
+        return loss.value
+
     def solve_columns(self, cols, p, q, mu=math.nan, kT=0.1, opts=None, rho=None, pi=None,
-                      eps=None, wts=None, col_stats=None) -> SolveResult:
+                      eps=None, wts=None, col_stats=None, sj_near=None) -> SolveResult:
         """Solve the listed columns (None = all).  rho/pi/eps/wts/col_stats are
         optional torch device tensors (float64 / int32) written by the library."""
         if cols is None:
@@ -271,7 +335,7 @@ class Context:
             cptr, n = _ptr(cols), len(cols)
         o = opts if opts is not None else default_opts()
         res = _Result(_ptr(rho), _ptr(pi), _ptr(eps), _ptr(wts), _ptr(col_stats), 0.0, 0.0, 0.0,
-                      0.0, 0.0)
+                      0.0, 0.0, _ptr(sj_near))
         self._check(self._lib.ma_solve_columns(self._h, n, cptr, int(p), int(q), float(mu),
                                                float(kT), ctypes.byref(o), ctypes.byref(res)))
         return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, res.kernel_ms)

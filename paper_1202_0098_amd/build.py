@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmarnoldi.so")
-SOURCES = ["ma_kernels.hip", "ma_host.cpp"]
+SOURCES = ["ma_kernels.hip", "ma_mlp.hip", "ma_host.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

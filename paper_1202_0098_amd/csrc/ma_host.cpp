@@ -86,6 +86,16 @@ struct ma_ctx {
     hipEvent_t evu = nullptr;         // orders `own` after the caller's null stream
     // the stream the solve path enqueues on (the null stream cannot be captured)
     hipStream_t work_stream() const { return stream ? stream : own; }
+    // Order the library's stream after the work already queued on the
+    // caller's stream (needed whenever they differ: the caller's device
+    // arrays may still be being written there).
+    hipError_t after_caller()
+    {
+        if (stream) return hipSuccess;
+        hipError_t e = hipEventRecord(evu, nullptr);
+        if (e == hipSuccess) e = hipStreamWaitEvent(own, evu, 0);
+        return e;
+    }
     std::string err = "no error";
     int cu_count = 0;
     bool built = false;
@@ -100,6 +110,19 @@ struct ma_ctx {
     // device system
     DevBuf blk_ptr, blk_col, Hd, Sd, Hf, Sf, reg_id, reg_off, reg_len, lrp_off, lrp, lblk, jloc,
         blk_loc;
+    bool have_geo = false;            // neighbour descriptors were built
+    DevBuf geo, out_loc;              // n_atoms * kGeoFeat floats; n_atoms * kNbOut ints
+
+    // start network: FP32 parameters, Adam moments, BF16 transposed weights,
+    // training workspace
+    struct Model {
+        bool ready = false, bf16_dirty = true;
+        int nf = 0, nh = 0, no = 0, nf_pad = 0, no_pad = 0, step = 0;
+        int64_t P = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+        DevBuf params, grad, m, v, W1t, W2t, W3t;
+        DevBuf Xb, Tb, Z1, A1, Z2, A2, Yb, dY, dA, partial;
+    } net;
+    DevBuf feat, x0;                  // per-solve descriptors and predicted starts
 
     // device solve buffers
     DevBuf cols, order, qbounds, ws, eps, wts, amp, stats, ctl, lohi, partial, Ecol, Ncol, sums;
@@ -109,6 +132,7 @@ struct ma_ctx {
     // captured launch sequence and the configuration it was captured for
     hipGraphExec_t gexec = nullptr;   // the column kernel
     hipGraphExec_t gexec2 = nullptr;  // bisection, Fermi weighting, reductions
+    hipGraphExec_t gexec0 = nullptr;  // descriptors and start network (learned start)
     std::vector<unsigned char> gkey;
 
     // autotuned (slots per CU, schedule) per (p, q, precision)
@@ -124,7 +148,8 @@ struct ma_ctx {
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (gexec2) (void)hipGraphExecDestroy(gexec2);
-        gexec = gexec2 = nullptr;
+        if (gexec0) (void)hipGraphExecDestroy(gexec0);
+        gexec = gexec2 = gexec0 = nullptr;
         gkey.clear();
     }
 
@@ -165,6 +190,7 @@ struct ma_ctx {
         S.lblk = lblk.as<int2>();
         S.jloc = jloc.as<int32_t>();
         S.blk_loc = blk_loc.as<int32_t>();
+        S.out_loc = out_loc.as<int32_t>();
         return S;
     }
 };
@@ -600,6 +626,65 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
         return ctx->fail(MA_EINVAL, "region dimension %d exceeds the supported %d", nmax,
                          8 * ma::kThreads);
 
+    // ---- neighbour descriptors for the start network ----
+    // For each atom: its kNbDesc nearest other atoms (by squared minimum-image
+    // distance, then index) as (|d|/5, d/|d|), and the local positions, in its
+    // own region, of its kNbOut nearest atoms (itself first).
+    std::vector<float> h_geo;
+    std::vector<int32_t> h_out_loc;
+    const bool have_geo = sys->xyz != nullptr;
+    if (have_geo) {
+        const double *xyz = sys->xyz, *box = sys->box;
+        h_geo.assign((size_t)n * ma::kGeoFeat, 0.0f);
+        h_out_loc.assign((size_t)n * ma::kNbOut, -1);
+        double lo3[3], hi3[3], vol = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            lo3[d] = 1e300;
+            hi3[d] = -1e300;
+            for (int a = 0; a < n; ++a) {
+                lo3[d] = std::min(lo3[d], xyz[3 * a + d]);
+                hi3[d] = std::max(hi3[d], xyz[3 * a + d]);
+            }
+            vol *= box ? box[d] : std::max(1.0, hi3[d] - lo3[d]);
+        }
+        const int want = std::min(n, ma::kNbDesc + 1);
+        const double r0 = std::cbrt(3.0 * want / (4.0 * M_PI * (n / vol))) * 1.3 + 1e-9;
+        CellGrid G;
+        G.build(n, xyz, box, r0 * 0.5);
+        parallel_for(n, [&](int64_t a0, int64_t a1, int t) {
+            std::vector<std::pair<double, int32_t>> cand;
+            std::vector<int32_t> &loc = locs[t];
+            for (int64_t a = a0; a < a1; ++a) {
+                double r = r0;
+                for (;;) {
+                    gather_within(G, xyz, box, n, (int)a, r, cand);
+                    if ((int)cand.size() >= want) break;
+                    r *= 1.25;
+                }
+                std::partial_sort(cand.begin(), cand.begin() + want, cand.end());
+                // rank 0 is the atom itself (distance 0)
+                for (int k = 1; k < want && k <= ma::kNbDesc; ++k) {
+                    const int b = cand[k].second;
+                    double dv[3];
+                    for (int d = 0; d < 3; ++d) {
+                        double v = xyz[3 * b + d] - xyz[3 * a + d];
+                        if (box) v = v - box[d] * std::nearbyint(v / box[d]);
+                        dv[d] = v;
+                    }
+                    const double dist = std::sqrt(cand[k].first);
+                    float *f = h_geo.data() + (size_t)a * ma::kGeoFeat + 4 * (k - 1);
+                    f[0] = (float)(dist / 5.0);
+                    for (int d = 0; d < 3; ++d) f[1 + d] = dist > 0 ? (float)(dv[d] / dist) : 0.0f;
+                }
+                const auto &L = lists[shared ? 0 : a];
+                for (size_t i = 0; i < L.size(); ++i) loc[L[i]] = (int32_t)i;
+                for (int k = 0; k < ma::kNbOut && k < want; ++k)
+                    h_out_loc[(size_t)a * ma::kNbOut + k] = loc[cand[k].second];
+                for (int32_t b : L) loc[b] = -1;
+            }
+        });
+    }
+
     // ---- upload ----
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     std::vector<float> Hf(nblk * oo), Sf(nblk * oo);
@@ -634,8 +719,14 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     count_ = (int64_t)h_lblk.size(); UP(lblk, h_lblk.data(), "lblk")
     count_ = n;           UP(jloc, h_jloc.data(), "jloc")
     count_ = nblk;        UP(blk_loc, h_blk_loc.data(), "blk_loc")
+    if (have_geo) {
+        count_ = (int64_t)h_geo.size();     UP(geo, h_geo.data(), "descriptors")
+        count_ = (int64_t)h_out_loc.size(); UP(out_loc, h_out_loc.data(), "neighbours")
+    }
 #undef UP
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "upload");
+    ctx->have_geo = have_geo;
+    if (ctx->net.ready && ctx->o != o) ctx->net.ready = false;   // shape changed
     ctx->o = o;
     ctx->n_atoms = n;
     ctx->nblk = nblk;
@@ -699,8 +790,8 @@ struct Plan {
 
 ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, int32_t q,
                     double mu, double kT, const ma_opts *opts_in, double *rho, double *pi,
-                    double *eps, double *wts, int32_t *col_stats, int slots_override,
-                    int sched_override, Plan &P)
+                    double *eps, double *wts, int32_t *col_stats, float *sj_near,
+                    int slots_override, int sched_override, Plan &P)
 {
     if (!ctx->built) return ctx->fail(MA_ESTATE, "ma_build_system has not succeeded");
     ma_default_opts(&P.opts);
@@ -715,7 +806,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         return ctx->fail(MA_EINVAL, "unknown precision %d", opts.precision);
     if (!(opts.cg_tol > 0) || !(opts.breakdown_tau >= 0) || !(opts.inner_tol > 0) || opts.max_refine < 0)
         return ctx->fail(MA_EINVAL, "invalid tolerances");
-    if (opts.start == MA_START_LEARNED) return ctx->fail(MA_EINVAL, "no start model is set");
+    if (opts.start != MA_START_ZERO && opts.start != MA_START_LEARNED)
+        return ctx->fail(MA_EINVAL, "unknown start %d", opts.start);
+    if (opts.start == MA_START_LEARNED && !(ctx->net.ready && ctx->have_geo))
+        return ctx->fail(MA_EINVAL, "learned start needs a start model and positions");
     if (opts.schedule < -1 || opts.schedule > MA_SCHED_XCD_LPT)
         return ctx->fail(MA_EINVAL, "unknown schedule %d", opts.schedule);
     if (cols == nullptr) ncols = ctx->M;
@@ -789,7 +883,11 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
     HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
     HIPCHK(ctx, ctx->amp.reserve(sizeof(double) * (size_t)ncols * ctx->maxpat * P.nu), "amplitudes");
-    HIPCHK(ctx, ctx->stats.reserve(sizeof(int32_t) * (size_t)ncols * 4), "stats");
+    HIPCHK(ctx, ctx->stats.reserve(sizeof(int32_t) * (size_t)ncols * ma::kStats), "stats");
+    if (opts.start == MA_START_LEARNED) {
+        HIPCHK(ctx, ctx->feat.reserve(sizeof(float) * (size_t)ncols * ctx->net.nf), "descriptors");
+        HIPCHK(ctx, ctx->x0.reserve(sizeof(float) * (size_t)ncols * ctx->net.no), "start vectors");
+    }
     HIPCHK(ctx, ctx->ctl.reserve(sizeof(int) * 16), "ctl");
     HIPCHK(ctx, ctx->lohi.reserve(sizeof(double) * 2), "lohi");
     HIPCHK(ctx, ctx->partial.reserve(sizeof(double) * ma::kCountBlocks * ma::kBisectTrials), "partial");
@@ -797,10 +895,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, ctx->Ncol.reserve(sizeof(double) * ncols), "Ncol");
     HIPCHK(ctx, ctx->sums.reserve(sizeof(double) * 2), "sums");
     hipStream_t st = ctx->work_stream();
-    if (!ctx->stream) {
-        HIPCHK(ctx, hipEventRecord(ctx->evu, nullptr), "event");
-        HIPCHK(ctx, hipStreamWaitEvent(st, ctx->evu, 0), "stream wait");
-    }
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
     HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, P.hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
     HIPCHK(ctx, hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "order");
     HIPCHK(ctx, hipMemcpyAsync(ctx->qbounds.p, qb.data(), sizeof(int32_t) * qb.size(), hipMemcpyHostToDevice, st), "queues");
@@ -817,7 +912,9 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     J.wts = wts ? wts : ctx->wts.as<double>();
     J.amp = ctx->amp.as<double>();
     J.stats = col_stats ? col_stats : ctx->stats.as<int32_t>();
-    J.x0 = nullptr;
+    J.x0 = opts.start == MA_START_LEARNED ? ctx->x0.as<float>() : nullptr;
+    J.sj_near = sj_near;
+    if (sj_near && !ctx->have_geo) return ctx->fail(MA_EINVAL, "sj_near needs positions");
     return MA_OK;
 }
 
@@ -827,6 +924,23 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
 hipError_t enqueue_solve(ma_ctx *ctx, const Plan &P)
 {
     return ma::launch_solve(P.S, P.J, P.slots, ctx->work_stream());
+}
+
+hipError_t net_refresh_bf16(ma_ctx *ctx, hipStream_t st);
+
+hipError_t enqueue_pre(ma_ctx *ctx, const Plan &P)
+{
+    hipStream_t st = ctx->work_stream();
+    auto &N = ctx->net;
+    hipError_t e = ma::launch_features(P.J.cols, P.J.ncols, ctx->o, ctx->geo.as<float>(),
+                                       ma::kGeoFeat, N.nf, ctx->feat.as<float>(), st);
+    if (e != hipSuccess) return e;
+    if ((e = net_refresh_bf16(ctx, st)) != hipSuccess) return e;
+    const float *pr = N.params.as<float>();
+    return ma::launch_mlp_infer(ctx->feat.as<float>(), P.J.ncols, N.nf, N.nf_pad, N.nh, N.no,
+                                N.W1t.as<unsigned short>(), pr + N.ob1, N.W2t.as<unsigned short>(),
+                                pr + N.ob2, N.W3t.as<unsigned short>(), pr + N.ob3,
+                                ctx->x0.as<float>(), st);
 }
 
 hipError_t enqueue_post(ma_ctx *ctx, const Plan &P)
@@ -894,6 +1008,7 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
             ctx->drop_graph();
             hipError_t e = capture(ctx, P, enqueue_solve, &ctx->gexec);
             if (e == hipSuccess) e = capture(ctx, P, enqueue_post, &ctx->gexec2);
+            if (e == hipSuccess && P.J.x0) e = capture(ctx, P, enqueue_pre, &ctx->gexec0);
             if (e != hipSuccess) {
                 ctx->drop_graph();
                 return ctx->hip_fail(e, "graph capture");
@@ -903,6 +1018,10 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
     }
     // ev0 .. ev1 brackets the whole solve, evk0 .. evk1 the column kernel
     HIPCHK(ctx, hipEventRecord(ctx->ev0, st), "event");
+    if (P.J.x0) {
+        if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec0, st), "graph launch");
+        else HIPCHK(ctx, enqueue_pre(ctx, P), "start network");
+    }
     HIPCHK(ctx, ma::launch_reset(P.J.queue, P.J.fail, st), "reset");
     HIPCHK(ctx, hipEventRecord(ctx->evk0, st), "event");
     if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, st), "graph launch");
@@ -928,7 +1047,7 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
     const int failc = ctl[ma::kMaxQueues];
     if (failc != INT_MAX) {
         int32_t st4[4] = {0, 0, 0, 0};
-        HIPCHK(ctx, hipMemcpy(st4, P.J.stats + (int64_t)failc * 4, sizeof st4, hipMemcpyDeviceToHost), "copy");
+        HIPCHK(ctx, hipMemcpy(st4, P.J.stats + (int64_t)failc * ma::kStats, sizeof st4, hipMemcpyDeviceToHost), "copy");
         const ma_status s = st4[3] == -4 ? MA_ENOTPD : MA_ENOCONV;
         return ctx->fail(s, "column %d (output row %d): %s after %d CG iterations", P.hcols[failc],
                          failc, s == MA_ENOTPD ? "S_A not positive definite" : "CG did not converge",
@@ -950,7 +1069,7 @@ MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *col
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     Plan P;
     ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, opts_in, out->rho, out->pi, out->eps,
-                            out->wts, out->col_stats, 0, -1, P);
+                            out->wts, out->col_stats, out->sj_near, 0, -1, P);
     if (s != MA_OK) return s;
     return run_plan(ctx, P, out);
 }
@@ -986,7 +1105,7 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     // occupancy limit of this shape
     Plan P0;
     ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
-                            nullptr, 1 << 20, MA_SCHED_LPT, P0);
+                            nullptr, nullptr, 1 << 20, MA_SCHED_LPT, P0);
     if (s != MA_OK) return s;
     const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
     std::memset(out, 0, sizeof(*out));
@@ -995,7 +1114,7 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
         for (int bpc = 1; bpc <= max_bpc && out->n_tried < 64; ++bpc) {
             Plan P;
             s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, bpc, sched, P);
+                          nullptr, nullptr, bpc, sched, P);
             if (s != MA_OK) return s;
             double best = INFINITY;
             for (int r = 0; r < reps; ++r) {
@@ -1015,6 +1134,288 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
             }
         }
     return ma_set_tuning(ctx, p, q, o.precision, out->slots_per_cu, out->schedule);
+}
+
+}  // extern "C"
+
+namespace {
+
+ma_status net_shape(ma_ctx *ctx)
+{
+    auto &N = ctx->net;
+    N.nf = ma::kGeoFeat + ctx->o;
+    N.nh = ma::kHidden;
+    N.no = ma::kNbOut * ctx->o;
+    N.nf_pad = (N.nf + 15) / 16 * 16;
+    N.no_pad = (N.no + 15) / 16 * 16;
+    N.oW1 = 0;
+    N.ob1 = N.oW1 + (int64_t)N.nf * N.nh;
+    N.oW2 = N.ob1 + N.nh;
+    N.ob2 = N.oW2 + (int64_t)N.nh * N.nh;
+    N.oW3 = N.ob2 + N.nh;
+    N.ob3 = N.oW3 + (int64_t)N.nh * N.no;
+    N.P = N.ob3 + N.no;
+    HIPCHK(ctx, N.params.reserve(sizeof(float) * N.P), "network");
+    HIPCHK(ctx, N.grad.reserve(sizeof(float) * N.P), "network");
+    HIPCHK(ctx, N.m.reserve(sizeof(float) * N.P), "network");
+    HIPCHK(ctx, N.v.reserve(sizeof(float) * N.P), "network");
+    HIPCHK(ctx, N.W1t.reserve(sizeof(unsigned short) * (size_t)N.nh * N.nf_pad), "network");
+    HIPCHK(ctx, N.W2t.reserve(sizeof(unsigned short) * (size_t)N.nh * N.nh), "network");
+    HIPCHK(ctx, N.W3t.reserve(sizeof(unsigned short) * (size_t)N.no_pad * N.nh), "network");
+    return MA_OK;
+}
+
+hipError_t net_refresh_bf16(ma_ctx *ctx, hipStream_t st)
+{
+    auto &N = ctx->net;
+    const float *p = N.params.as<float>();
+    hipError_t e = ma::launch_to_bf16_t(p + N.oW1, N.nf, N.nh, N.nf_pad, N.nh, N.W1t.as<unsigned short>(), st);
+    if (e == hipSuccess) e = ma::launch_to_bf16_t(p + N.oW2, N.nh, N.nh, N.nh, N.nh, N.W2t.as<unsigned short>(), st);
+    if (e == hipSuccess) e = ma::launch_to_bf16_t(p + N.oW3, N.nh, N.no, N.nh, N.no_pad, N.W3t.as<unsigned short>(), st);
+    return e;
+}
+
+ma_status net_workspace(ma_ctx *ctx, int64_t n)
+{
+    auto &N = ctx->net;
+    HIPCHK(ctx, N.Xb.reserve(sizeof(float) * (size_t)n * N.nf), "training workspace");
+    HIPCHK(ctx, N.Tb.reserve(sizeof(float) * (size_t)n * N.no), "training workspace");
+    HIPCHK(ctx, N.Z1.reserve(sizeof(float) * (size_t)n * N.nh), "training workspace");
+    HIPCHK(ctx, N.A1.reserve(sizeof(float) * (size_t)n * N.nh), "training workspace");
+    HIPCHK(ctx, N.Z2.reserve(sizeof(float) * (size_t)n * N.nh), "training workspace");
+    HIPCHK(ctx, N.A2.reserve(sizeof(float) * (size_t)n * N.nh), "training workspace");
+    HIPCHK(ctx, N.Yb.reserve(sizeof(float) * (size_t)n * N.no), "training workspace");
+    HIPCHK(ctx, N.dY.reserve(sizeof(float) * (size_t)n * N.no), "training workspace");
+    HIPCHK(ctx, N.dA.reserve(sizeof(float) * (size_t)n * N.nh), "training workspace");
+    HIPCHK(ctx, N.partial.reserve(sizeof(double) * 256), "training workspace");
+    return MA_OK;
+}
+
+// FP32 forward for n rows of x into y (activations kept for the backward pass).
+hipError_t net_forward_f32(ma_ctx *ctx, const float *x, int64_t n, float *y, hipStream_t st)
+{
+    auto &N = ctx->net;
+    const float *p = N.params.as<float>();
+    hipError_t e = ma::launch_gemm((int)n, N.nh, N.nf, x, N.nf, 1, nullptr, p + N.oW1, N.nh, 1,
+                                   p + N.ob1, 0.f, N.A1.as<float>(), N.nh, N.Z1.as<float>(), st);
+    if (e == hipSuccess)
+        e = ma::launch_gemm((int)n, N.nh, N.nh, N.A1.as<float>(), N.nh, 1, nullptr, p + N.oW2, N.nh, 1,
+                            p + N.ob2, 0.f, N.A2.as<float>(), N.nh, N.Z2.as<float>(), st);
+    if (e == hipSuccess)
+        e = ma::launch_gemm((int)n, N.no, N.nh, N.A2.as<float>(), N.nh, 1, nullptr, p + N.oW3, N.no, 1,
+                            p + N.ob3, 0.f, y, N.no, nullptr, st);
+    return e;
+}
+
+// Loss and gradient of the mean squared error on n rows; optional Adam step.
+ma_status net_train_core(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx, int64_t n,
+                         bool update, float lr, double *loss, float *grad_host)
+{
+    auto &N = ctx->net;
+    if (!N.ready) return ctx->fail(MA_ESTATE, "no start network (ma_mlp_init or ma_mlp_set_params)");
+    if (!x || !t || n < 1 || n > INT_MAX) return ctx->fail(MA_EINVAL, "invalid training batch");
+    ma_status s = net_workspace(ctx, n);
+    if (s != MA_OK) return s;
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    const float *X = x, *T = t;
+    if (idx) {
+        HIPCHK(ctx, ma::launch_gather_rows(x, idx, n, N.nf, N.Xb.as<float>(), st), "gather");
+        HIPCHK(ctx, ma::launch_gather_rows(t, idx, n, N.no, N.Tb.as<float>(), st), "gather");
+        X = N.Xb.as<float>();
+        T = N.Tb.as<float>();
+    }
+    float *p = N.params.as<float>(), *g = N.grad.as<float>();
+    const int nn = (int)n;
+    HIPCHK(ctx, net_forward_f32(ctx, X, n, N.Yb.as<float>(), st), "forward");
+    HIPCHK(ctx, ma::launch_mse(N.Yb.as<float>(), T, nullptr, n, N.no, N.dY.as<float>(),
+                               N.partial.as<double>(), 256, st), "loss");
+    // layer 3
+    HIPCHK(ctx, ma::launch_gemm(N.nh, N.no, nn, N.A2.as<float>(), 1, N.nh, nullptr, N.dY.as<float>(),
+                                N.no, 1, nullptr, 0.f, g + N.oW3, N.no, nullptr, st), "backward");
+    HIPCHK(ctx, ma::launch_colsum(N.dY.as<float>(), n, N.no, g + N.ob3, st), "backward");
+    HIPCHK(ctx, ma::launch_gemm(nn, N.nh, N.no, N.dY.as<float>(), N.no, 1, nullptr, p + N.oW3, 1, N.no,
+                                nullptr, 0.f, N.dA.as<float>(), N.nh, nullptr, st), "backward");
+    // layer 2
+    HIPCHK(ctx, ma::launch_silu_bwd(N.dA.as<float>(), N.Z2.as<float>(), n * N.nh, st), "backward");
+    HIPCHK(ctx, ma::launch_gemm(N.nh, N.nh, nn, N.A1.as<float>(), 1, N.nh, nullptr, N.dA.as<float>(),
+                                N.nh, 1, nullptr, 0.f, g + N.oW2, N.nh, nullptr, st), "backward");
+    HIPCHK(ctx, ma::launch_colsum(N.dA.as<float>(), n, N.nh, g + N.ob2, st), "backward");
+    float *dA1 = N.Z2.as<float>();   // Z2 is no longer needed
+    HIPCHK(ctx, ma::launch_gemm(nn, N.nh, N.nh, N.dA.as<float>(), N.nh, 1, nullptr, p + N.oW2, 1, N.nh,
+                                nullptr, 0.f, dA1, N.nh, nullptr, st), "backward");
+    // layer 1
+    HIPCHK(ctx, ma::launch_silu_bwd(dA1, N.Z1.as<float>(), n * N.nh, st), "backward");
+    HIPCHK(ctx, ma::launch_gemm(N.nf, N.nh, nn, X, 1, N.nf, nullptr, dA1, N.nh, 1, nullptr, 0.f,
+                                g + N.oW1, N.nh, nullptr, st), "backward");
+    HIPCHK(ctx, ma::launch_colsum(dA1, n, N.nh, g + N.ob1, st), "backward");
+    if (update) {
+        N.step += 1;
+        HIPCHK(ctx, ma::launch_adam(p, g, N.m.as<float>(), N.v.as<float>(), N.P, lr, 0.9f, 0.999f,
+                                    1e-8f, N.step, st), "adam");
+        N.bf16_dirty = true;
+    }
+    double part[256];
+    HIPCHK(ctx, hipMemcpyAsync(part, N.partial.p, sizeof part, hipMemcpyDeviceToHost, st), "copy");
+    if (grad_host)
+        HIPCHK(ctx, hipMemcpyAsync(grad_host, g, sizeof(float) * N.P, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipStreamSynchronize(st), "training step");
+    if (loss) {
+        double sum = 0.0;
+        for (int b = 0; b < 256; ++b) sum += part[b];
+        *loss = sum / ((double)n * N.no);
+    }
+    return MA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+MA_API ma_status ma_mlp_shape_of(const ma_ctx *ctx, ma_mlp_shape *out)
+{
+    if (!ctx || !out) return MA_EINVAL;
+    if (!ctx->built) return MA_ESTATE;
+    out->n_in = ma::kGeoFeat + ctx->o;
+    out->n_hidden = ma::kHidden;
+    out->n_out = ma::kNbOut * ctx->o;
+    out->n_params = (int64_t)out->n_in * out->n_hidden + out->n_hidden +
+                    (int64_t)out->n_hidden * out->n_hidden + out->n_hidden +
+                    (int64_t)out->n_hidden * out->n_out + out->n_out;
+    return MA_OK;
+}
+
+MA_API ma_status ma_mlp_init(ma_ctx *ctx, uint64_t seed)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built) return ctx->fail(MA_ESTATE, "build a system first (the network's shape follows o)");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ma_status s = net_shape(ctx);
+    if (s != MA_OK) return s;
+    auto &N = ctx->net;
+    std::vector<float> h(N.P, 0.0f);
+    // splitmix64 stream -> Box-Muller normals
+    uint64_t state = seed;
+    auto next = [&]() {
+        uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int64_t off, int64_t count, double sd) {
+        for (int64_t i = 0; i < count; ++i) {
+            const double u1 = next(), u2 = next();
+            h[off + i] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2));
+        }
+    };
+    fill(N.oW1, (int64_t)N.nf * N.nh, std::sqrt(2.0 / N.nf));
+    fill(N.oW2, (int64_t)N.nh * N.nh, std::sqrt(2.0 / N.nh));
+    fill(N.oW3, (int64_t)N.nh * N.no, std::sqrt(1.0 / N.nh));
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, hipMemcpyAsync(N.params.p, h.data(), sizeof(float) * N.P, hipMemcpyHostToDevice, st), "upload");
+    std::vector<float> z(N.P, 0.0f);
+    HIPCHK(ctx, hipMemcpyAsync(N.m.p, z.data(), sizeof(float) * N.P, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(ctx, hipMemcpyAsync(N.v.p, z.data(), sizeof(float) * N.P, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(ctx, hipStreamSynchronize(st), "upload");
+    N.step = 0;
+    N.ready = true;
+    N.bf16_dirty = true;
+    ctx->drop_graph();
+    return MA_OK;
+}
+
+MA_API ma_status ma_mlp_set_params(ma_ctx *ctx, const float *params, int64_t count)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built) return ctx->fail(MA_ESTATE, "build a system first");
+    ma_status s = net_shape(ctx);
+    if (s != MA_OK) return s;
+    auto &N = ctx->net;
+    if (!params || count != N.P) return ctx->fail(MA_EINVAL, "expected %lld parameters", (long long)N.P);
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(params[i])) return ctx->fail(MA_EINVAL, "non-finite parameter %lld", (long long)i);
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, hipMemcpyAsync(N.params.p, params, sizeof(float) * N.P, hipMemcpyHostToDevice, st), "upload");
+    std::vector<float> z(N.P, 0.0f);
+    HIPCHK(ctx, hipMemcpyAsync(N.m.p, z.data(), sizeof(float) * N.P, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(ctx, hipMemcpyAsync(N.v.p, z.data(), sizeof(float) * N.P, hipMemcpyHostToDevice, st), "upload");
+    HIPCHK(ctx, hipStreamSynchronize(st), "upload");
+    N.step = 0;
+    N.ready = true;
+    N.bf16_dirty = true;
+    return MA_OK;
+}
+
+MA_API ma_status ma_mlp_get_params(const ma_ctx *ctx, float *params, int64_t count)
+{
+    if (!ctx) return MA_EINVAL;
+    const auto &N = ctx->net;
+    if (!N.ready) return MA_ESTATE;
+    if (!params || count != N.P) return MA_EINVAL;
+    if (hipMemcpy(params, N.params.p, sizeof(float) * N.P, hipMemcpyDeviceToHost) != hipSuccess)
+        return MA_EDEVICE;
+    return MA_OK;
+}
+
+MA_API ma_status ma_column_features(ma_ctx *ctx, int64_t ncols, const int32_t *cols, float *feat)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built || !ctx->have_geo) return ctx->fail(MA_ESTATE, "no system with positions");
+    if (!cols || !feat || ncols < 1 || ncols > INT_MAX) return ctx->fail(MA_EINVAL, "invalid arguments");
+    for (int64_t c = 0; c < ncols; ++c)
+        if (cols[c] < 0 || cols[c] >= ctx->M) return ctx->fail(MA_EINVAL, "column out of range");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    HIPCHK(ctx, ctx->cols.reserve(sizeof(int32_t) * ncols), "cols");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, cols, sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
+    HIPCHK(ctx, ma::launch_features(ctx->cols.as<int32_t>(), (int)ncols, ctx->o, ctx->geo.as<float>(),
+                                    ma::kGeoFeat, ma::kGeoFeat + ctx->o, feat, st), "descriptors");
+    HIPCHK(ctx, hipStreamSynchronize(st), "descriptors");
+    ctx->drop_graph();   // the column buffer of a captured solve was rewritten
+    return MA_OK;
+}
+
+MA_API ma_status ma_mlp_forward(ma_ctx *ctx, const float *x, int64_t n, float *y, int32_t bf16)
+{
+    if (!ctx) return MA_EINVAL;
+    auto &N = ctx->net;
+    if (!N.ready) return ctx->fail(MA_ESTATE, "no start network");
+    if (!x || !y || n < 1 || n > INT_MAX) return ctx->fail(MA_EINVAL, "invalid arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    if (bf16) {
+        HIPCHK(ctx, net_refresh_bf16(ctx, st), "bf16 weights");
+        const float *p = N.params.as<float>();
+        HIPCHK(ctx, ma::launch_mlp_infer(x, n, N.nf, N.nf_pad, N.nh, N.no, N.W1t.as<unsigned short>(),
+                                         p + N.ob1, N.W2t.as<unsigned short>(), p + N.ob2,
+                                         N.W3t.as<unsigned short>(), p + N.ob3, y, st), "inference");
+    } else {
+        ma_status s = net_workspace(ctx, n);
+        if (s != MA_OK) return s;
+        HIPCHK(ctx, net_forward_f32(ctx, x, n, y, st), "forward");
+    }
+    HIPCHK(ctx, hipStreamSynchronize(st), "forward");
+    return MA_OK;
+}
+
+MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
+                                  int64_t n, double *loss, float *grad)
+{
+    if (!ctx) return MA_EINVAL;
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return net_train_core(ctx, x, t, idx, n, false, 0.0f, loss, grad);
+}
+
+MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
+                                   int64_t n, float lr, double *loss)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!(lr > 0)) return ctx->fail(MA_EINVAL, "lr must be positive");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return net_train_core(ctx, x, t, idx, n, true, lr, loss, nullptr);
 }
 
 }  // extern "C"

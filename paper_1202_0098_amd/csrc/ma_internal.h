@@ -13,6 +13,10 @@ constexpr int kMaxNu = 64;
 constexpr int kBisectTrials = 63;        // trial potentials per bisection pass
 constexpr int kBisectPasses = 9;         // 64^9 narrows any bracket below 1e-15
 constexpr int kCountBlocks = 256;        // fixed grid of the electron-count kernel
+constexpr int kNbDesc = 48;              // neighbours in a column descriptor
+constexpr int kNbOut = 12;               // atoms whose s_j coefficients the network predicts
+constexpr int kGeoFeat = 4 * kNbDesc;    // (d/5, dx/d, dy/d, dz/d) per neighbour
+constexpr int kHidden = 256;             // hidden width of the start network
 
 // Device view of a built system.
 struct DevSystem {
@@ -37,6 +41,8 @@ struct DevSystem {
     const int32_t *jloc;       // local position of atom A inside its region
     const int32_t *blk_loc;    // per global block: local position of its column atom
                                // inside the region of its row atom
+    const int32_t *out_loc;    // n_atoms * kNbOut: local position (in the atom's own
+                               // region) of its kNbOut nearest atoms, -1 if outside
 };
 
 // One solve.
@@ -58,9 +64,14 @@ struct DevJob {
     double *eps;               // ncols * nu
     double *wts;               // ncols * nu
     double *amp;               // ncols * maxpat * nu: v_ia v_ja at pattern rows
-    int32_t *stats;            // ncols * 4
-    const float *x0;           // optional CG start vectors (ncols * nmax), local numbering
+    int32_t *stats;            // ncols * kStats
+    const float *x0;           // optional: predicted s_j on the kNbOut nearest atoms
+                               // (ncols * kNbOut * o), else zero start
+    float *sj_near;            // optional output: converged s_j on the same orbitals
 };
+
+constexpr int kStats = 8;      // nu_eff, CG iterations, FP64 residual evaluations, status,
+                               // start used (0 zero, 1 learned, 2 learned rejected), 3 spare
 
 // Shared-memory bytes the column kernel needs.
 size_t solve_smem_bytes(int nmax, int nu);
@@ -82,5 +93,27 @@ hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr,
                       double kT, double *rho, double *pi, double *Ecol, double *Ncol,
                       hipStream_t st);
 hipError_t launch_sum2(const double *a, const double *b, int n, double *out, hipStream_t st);
+
+// Start network (ma_mlp.hip).
+hipError_t launch_features(const int32_t *cols, int ncols, int o, const float *geo, int nf_geo,
+                           int nf, float *feat, hipStream_t st);
+hipError_t launch_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, float *out,
+                              hipStream_t st);
+hipError_t launch_to_bf16_t(const float *W, int rows, int cols, int rows_pad, int cols_pad,
+                            unsigned short *Wt, hipStream_t st);
+size_t mlp_infer_smem(int nf_pad, int nh);
+hipError_t launch_mlp_infer(const float *X, int64_t n, int nf, int nf_pad, int nh, int no,
+                            const unsigned short *W1t, const float *b1, const unsigned short *W2t,
+                            const float *b2, const unsigned short *W3t, const float *b3, float *Y,
+                            hipStream_t st);
+hipError_t launch_gemm(int M, int N, int K, const float *A, int64_t sa0, int64_t sa1,
+                       const int32_t *gather, const float *B, int64_t sb0, int64_t sb1,
+                       const float *bias, float beta, float *C, int64_t ldc, float *Z, hipStream_t st);
+hipError_t launch_mse(const float *Y, const float *T, const int32_t *gather, int64_t n, int no,
+                      float *dY, double *partial, int nblocks, hipStream_t st);
+hipError_t launch_silu_bwd(float *G, const float *Z, int64_t total, hipStream_t st);
+hipError_t launch_colsum(const float *G, int64_t n, int m, float *db, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t st);
 
 }  // namespace ma

@@ -264,16 +264,28 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
 
     // ---------------- inner CG: S_A s = e_j ----------------
     double x[R];
-    int iters = 0, nres = 0, status = 0;
+    int iters = 0, nres = 0, status = 0, start = 0;
     bool converged = false;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) x[rr] = 0.0;
+    const int nout = kNbOut * o;
     if (J.x0) {
+        // predicted coefficients on the orbitals of the kNbOut nearest atoms
+        for (int i = tid; i < n; i += NT) sm.xa[i] = 0.0;
+        __syncthreads();
+        for (int e = tid; e < nout; e += NT) {
+            const int k = e / o, cc = e - k * o;
+            const int la = S.out_loc[(int64_t)g.A * kNbOut + k];
+            if (la >= 0) sm.xa[la * o + cc] = (double)J.x0[(int64_t)c * nout + e];
+        }
+        __syncthreads();
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int i = tid + rr * NT;
-            if (i < n) x[rr] = (double)J.x0[(int64_t)c * ld + i];
+            if (i < n) x[rr] = sm.xa[i];
         }
+        start = 1;
+        __syncthreads();
     }
     if (PREC == 0) {
         double r[R], p[R], q[R];
@@ -285,6 +297,16 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
         double rho2 = block_sum(dot_rows<R>(r, r, n), sm.red);
         ++nres;
+        if (start == 1 && !(rho2 < 1.0)) {
+            // the residual judge rejects the predicted start: zero start
+            start = 2;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                x[rr] = 0.0;
+                r[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+            }
+            rho2 = 1.0;
+        }
         for (int restart = 0; restart <= 3 && !converged && status == 0; ++restart) {
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) p[rr] = r[rr];
@@ -328,8 +350,18 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
             spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
-            const double rho2 = block_sum(dot_rows<R>(r64, r64, n), sm.red);
+            double rho2 = block_sum(dot_rows<R>(r64, r64, n), sm.red);
             ++nres;
+            if (ref == 0 && start == 1 && !(rho2 < 1.0)) {
+                // the residual judge rejects the predicted start: zero start
+                start = 2;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    x[rr] = 0.0;
+                    r64[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+                }
+                rho2 = 1.0;
+            }
             if (sqrt(rho2) <= J.cg_tol) { converged = true; break; }
             if (ref == J.max_refine) break;
             const double rho = sqrt(rho2);
@@ -379,6 +411,18 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         }
     }
     if (status == 0 && !converged) status = -5;
+    if (J.sj_near) {
+        // s_j on the orbitals of the kNbOut nearest atoms (training targets)
+        __syncthreads();
+        store_rows<R, double>(sm.xa, x, n);
+        __syncthreads();
+        for (int e = tid; e < nout; e += NT) {
+            const int k = e / o, cc = e - k * o;
+            const int la = S.out_loc[(int64_t)g.A * kNbOut + k];
+            J.sj_near[(int64_t)c * nout + e] = (status == 0 && la >= 0) ? (float)sm.xa[la * o + cc] : 0.0f;
+        }
+        __syncthreads();
+    }
 
     int L = 0;
     if (status == 0) {
@@ -741,11 +785,13 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         }
     }
     if (tid == 0) {
-        int32_t *st = J.stats + (int64_t)c * 4;
+        int32_t *st = J.stats + (int64_t)c * kStats;
         st[0] = L;
         st[1] = iters;
         st[2] = nres;
         st[3] = status;
+        st[4] = start;
+        st[5] = st[6] = st[7] = 0;
         if (status != 0) atomicMin(J.fail, c);
     }
     __syncthreads();
@@ -809,7 +855,7 @@ __global__ void __launch_bounds__(1024) k_minmax(const double *eps, const int32_
     double lo = INFINITY, hi = -INFINITY;
     for (int64_t e = threadIdx.x; e < (int64_t)ncols * nu; e += blockDim.x) {
         const int64_t c = e / nu;
-        if (e - c * nu < stats[c * 4]) {
+        if (e - c * nu < stats[c * kStats]) {
             lo = fmin(lo, eps[e]);
             hi = fmax(hi, eps[e]);
         }
@@ -852,7 +898,7 @@ __global__ void __launch_bounds__(256) k_count(const double *eps, const double *
     const int64_t e0 = blockIdx.x * chunk, e1 = min(total, e0 + chunk);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
         const int64_t c = e / nu;
-        if (e - c * nu >= stats[c * 4]) continue;
+        if (e - c * nu >= stats[c * kStats]) continue;
         const double ev = eps[e], w = wts[e];
 #pragma unroll
         for (int t = 0; t < KT_; ++t) {
@@ -906,7 +952,7 @@ __global__ void __launch_bounds__(128) k_rho(DevSystem S, DevJob J, const double
     for (int c = blockIdx.x; c < J.ncols; c += gridDim.x) {
         const int j = J.cols[c];
         const int A = j / o, r = j - A * o;
-        const int L = J.stats[(int64_t)c * 4];
+        const int L = J.stats[(int64_t)c * kStats];
         for (int a = threadIdx.x; a < nu; a += blockDim.x) {
             const double e = J.eps[(int64_t)c * nu + a];
             const double fa = a < L ? fermi((e - mu) / kT) : 0.0;

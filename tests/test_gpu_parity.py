@@ -57,13 +57,13 @@ def _gpu_solve(ctx, torch, s, cols, p, q, mu, kT, **opt):
     pi = torch.zeros_like(rho)
     eps = torch.zeros(ncols * nu, dtype=torch.float64, device="cuda")
     wts = torch.zeros_like(eps)
-    st = torch.zeros(ncols * 4, dtype=torch.int32, device="cuda")
+    st = torch.zeros(ncols * ma.STATS, dtype=torch.int32, device="cuda")
     res = ctx.solve_columns(cols, p, q, mu=mu, kT=kT, opts=ma.default_opts(**opt),
                             rho=rho, pi=pi, eps=eps, wts=wts, col_stats=st)
     torch.cuda.synchronize()
     return (res, rho.cpu().numpy().reshape(s.nblk, o, o), pi.cpu().numpy().reshape(s.nblk, o, o),
             eps.cpu().numpy().reshape(ncols, nu), wts.cpu().numpy().reshape(ncols, nu),
-            st.cpu().numpy().reshape(ncols, 4))
+            st.cpu().numpy().reshape(ncols, ma.STATS))
 
 
 def _compare(s, ora, cols, gpu, rho_tol, e_tol, mu_tol=1e-9):
@@ -137,6 +137,25 @@ def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda):
     _say(f"diamond4096 fp64 solve {len(cols)} sampled columns")
     gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT)
     ora = oracle.solve(s, cols=cols, mu=0.95)
+    _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
+
+
+def test_fp64_disordered_uneven_regions(ctx, torch_cuda):
+    """Disordered cell with per-atom region sizes 60..260 atoms (240..1,040
+    orbitals), p = q = 20: the largest and smallest regions and a random
+    sample."""
+    import oracle
+    s = synth.config_disordered8000(3001)
+    _say("disordered8000 build")
+    ctx.build_tb(s)
+    order = np.argsort(s.region_nrp, kind="stable")
+    atoms = np.concatenate([order[:8], order[-8:],
+                            np.random.default_rng(5).choice(s.n_atoms, 16, replace=False)])
+    cols = np.unique((atoms[:, None] * 4 + np.arange(4)[None, :]).ravel()).astype(np.int32)
+    _say(f"disordered8000 fp64 {len(cols)} columns, regions {s.region_nrp[atoms].min()}.."
+         f"{s.region_nrp[atoms].max()} atoms")
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.7, s.kT)
+    ora = oracle.solve(s, cols=cols, mu=0.7)
     _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
