@@ -56,8 +56,15 @@ def main():
     ap.add_argument("--workload", default="diamond4096")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_f64acc"])
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1024,
-                    help="columns of the oracle CPU baseline sample (0 = skip)")
+    ap.add_argument("--tuning", default="",
+                    help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE' instead of the autotuner")
+    ap.add_argument("--no-graph", action="store_true", help="launch without hipGraph replay")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run a plain device copy of MIB MiB five times "
+                         "(reference kernel for HBM byte counters)")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="columns of the oracle CPU baseline sample (0 = skip, -1 = whole "
+                         "workload up to 16,384 columns)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -82,9 +89,14 @@ def main():
     rho = torch.zeros(s.nblk * o * o, dtype=torch.float64, device=dev)
     pi = torch.zeros_like(rho)
     stats = torch.zeros(s.M * ma.STATS, dtype=torch.int32, device=dev)
-    opts = ma.default_opts(precision=args.precision)
+    opts = ma.default_opts(precision=args.precision, use_graph=0 if args.no_graph else 1)
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        slots, sched = args.tuning.split(",")
+        ctx.set_tuning(s.p, s.q, args.precision, int(slots), sched)
+        tuning = {"slots_per_cu": int(slots), "schedule": sched}
+        log(f"fixed tuning {tuning}")
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         first = ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
         tuning = ctx.autotune(None, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
@@ -113,29 +125,41 @@ def main():
     st = stats.cpu().numpy().reshape(s.M, ma.STATS)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {cols_per_s:.4g} columns/s; "
         f"nu_eff mean {st[:, 0].mean():.2f}, CG iters mean {st[:, 1].mean():.2f}")
+    if args.copy_calib > 0:
+        # a plain elementwise copy: reads and writes exactly MIB MiB per launch
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 launches of {args.copy_calib} MiB read + {args.copy_calib} MiB written")
+        del a, b
 
     # ---- roofline of the column kernel -------------------------------------
     k_ms = float(np.mean(kernel_ms))
     reg_atoms, loc_blocks = ctx.region_sizes(s.n_atoms)
     counts = kernel_model(s, st, reg_atoms, loc_blocks, args.precision)
-    achieved_tflops = counts["flops"] / (k_ms * 1e-3) / 1e12
+    achieved_gbs = counts["bytes"] / (k_ms * 1e-3) / 1e9
     roofline = {
-        "bound": "alu",
-        "achieved": round(achieved_tflops, 4),
-        "peak": PEAK_FP64_VECTOR_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_tflops / PEAK_FP64_VECTOR_TFLOPS, 5),
-        "traffic": None,
-        "kernel": "k_solve",
+        "bound": "hbm",
+        "achieved": round(achieved_gbs, 2),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved_gbs / PEAK_HBM_GBS, 5),
+        "traffic": measured_traffic(s.name, args.precision),
+        "algorithmic_bytes": round(counts["bytes"]),
+        "kernel": "column kernel",
         "kernel_ms": round(k_ms, 4),
-        "model_bytes_GBs": round(counts["bytes"] / (k_ms * 1e-3) / 1e9, 2),
+        "fp64_tflops": round(counts["flops"] / (k_ms * 1e-3) / 1e12, 4),
     }
 
     # ---- CPU baseline: the oracle on a bounded sample ----------------------
     cpu = None
-    if args.cpu_sample > 0:
+    sample = min(s.M, 16384) if args.cpu_sample < 0 else min(args.cpu_sample, s.M)
+    if sample > 0:
         import oracle
-        cols = np.sort(np.random.default_rng(12345).choice(s.M, min(args.cpu_sample, s.M),
+        cols = np.sort(np.random.default_rng(12345).choice(s.M, sample,
                                                            replace=False)).astype(np.int32)
         oracle.build()
         t0 = time.perf_counter()
@@ -163,7 +187,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": s.name, "atoms": s.n_atoms, "columns": s.M, "p": s.p, "q": s.q,
                    "kT": s.kT, "mu": "bisected at half filling", "precision": args.precision,
-                   "build_s": round(build_s, 3), "hipgraph": True,
+                   "build_s": round(build_s, 3), "hipgraph": not args.no_graph,
                    "tuning": None if tuning is None else {
                        "slots_per_cu": tuning["slots_per_cu"], "schedule": tuning["schedule"]}},
         "roofline": roofline,
@@ -172,30 +196,62 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def measured_traffic(workload_name, precision):
+    """HBM bytes per launch of the column kernel from the committed counter
+    summary of this workload and precision (FETCH_SIZE + WRITE_SIZE, scaled
+    by the same counters on a plain copy of known size), or None when there is
+    none or the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_solve_{workload_name}_{precision}_traffic.md")
+    src = os.path.join(ROOT, "paper_1202_0098_amd", "csrc", "ma_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel source sha256") != digest:
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def kernel_model(s, st, reg_atoms, loc_blocks, precision):
-    """Algorithmic flops and operator bytes of one column-kernel launch.
+    """Algorithmic bytes and flops of one column-kernel launch.
 
     Per column j with region dimension n = o * (atoms of the region), local
     operator blocks nb (o x o each), nu_eff = L accepted basis vectors and c
     operator applications in the CG (iterations plus FP64 residual checks):
-      operator applications  c (S) + 2 L (fused H and S on each candidate)
+      operator applications  a = c (S) + 2 L (H and S on each candidate)
                              + q (H on the chain vectors of block 2)
-      SpMV flops             2 o^2 nb per application
-      Gram-Schmidt, projection  ~ 6 n L^2 FP64 flops (two CGS passes, dots and
-                             updates, 4 n L^2 / 2 summed; H~ and S~ with both
-                             triangles, 4 n L^2 / 2)
-      operator bytes         nb (o^2 value bytes + 8 index bytes) per application
+      operator bytes         a * nb * (o^2 v + 4) / o: each application
+                             streams the region operator once (v = 8 bytes per
+                             FP64 value, 4 per FP32 value, 4 bytes of block
+                             index), shared by the o columns of the atom
+      compulsory outputs     Ritz values and weights (16 nu bytes) and the
+                             amplitudes at the pattern rows (8 or 4 bytes per
+                             row and Ritz vector)
+      flops                  2 o^2 nb per application, plus ~6 n L^2 FP64 flops
+                             of Gram-Schmidt and projection
     """
     o = s.n_orb
+    nu = s.p + s.q
     a = np.arange(s.M) // o
     L = st[:, 0].astype(float)
     c = st[:, 1].astype(float) + st[:, 2].astype(float)
     n = reg_atoms[a].astype(float) * o
     nb = loc_blocks[a].astype(float)
+    npat = np.diff(s.blk_ptr)[a].astype(float) * o
     apps = c + 2 * L + s.q
     flops = float(np.sum(2 * o * o * nb * apps + 6 * n * L * L))
-    vbytes = 4 if precision == "mixed" else 8
-    bytes_ = float(np.sum(apps * nb * (o * o * vbytes + 8)))
+    vbytes = 8 if precision == "fp64" else 4
+    bytes_ = float(np.sum(apps * nb * (o * o * vbytes + 4) / o + 16 * nu + npat * nu * vbytes))
     return {"flops": flops, "bytes": bytes_}
 
 
