@@ -71,6 +71,7 @@ typedef enum {
 enum { MA_REGION_ALL = 0, MA_REGION_RADIUS = 1, MA_REGION_NEAREST = 2 };
 enum { MA_PREC_FP64 = 0, MA_PREC_MIXED = 1, MA_PREC_MIXED_F64ACC = 2 };
 enum { MA_START_ZERO = 0, MA_START_LEARNED = 1 };
+enum { MA_BASIS_AUTO = 0, MA_BASIS_ONCHIP = 1, MA_BASIS_WORKSPACE = 2 };
 
 /* The pencil and its geometry.  All pointers are host memory owned by the
  * caller; ma_build_system copies what it needs. */
@@ -120,6 +121,14 @@ typedef struct {
                                value if available, else MA_SCHED_LPT */
     int32_t use_graph;      /* 1: capture the launch sequence in a hipGraph and replay it
                                while the configuration and buffers are unchanged */
+    int32_t basis_kernel;   /* MA_BASIS_AUTO: the on-chip basis kernel whenever every
+                               region has at most 512 orbitals, p + q <= 32 and
+                               q <= 16 (q <= 8 when p + q <= 16), else the workspace
+                               kernel; MA_BASIS_ONCHIP / MA_BASIS_WORKSPACE force one
+                               (MA_EINVAL if the on-chip kernel cannot hold the shape) */
+    int32_t chunk_columns;  /* columns per chunk of the processing order (0 = as many
+                               as a 4 GiB chunk buffer holds); a solve of several
+                               chunks launches eagerly instead of replaying graphs */
 } ma_opts;
 
 /* Schedules of the persistent column kernel.  LPT: one queue, columns with
@@ -146,12 +155,14 @@ typedef struct {
     double n_elec;          /* spin * sum_j N_j over the solved columns */
     double mu;              /* chemical potential used */
     double elapsed_ms;      /* device time of the whole solve on the stream */
-    double kernel_ms;       /* device time of the column kernel alone (HIP events
-                               around its launch on the same stream) */
+    double kernel_ms;       /* device time of the basis kernel alone (CG, basis,
+                               Galerkin pair; HIP events around its launches on the
+                               same stream, summed over column chunks) */
     float *sj_near;         /* device, ncols*12*o, optional: the converged s_j on the
                                orbitals of the 12 atoms nearest to atom(j), nearest
                                first (atom(j) itself first), the start network's
                                training target */
+    double eig_ms;          /* device time of the batched reduced-eigenproblem kernel */
 } ma_result;
 
 /* Result of ma_autotune. */

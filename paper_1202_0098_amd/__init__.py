@@ -56,7 +56,8 @@ class _Opts(ctypes.Structure):
                 ("breakdown_tau", ctypes.c_double), ("spin", ctypes.c_double),
                 ("n_target", ctypes.c_double), ("start", ctypes.c_int32),
                 ("slots_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("basis_kernel", ctypes.c_int32),
+                ("chunk_columns", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -67,6 +68,7 @@ class _Tuning(ctypes.Structure):
 
 
 SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
+BASIS_KERNELS = {"auto": 0, "onchip": 1, "workspace": 2}
 
 
 class _Result(ctypes.Structure):
@@ -74,7 +76,8 @@ class _Result(ctypes.Structure):
                 ("wts", ctypes.c_void_p), ("col_stats", ctypes.c_void_p),
                 ("energy", ctypes.c_double), ("n_elec", ctypes.c_double),
                 ("mu", ctypes.c_double), ("elapsed_ms", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double), ("sj_near", ctypes.c_void_p)]
+                ("kernel_ms", ctypes.c_double), ("sj_near", ctypes.c_void_p),
+                ("eig_ms", ctypes.c_double)]
 
 
 class _MlpShape(ctypes.Structure):
@@ -153,6 +156,8 @@ def default_opts(**kw) -> _Opts:
             v = SCHEDULES[v]
         if k == "start" and isinstance(v, str):
             v = {"zero": 0, "learned": 1}[v]
+        if k == "basis_kernel" and isinstance(v, str):
+            v = BASIS_KERNELS[v]
         setattr(o, k, v)
     return o
 
@@ -192,6 +197,7 @@ class SolveResult:
     mu: float
     elapsed_ms: float
     kernel_ms: float
+    eig_ms: float = 0.0
 
 
 class Context:
@@ -335,7 +341,8 @@ class Context:
             cptr, n = _ptr(cols), len(cols)
         o = opts if opts is not None else default_opts()
         res = _Result(_ptr(rho), _ptr(pi), _ptr(eps), _ptr(wts), _ptr(col_stats), 0.0, 0.0, 0.0,
-                      0.0, 0.0, _ptr(sj_near))
+                      0.0, 0.0, _ptr(sj_near), 0.0)
         self._check(self._lib.ma_solve_columns(self._h, n, cptr, int(p), int(q), float(mu),
                                                float(kT), ctypes.byref(o), ctypes.byref(res)))
-        return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, res.kernel_ms)
+        return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, res.kernel_ms,
+                           res.eig_ms)

@@ -106,6 +106,7 @@ struct ma_ctx {
     int nmax = 0, maxpat = 0;
     std::vector<int32_t> reg_len_of_atom;   // host: region atoms per atom (for ordering)
     std::vector<int64_t> lblk_of_atom;      // host: local operator blocks per atom
+    std::vector<int32_t> pat_blocks;        // host: blocks in each atom's block-row
 
     // device system
     DevBuf blk_ptr, blk_col, Hd, Sd, Hf, Sf, reg_id, reg_off, reg_len, lrp_off, lrp, lblk, jloc,
@@ -125,12 +126,15 @@ struct ma_ctx {
     DevBuf feat, x0;                  // per-solve descriptors and predicted starts
 
     // device solve buffers
-    DevBuf cols, order, qbounds, ws, eps, wts, amp, stats, ctl, lohi, partial, Ecol, Ncol, sums;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr;
+    DevBuf cols, order, qbounds, ws, eps, wts, amp, amp_off, mid, stats, ctl, lohi, partial, Ecol,
+        Ncol, sums;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr, eve1 = nullptr;
+    std::vector<hipEvent_t> chunk_ev;  // per-chunk timing of eager multi-chunk solves
     uint64_t generation = 0;          // bumped by every ma_build_system
 
     // captured launch sequence and the configuration it was captured for
-    hipGraphExec_t gexec = nullptr;   // the column kernel
+    hipGraphExec_t gexec = nullptr;   // queue reset and the basis kernel
+    hipGraphExec_t gexec1 = nullptr;  // the eigensolver kernel
     hipGraphExec_t gexec2 = nullptr;  // bisection, Fermi weighting, reductions
     hipGraphExec_t gexec0 = nullptr;  // descriptors and start network (learned start)
     std::vector<unsigned char> gkey;
@@ -147,9 +151,10 @@ struct ma_ctx {
     void drop_graph()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (gexec1) (void)hipGraphExecDestroy(gexec1);
         if (gexec2) (void)hipGraphExecDestroy(gexec2);
         if (gexec0) (void)hipGraphExecDestroy(gexec0);
-        gexec = gexec2 = gexec0 = nullptr;
+        gexec = gexec1 = gexec2 = gexec0 = nullptr;
         gkey.clear();
     }
 
@@ -420,6 +425,8 @@ MA_API void ma_default_opts(ma_opts *o)
     o->slots_per_cu = 0;
     o->schedule = -1;
     o->use_graph = 1;
+    o->basis_kernel = MA_BASIS_AUTO;
+    o->chunk_columns = 0;
 }
 
 MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
@@ -437,6 +444,7 @@ MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
             hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreate(&c->evk0) != hipSuccess || hipEventCreate(&c->evk1) != hipSuccess ||
+        hipEventCreate(&c->eve1) != hipSuccess ||
         hipEventCreateWithFlags(&c->evu, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
         delete c;
@@ -454,6 +462,9 @@ MA_API ma_status ma_destroy(ma_ctx *ctx)
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->evk0) (void)hipEventDestroy(ctx->evk0);
     if (ctx->evk1) (void)hipEventDestroy(ctx->evk1);
+    if (ctx->eve1) (void)hipEventDestroy(ctx->eve1);
+    for (hipEvent_t e : ctx->chunk_ev) (void)hipEventDestroy(e);
+    ctx->chunk_ev.clear();
     ctx->drop_graph();
     if (ctx->evu) (void)hipEventDestroy(ctx->evu);
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
@@ -735,9 +746,11 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     ctx->maxpat = maxpat;
     ctx->reg_len_of_atom.resize(n);
     ctx->lblk_of_atom.resize(n);
+    ctx->pat_blocks.resize(n);
     for (int a = 0; a < n; ++a) {
         ctx->reg_len_of_atom[a] = h_reg_len[h_reg_id[a]];
         ctx->lblk_of_atom[a] = cnt[h_reg_id[a] + 1];
+        ctx->pat_blocks[a] = (int32_t)(bp[a + 1] - bp[a]);
     }
     ctx->built = true;
     return MA_OK;
@@ -782,11 +795,26 @@ struct Plan {
     int p = 0, q = 0, nu = 0, slots = 0, sched = 0;
     double mu = 0, kT = 0, n_target = 0;
     bool bisect = false;
+    bool small = false;          // basis kernel keeps the basis on chip
+    int chunk = 0, nchunks = 0;  // columns per chunk of the processing order
     std::vector<int32_t> hcols;
     ma::DevSystem S;
-    ma::DevJob J;
+    ma::DevJob J;                // J.c0, J.cn, J.qbounds describe chunk 0
+    const int32_t *qb_dev = nullptr;
     double *rho = nullptr, *pi = nullptr;
+    ma::DevJob chunk_job(int k) const
+    {
+        ma::DevJob Jk = J;
+        Jk.c0 = k * chunk;
+        Jk.cn = std::min(chunk, J.ncols - Jk.c0);
+        Jk.qbounds = qb_dev + (int64_t)k * (J.nqueues + 1);
+        return Jk;
+    }
 };
+
+// Chunk buffer budget: the Galerkin pairs and basis rows of the columns of
+// one chunk (the rest of the solve's memory is proportional to the system).
+constexpr size_t kMidBudget = (size_t)4 << 30;
 
 ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, int32_t q,
                     double mu, double kT, const ma_opts *opts_in, double *rho, double *pi,
@@ -829,6 +857,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     P.n_target = std::isnan(opts.n_target) ? 0.5 * (double)ncols : opts.n_target;
     P.rho = rho;
     P.pi = pi;
+    if (sj_near && !ctx->have_geo) return ctx->fail(MA_EINVAL, "sj_near needs positions");
 
     // launch configuration: explicit, autotuned, or defaults
     const ma_ctx::Tune *tn = ctx->find_tune(p, q, opts.precision);
@@ -848,19 +877,33 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     J.inner_tol = opts.inner_tol;
     J.tau = opts.breakdown_tau;
     J.max_refine = opts.max_refine;
-    J.ws_stride = (int64_t)(3 * P.nu + q) * ctx->nmax;
+    if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_WORKSPACE)
+        return ctx->fail(MA_EINVAL, "unknown basis kernel %d", opts.basis_kernel);
+    if (opts.chunk_columns < 0) return ctx->fail(MA_EINVAL, "chunk_columns must be >= 0");
+    const bool fits = ma::basis_small_fits(ctx->nmax, P.nu, q, ctx->o);
+    if (opts.basis_kernel == MA_BASIS_ONCHIP && !fits)
+        return ctx->fail(MA_EINVAL, "the on-chip basis kernel cannot hold regions of %d orbitals "
+                         "with p = %d, q = %d", ctx->nmax, p, q);
+    P.small = opts.basis_kernel == MA_BASIS_WORKSPACE ? false : fits;
+    J.ws_stride = P.small ? 0 : (int64_t)(3 * P.nu + q) * ctx->nmax;
     int bpc = 0;
-    hipError_t e = ma::solve_occupancy(S, J, &bpc);
+    hipError_t e = ma::basis_occupancy(S, J, P.small, &bpc);
     if (e != hipSuccess) return ctx->hip_fail(e, "occupancy");
     if (bpc < 1)
-        return ctx->fail(MA_EINVAL, "column kernel does not fit on a compute unit (nu=%d, nmax=%d)",
+        return ctx->fail(MA_EINVAL, "basis kernel does not fit on a compute unit (nu=%d, nmax=%d)",
                          P.nu, ctx->nmax);
     int want = slots_override > 0 ? slots_override
                : opts.slots_per_cu > 0 ? opts.slots_per_cu : (tn ? tn->slots : bpc);
     bpc = std::min(bpc, std::max(1, want));
-    P.slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, ncols);
 
-    // processing order and queue bounds
+    // chunks of the processing order
+    J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
+    const int64_t per_chunk = std::max<int64_t>(1, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
+    P.chunk = (int)std::min<int64_t>(ncols, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
+    P.nchunks = (int)((ncols + P.chunk - 1) / P.chunk);
+    P.slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, P.chunk);
+
+    // processing order and per-chunk queue bounds
     std::vector<int32_t> order(ncols);
     std::iota(order.begin(), order.end(), 0);
     auto lpt = [&](std::vector<int32_t>::iterator b, std::vector<int32_t>::iterator e2) {
@@ -870,19 +913,44 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     };
     const bool xcd = P.sched == MA_SCHED_XCD_INPUT || P.sched == MA_SCHED_XCD_LPT;
     J.nqueues = xcd ? ma::kMaxQueues : 1;
-    std::vector<int32_t> qb(J.nqueues + 1);
-    for (int k = 0; k <= J.nqueues; ++k) qb[k] = (int32_t)((int64_t)ncols * k / J.nqueues);
-    if (P.sched == MA_SCHED_LPT) lpt(order.begin(), order.end());
-    if (P.sched == MA_SCHED_XCD_LPT)
-        for (int k = 0; k < J.nqueues; ++k) lpt(order.begin() + qb[k], order.begin() + qb[k + 1]);
+    std::vector<int32_t> qb((size_t)P.nchunks * (J.nqueues + 1));
+    for (int k = 0; k < P.nchunks; ++k) {
+        const int64_t c0 = (int64_t)k * P.chunk, cn = std::min<int64_t>(P.chunk, ncols - c0);
+        for (int i = 0; i <= J.nqueues; ++i)
+            qb[(size_t)k * (J.nqueues + 1) + i] = (int32_t)(c0 + cn * i / J.nqueues);
+        if (P.sched == MA_SCHED_LPT) lpt(order.begin() + c0, order.begin() + c0 + cn);
+        if (P.sched == MA_SCHED_XCD_LPT)
+            for (int i = 0; i < J.nqueues; ++i)
+                lpt(order.begin() + qb[(size_t)k * (J.nqueues + 1) + i],
+                    order.begin() + qb[(size_t)k * (J.nqueues + 1) + i + 1]);
+    }
+    // amplitudes (only while the chemical potential is unknown), compact per column
+    const int o = ctx->o;
+    std::vector<int64_t> aoff;
+    size_t amp_elems = 0;
+    if (P.bisect) {
+        aoff.resize(ncols + 1);
+        aoff[0] = 0;
+        for (int64_t c = 0; c < ncols; ++c) {
+            const int A = P.hcols[c] / o;
+            aoff[c + 1] = aoff[c] + (int64_t)ctx->pat_blocks[A] * o * P.nu;
+        }
+        amp_elems = (size_t)aoff[ncols];
+    }
+    const size_t amp_bytes = (opts.precision == MA_PREC_FP64 ? sizeof(double) : sizeof(float)) *
+                             std::max<size_t>(1, amp_elems);
 
     HIPCHK(ctx, ctx->cols.reserve(sizeof(int32_t) * ncols), "cols");
     HIPCHK(ctx, ctx->order.reserve(sizeof(int32_t) * ncols), "order");
-    HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * (ma::kMaxQueues + 1)), "queues");
-    HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
+    HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * qb.size()), "queues");
+    if (!P.small) HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
+    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.chunk), "chunk buffer");
     HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
     HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
-    HIPCHK(ctx, ctx->amp.reserve(sizeof(double) * (size_t)ncols * ctx->maxpat * P.nu), "amplitudes");
+    if (P.bisect) {
+        HIPCHK(ctx, ctx->amp.reserve(amp_bytes), "amplitudes");
+        HIPCHK(ctx, ctx->amp_off.reserve(sizeof(int64_t) * (ncols + 1)), "amplitude offsets");
+    }
     HIPCHK(ctx, ctx->stats.reserve(sizeof(int32_t) * (size_t)ncols * ma::kStats), "stats");
     if (opts.start == MA_START_LEARNED) {
         HIPCHK(ctx, ctx->feat.reserve(sizeof(float) * (size_t)ncols * ctx->net.nf), "descriptors");
@@ -899,32 +967,57 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, P.hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
     HIPCHK(ctx, hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "order");
     HIPCHK(ctx, hipMemcpyAsync(ctx->qbounds.p, qb.data(), sizeof(int32_t) * qb.size(), hipMemcpyHostToDevice, st), "queues");
+    if (P.bisect)
+        HIPCHK(ctx, hipMemcpyAsync(ctx->amp_off.p, aoff.data(), sizeof(int64_t) * (ncols + 1), hipMemcpyHostToDevice, st), "amplitude offsets");
     // the copies read pageable host vectors: finish them before those go away
     HIPCHK(ctx, hipStreamSynchronize(st), "upload");
 
     J.cols = ctx->cols.as<int32_t>();
     J.order = ctx->order.as<int32_t>();
-    J.qbounds = ctx->qbounds.as<int32_t>();
+    P.qb_dev = ctx->qbounds.as<int32_t>();
+    J.qbounds = P.qb_dev;
+    J.c0 = 0;
+    J.cn = P.chunk;
     J.queue = ctx->ctl.as<int>();
     J.fail = ctx->ctl.as<int>() + ma::kMaxQueues;
-    J.ws = ctx->ws.as<double>();
+    J.ws = P.small ? nullptr : ctx->ws.as<double>();
+    J.mid = ctx->mid.as<double>();
     J.eps = eps ? eps : ctx->eps.as<double>();
     J.wts = wts ? wts : ctx->wts.as<double>();
-    J.amp = ctx->amp.as<double>();
+    J.amp = P.bisect ? ctx->amp.p : nullptr;
+    J.amp_off = P.bisect ? ctx->amp_off.as<int64_t>() : nullptr;
     J.stats = col_stats ? col_stats : ctx->stats.as<int32_t>();
     J.x0 = opts.start == MA_START_LEARNED ? ctx->x0.as<float>() : nullptr;
     J.sj_near = sj_near;
-    if (sj_near && !ctx->have_geo) return ctx->fail(MA_EINVAL, "sj_near needs positions");
+    J.direct = P.bisect ? 0 : 1;
+    J.mu = P.bisect ? 0.0 : mu;
+    J.kT = kT;
+    J.rho = rho;
+    J.pi = pi;
+    J.Ecol = ctx->Ecol.as<double>();
+    J.Ncol = ctx->Ncol.as<double>();
     return MA_OK;
 }
 
-// The launch sequence of one solve, in two parts (each captured into a graph
-// or launched directly): the column kernel, then the chemical potential,
-// Fermi weighting and reductions.  The work counters are reset outside.
-hipError_t enqueue_solve(ma_ctx *ctx, const Plan &P)
+// The launch sequence of one solve: per chunk the queue reset and the basis
+// kernel, then the eigensolver kernel; then the chemical potential, the
+// Fermi weighting of the stored amplitudes and the reductions.
+hipError_t enqueue_basis(ma_ctx *ctx, const Plan &P, int k)
 {
-    return ma::launch_solve(P.S, P.J, P.slots, ctx->work_stream());
+    hipStream_t st = ctx->work_stream();
+    const ma::DevJob Jk = P.chunk_job(k);
+    hipError_t e = ma::launch_reset(Jk.queue, Jk.fail, k == 0 ? 1 : 0, st);
+    if (e != hipSuccess) return e;
+    return ma::launch_basis(P.S, Jk, P.small, (int)std::min<int64_t>(P.slots, Jk.cn), st);
 }
+
+hipError_t enqueue_eig(ma_ctx *ctx, const Plan &P, int k)
+{
+    return ma::launch_eig(P.S, P.chunk_job(k), ctx->work_stream());
+}
+
+hipError_t enqueue_basis0(ma_ctx *ctx, const Plan &P) { return enqueue_basis(ctx, P, 0); }
+hipError_t enqueue_eig0(ma_ctx *ctx, const Plan &P) { return enqueue_eig(ctx, P, 0); }
 
 hipError_t net_refresh_bf16(ma_ctx *ctx, hipStream_t st);
 
@@ -953,9 +1046,9 @@ hipError_t enqueue_post(ma_ctx *ctx, const Plan &P)
         if ((e = ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, P.kT, ctx->lohi.as<double>(), st)) != hipSuccess) return e;
         if ((e = ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, J.nu, P.kT, P.n_target,
                                    ctx->lohi.as<double>(), ctx->partial.as<double>(), st)) != hipSuccess) return e;
+        if ((e = ma::launch_rho(S, J, ctx->lohi.as<double>(), P.kT, P.rho, P.pi,
+                                ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), st)) != hipSuccess) return e;
     }
-    if ((e = ma::launch_rho(S, J, P.bisect ? ctx->lohi.as<double>() : nullptr, P.mu, P.kT, P.rho,
-                            P.pi, ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), st)) != hipSuccess) return e;
     return ma::launch_sum2(ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), J.ncols,
                            ctx->sums.as<double>(), st);
 }
@@ -986,10 +1079,10 @@ std::vector<unsigned char> graph_key(const ma_ctx *ctx, const Plan &P)
 {
     std::vector<unsigned char> k;
     key_add(k, ctx->generation);
-    key_add(k, P.J);          // sizes, tolerances and every device pointer
+    key_add(k, P.J);          // sizes, tolerances, mu, and every device pointer
     key_add(k, P.slots);
+    key_add(k, P.small);
     key_add(k, P.bisect);
-    key_add(k, P.mu);
     key_add(k, P.kT);
     key_add(k, P.n_target);
     key_add(k, P.rho);
@@ -997,16 +1090,20 @@ std::vector<unsigned char> graph_key(const ma_ctx *ctx, const Plan &P)
     return k;
 }
 
-// Run the plan; fills the result scalars.  kernel_ms is the column kernel's
-// time from HIP events recorded around its launch on the stream.
+// Run the plan; fills the result scalars.  kernel_ms is the basis kernel's
+// time and eig_ms the eigensolver kernel's, from HIP events recorded around
+// their launches on the stream (summed over chunks).  A single-chunk solve
+// with use_graph replays captured graphs; events sit between the graphs.
 ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
 {
     hipStream_t st = ctx->work_stream();
-    if (P.opts.use_graph) {
+    const bool graphs = P.opts.use_graph && P.nchunks == 1;
+    if (graphs) {
         std::vector<unsigned char> key = graph_key(ctx, P);
         if (!ctx->gexec || key != ctx->gkey) {
             ctx->drop_graph();
-            hipError_t e = capture(ctx, P, enqueue_solve, &ctx->gexec);
+            hipError_t e = capture(ctx, P, enqueue_basis0, &ctx->gexec);
+            if (e == hipSuccess) e = capture(ctx, P, enqueue_eig0, &ctx->gexec1);
             if (e == hipSuccess) e = capture(ctx, P, enqueue_post, &ctx->gexec2);
             if (e == hipSuccess && P.J.x0) e = capture(ctx, P, enqueue_pre, &ctx->gexec0);
             if (e != hipSuccess) {
@@ -1016,19 +1113,35 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
             ctx->gkey = key;
         }
     }
-    // ev0 .. ev1 brackets the whole solve, evk0 .. evk1 the column kernel
+    float ms = 0.0f;
+    double basis_ms = 0.0, eig_ms = 0.0;
     HIPCHK(ctx, hipEventRecord(ctx->ev0, st), "event");
     if (P.J.x0) {
-        if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec0, st), "graph launch");
+        if (graphs) HIPCHK(ctx, hipGraphLaunch(ctx->gexec0, st), "graph launch");
         else HIPCHK(ctx, enqueue_pre(ctx, P), "start network");
     }
-    HIPCHK(ctx, ma::launch_reset(P.J.queue, P.J.fail, st), "reset");
-    HIPCHK(ctx, hipEventRecord(ctx->evk0, st), "event");
-    if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec, st), "graph launch");
-    else HIPCHK(ctx, enqueue_solve(ctx, P), "column kernel");
-    HIPCHK(ctx, hipEventRecord(ctx->evk1, st), "event");
-    if (P.opts.use_graph) HIPCHK(ctx, hipGraphLaunch(ctx->gexec2, st), "graph launch");
-    else HIPCHK(ctx, enqueue_post(ctx, P), "launch");
+    if (graphs) {
+        HIPCHK(ctx, hipEventRecord(ctx->evk0, st), "event");
+        HIPCHK(ctx, hipGraphLaunch(ctx->gexec, st), "graph launch");
+        HIPCHK(ctx, hipEventRecord(ctx->evk1, st), "event");
+        HIPCHK(ctx, hipGraphLaunch(ctx->gexec1, st), "graph launch");
+        HIPCHK(ctx, hipEventRecord(ctx->eve1, st), "event");
+        HIPCHK(ctx, hipGraphLaunch(ctx->gexec2, st), "graph launch");
+    } else {
+        while ((int)ctx->chunk_ev.size() < 3 * P.nchunks) {
+            hipEvent_t ev;
+            HIPCHK(ctx, hipEventCreate(&ev), "event");
+            ctx->chunk_ev.push_back(ev);
+        }
+        for (int k = 0; k < P.nchunks; ++k) {
+            HIPCHK(ctx, hipEventRecord(ctx->chunk_ev[3 * k], st), "event");
+            HIPCHK(ctx, enqueue_basis(ctx, P, k), "basis kernel");
+            HIPCHK(ctx, hipEventRecord(ctx->chunk_ev[3 * k + 1], st), "event");
+            HIPCHK(ctx, enqueue_eig(ctx, P, k), "eigensolver kernel");
+            HIPCHK(ctx, hipEventRecord(ctx->chunk_ev[3 * k + 2], st), "event");
+        }
+        HIPCHK(ctx, enqueue_post(ctx, P), "launch");
+    }
     HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
     double sums[2] = {0, 0}, lohi[2] = {0, 0};
     int ctl[ma::kMaxQueues + 1];
@@ -1036,11 +1149,23 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
     HIPCHK(ctx, hipMemcpyAsync(ctl, ctx->ctl.p, sizeof ctl, hipMemcpyDeviceToHost, st), "copy");
     if (P.bisect) HIPCHK(ctx, hipMemcpyAsync(lohi, ctx->lohi.p, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
     HIPCHK(ctx, hipStreamSynchronize(st), "solve");
-    float ms = 0.0f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "elapsed");
     out->elapsed_ms = ms;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evk0, ctx->evk1), "elapsed");
-    out->kernel_ms = ms;
+    if (graphs) {
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evk0, ctx->evk1), "elapsed");
+        basis_ms = ms;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evk1, ctx->eve1), "elapsed");
+        eig_ms = ms;
+    } else {
+        for (int k = 0; k < P.nchunks; ++k) {
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->chunk_ev[3 * k], ctx->chunk_ev[3 * k + 1]), "elapsed");
+            basis_ms += ms;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->chunk_ev[3 * k + 1], ctx->chunk_ev[3 * k + 2]), "elapsed");
+            eig_ms += ms;
+        }
+    }
+    out->kernel_ms = basis_ms;
+    out->eig_ms = eig_ms;
     out->energy = P.opts.spin * sums[0];
     out->n_elec = P.opts.spin * sums[1];
     out->mu = P.bisect ? 0.5 * (lohi[0] + lohi[1]) : P.mu;
@@ -1050,7 +1175,8 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         HIPCHK(ctx, hipMemcpy(st4, P.J.stats + (int64_t)failc * ma::kStats, sizeof st4, hipMemcpyDeviceToHost), "copy");
         const ma_status s = st4[3] == -4 ? MA_ENOTPD : MA_ENOCONV;
         return ctx->fail(s, "column %d (output row %d): %s after %d CG iterations", P.hcols[failc],
-                         failc, s == MA_ENOTPD ? "S_A not positive definite" : "CG did not converge",
+                         failc, s == MA_ENOTPD ? "S_A or the reduced overlap not positive definite"
+                                               : "CG did not converge",
                          st4[1]);
     }
     return MA_OK;

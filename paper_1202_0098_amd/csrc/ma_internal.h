@@ -45,43 +45,73 @@ struct DevSystem {
                                // region) of its kNbOut nearest atoms, -1 if outside
 };
 
-// One solve.
+// One solve.  Columns are processed in chunks of the processing order: the
+// basis kernel of a chunk writes, per column, the Galerkin pair and the
+// basis rows the outputs need into a chunk buffer (`mid`), and the
+// eigensolver kernel turns them into Ritz values, weights and amplitudes (or,
+// with a given chemical potential, into rho, pi and E_j, N_j directly).
 struct DevJob {
     int ncols;
     const int32_t *cols;       // global column per output row c
-    const int32_t *order;      // processing order (LPT): order[idx] = c
+    const int32_t *order;      // processing order: order[idx] = c
     int p, q, nu;
-    int precision;             // 0 FP64, 1 mixed
+    int precision;             // 0 FP64, 1 mixed (FP32 sums), 2 mixed (FP64 sums)
     double cg_tol, inner_tol, tau;
     int max_refine;
-    int *queue;                // work counters, one per queue (reset before launch)
+    int *queue;                // work counters, one per queue (reset before each chunk)
     int nqueues;               // 1, or 8 (one per XCD)
-    const int32_t *qbounds;    // nqueues + 1 offsets into order
+    const int32_t *qbounds;    // nqueues + 1 absolute offsets into order, this chunk
     int *fail;                 // [0] = first failing c (INT_MAX none)
-    double *ws;                // workspace, slots * ws_stride doubles
+    double *ws;                // basis workspace of the large-region kernel, slots * ws_stride
     int64_t ws_stride;
+    // chunk: order positions c0 .. c0 + cn; slot s = position - c0
+    int c0, cn;
+    double *mid;               // cn * mid_stride doubles
+    int64_t mid_stride;        // 2 nu^2 + (maxpat + 2) nu
     // per column outputs
     double *eps;               // ncols * nu
     double *wts;               // ncols * nu
-    double *amp;               // ncols * maxpat * nu: v_ia v_ja at pattern rows
+    void *amp;                 // v_ia v_ja at the pattern rows (rank order): FP64 for
+                               // precision 0, FP32 otherwise; column c starts at element
+    const int64_t *amp_off;    // amp_off[c] and holds npat(c) * nu entries
     int32_t *stats;            // ncols * kStats
     const float *x0;           // optional: predicted s_j on the kNbOut nearest atoms
                                // (ncols * kNbOut * o), else zero start
     float *sj_near;            // optional output: converged s_j on the same orbitals
+    // Given chemical potential: the eigensolver kernel applies the Fermi
+    // weights and writes rho, pi (either may be null) and E_j, N_j.
+    int direct;
+    double mu, kT;
+    double *rho, *pi, *Ecol, *Ncol;
 };
+
+// Slot layout of the chunk buffer (doubles, row stride nu):
+//   [0, nu^2)             X = U^T H U (at least its upper triangle; the
+//                         eigensolver symmetrises)
+//   [nu^2, 2 nu^2)        U^T S U
+//   [2 nu^2, ...)         row 0: u_m at the local row of j, row 1: (S u_m) at
+//                         that row, row 2 + t: u_m at pattern row t of j
+inline int64_t mid_stride_of(int nu, int maxpat) { return 2 * (int64_t)nu * nu + (int64_t)(maxpat + 2) * nu; }
 
 constexpr int kStats = 8;      // nu_eff, CG iterations, FP64 residual evaluations, status,
                                // start used (0 zero, 1 learned, 2 learned rejected), 3 spare
 
-// Shared-memory bytes the column kernel needs.
-size_t solve_smem_bytes(int nmax, int nu);
-
-// Launchers (all asynchronous on `st`).
+// Basis kernels.  The small-region kernel keeps the basis on chip (U in LDS,
+// S U and the block-2 chain in registers) and is used when every region has
+// at most kSmallRows orbitals, nu <= 32 and q <= nu_cap / 2; otherwise the
+// large-region kernel keeps U, S U, H U and the chain in a global workspace.
 constexpr int kMaxQueues = 8;
-hipError_t launch_reset(int *queue, int *fail, hipStream_t st);
-hipError_t launch_solve(const DevSystem &S, const DevJob &J, int slots, hipStream_t st);
-int solve_rows_per_thread(int nmax);
-hipError_t solve_occupancy(const DevSystem &S, const DevJob &J, int *blocks_per_cu);
+constexpr int kSmallRows = 512;
+bool basis_small_fits(int nmax, int nu, int q, int o);
+size_t basis_smem_bytes(int nmax, int nu, bool small);
+int basis_rows_per_thread(int nmax);
+hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st);
+hipError_t launch_basis(const DevSystem &S, const DevJob &J, bool small, int slots, hipStream_t st);
+hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, bool small, int *blocks_per_cu);
+
+// Batched reduced eigenproblems and column outputs, one wavefront per column
+// of the chunk.
+hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st);
 
 // Fermi weighting, chemical potential, reductions.
 hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int nu,
@@ -89,9 +119,8 @@ hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int
 hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *stats,
                          int ncols, int nu, double kT, double n_target, double *lohi,
                          double *partial, hipStream_t st);
-hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr, double mu,
-                      double kT, double *rho, double *pi, double *Ecol, double *Ncol,
-                      hipStream_t st);
+hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr, double kT,
+                      double *rho, double *pi, double *Ecol, double *Ncol, hipStream_t st);
 hipError_t launch_sum2(const double *a, const double *b, int n, double *out, hipStream_t st);
 
 // Start network (ma_mlp.hip).

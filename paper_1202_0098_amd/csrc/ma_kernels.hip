@@ -1,22 +1,33 @@
 // Device kernels of libmarnoldi (gfx950).
 //
-// k_solve: the per-column multiple Arnoldi solve (arXiv:1202.0098, Sec. 2),
-// one workgroup per column, persistent over an atomic work queue.  Per
-// column:
+// The per-column multiple Arnoldi solve (arXiv:1202.0098, Sec. 2) runs as two
+// kernels per chunk of columns.
+//
+// Basis kernel (persistent workgroups draining work queues), per column:
 //   inner CG for s_j = S_A^-1 e_j                 (Sec. 2, inner CG loop)
 //   S-orthonormal basis of K_p(H;e_j)+K_q(H;s_j)  (Eqs. 4, 6-9)
-//   Galerkin pair H~ = U^T H U, S~ = U^T S U      (Sec. 2, Galerkin principle)
-//   Cholesky of S~, cyclic Jacobi of L^-1 H~ L^-T (reduced eigenproblem)
-//   Ritz vectors at the pattern rows of j         (Eq. 10, Eqs. 13-14)
+//   Galerkin pair X = U^T H U, S~ = U^T S U        (Sec. 2, Galerkin principle)
 // H_A, S_A are the principal submatrices of H, S on the region of atom(j)
 // (real-space projection, Sec. 3), read through a per-region local block
-// index.  Thread t owns local rows t, t+256, ...; the vector an SpMV reads is
-// staged in LDS.  The basis U, S U, H U and the Krylov chain on s_j live in a
-// per-workgroup slice of a global workspace.
+// index.  Thread t owns local rows t, t + NT, ...; the vector an SpMV reads
+// is staged in LDS.  Two variants:
+//   k_basis_s  regions of at most 512 orbitals, nu <= 32: U lives in LDS,
+//              S U and the block-2 chain in registers (row-owned), and the
+//              Galerkin pair is accumulated as each vector is accepted, so the
+//              basis never leaves the compute unit;
+//   k_basis_g  any region: U, S U, H U and the chain live in a per-workgroup
+//              slice of a global workspace and the pair is formed on the FP64
+//              matrix cores.
+// Both write the pair and the basis rows the outputs need into a chunk buffer.
 //
-// The remaining kernels weight the Ritz pairs with the Fermi function
-// (Eqs. 13-14), bisect the chemical potential on the electron count and
-// reduce the column energies (Eq. 17) in a fixed order.
+// Eigensolver kernel (one wavefront per column): Cholesky of S~, cyclic
+// Jacobi of L^-1 H~ L^-T, the Ritz vectors at the rows of the outputs, Ritz
+// values and weights, and either the amplitudes v_ia v_ja (chemical potential
+// still to be found) or the Fermi-weighted rho, pi, E_j, N_j (Eqs. 13-14, 17).
+//
+// The remaining kernels bisect the chemical potential on the electron count
+// (Sec. 2, summation over j), weight the stored amplitudes with the Fermi
+// function and reduce the column energies in a fixed order.
 #include <float.h>
 #include <limits.h>
 #include <math.h>
@@ -29,17 +40,11 @@ namespace ma {
 
 namespace {
 
-constexpr int NT = kThreads;
-constexpr int NW = kWaves;
-constexpr int kTile = 16;          // rows per projection tile
-
-__host__ __device__ inline int vec_doubles(int nmax, int nu)
-{
-    return 2 * nmax > 3 * kTile * nu ? 2 * nmax : 3 * kTile * nu;
-}
+constexpr int NTG = 256;           // workgroup size of the large-region kernel
+constexpr int NWG = NTG / 64;
 
 // ------------------------------------------------------------------------
-// reductions (xor butterflies give bitwise identical sums in every lane)
+// reductions (fixed order: results are bitwise reproducible)
 // ------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -55,9 +60,9 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// Sum over the workgroup, in a fixed order.  Ends with a barrier, so the
+// Sum over the workgroup (NWV wavefronts).  Ends with a barrier, so the
 // caller may overwrite shared buffers read before the call.
-template <typename T>
+template <int NWV, typename T>
 __device__ __forceinline__ T block_sum(T v, T *red)
 {
     v = wave_sum(v);
@@ -65,9 +70,84 @@ __device__ __forceinline__ T block_sum(T v, T *red)
     __syncthreads();
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) s += red[k];
+    for (int k = 0; k < NWV; ++k) s += red[k];
     __syncthreads();
     return s;
+}
+
+// Transposed wavefront reduction of NV values per lane (NV a power of two,
+// at most 32): log2(NV) halving exchanges, each lane keeping the half its
+// lane bit selects, then a butterfly over the remaining lane bits.  Costs
+// NV - 1 + 6 - log2(NV) exchanges instead of 6 NV.  Afterwards v[0] of lane l
+// holds the wavefront total of value tr_index<NV>(l).
+template <int NV>
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2<NV>(v / 2); }
+
+template <int NV>
+__device__ __forceinline__ void wave_transpose_reduce(double (&v)[NV])
+{
+    constexpr int LG = ilog2<NV>(NV);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int step = 0; step < LG; ++step) {
+        const int half = NV >> (step + 1), off = 32 >> step;
+        const bool hi = (lane & off) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const double lo_v = v[k], hi_v = v[k + half];
+            const double send = hi ? lo_v : hi_v;
+            const double keep = hi ? hi_v : lo_v;
+            v[k] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+#pragma unroll
+    for (int step = LG; step < 6; ++step) v[0] += __shfl_xor(v[0], 32 >> step, 64);
+}
+
+template <int NV>
+__device__ __forceinline__ int tr_index(int lane)
+{
+    constexpr int LG = ilog2<NV>(NV);
+    int idx = 0;
+#pragma unroll
+    for (int step = 0; step < LG; ++step)
+        if (lane & (32 >> step)) idx += NV >> (step + 1);
+    return idx;
+}
+
+// the lanes whose butterfly bits are zero hold every value exactly once
+template <int NV>
+__device__ __forceinline__ bool tr_writer(int lane) { return (lane & (64 / NV - 1)) == 0; }
+
+// G groups of NV values per thread, summed over the workgroup: out[g*NV + k]
+// (LDS) receives the total of value k of group g.  `gen(g, v)` fills group g;
+// groups are produced and reduced one at a time to bound register use.
+// Starts and ends with the scratch area free; ends with a barrier.
+template <int NWV, int NV, int G, typename F>
+__device__ __forceinline__ void block_reduce(F &&gen, double *scratch, double *out)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double res[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double v[NV];
+        gen(g, v);
+        wave_transpose_reduce<NV>(v);
+        res[g] = v[0];
+    }
+    if (tr_writer<NV>(lane)) {
+        const int k = tr_index<NV>(lane);
+#pragma unroll
+        for (int g = 0; g < G; ++g) scratch[(w * G + g) * NV + k] = res[g];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < G * NV; t += NWV * 64) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NWV; ++k) s += scratch[k * G * NV + t];
+        out[t] = s;
+    }
+    __syncthreads();
 }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -99,9 +179,23 @@ struct Col {
     int A, r;            // atom and orbital of j
 };
 
+__device__ __forceinline__ Col make_col(const DevSystem &S, const DevJob &J, int c, int o)
+{
+    Col g;
+    const int j = J.cols[c];
+    g.A = j / o;
+    g.r = j - g.A * o;
+    const int rid = S.reg_id[g.A];
+    g.n_at = S.reg_len[rid];
+    g.n = g.n_at * o;
+    g.rp = S.lrp + S.lrp_off[rid];
+    g.jl = S.jloc[g.A] * o + g.r;
+    return g;
+}
+
 // SpMV on the thread's own rows: hy = H x, sy = S x (x in LDS), zy = H xb.
 // TM: stored operator values; TX: vector entries and accumulation.
-template <int O, int R, typename TM, typename TX, bool DO_H, bool DO_S, bool DO_Z>
+template <int O, int R, int NT, typename TM, typename TX, bool DO_H, bool DO_S, bool DO_Z>
 __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int o_rt,
                                           const TM *__restrict__ Hv, const TM *__restrict__ Sv,
                                           const TX *xa, const TX *xb, double (&hy)[R],
@@ -122,18 +216,18 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
                 const int xo = e.x * o;
                 if constexpr (O > 0) {
 #pragma unroll
-                    for (int c = 0; c < O; ++c) {
-                        const TX xv = xa[xo + c];
-                        if (DO_H) h += (TX)Hv[base + c] * xv;
-                        if (DO_S) s += (TX)Sv[base + c] * xv;
-                        if (DO_Z) z += (TX)Hv[base + c] * xb[xo + c];
+                    for (int cc = 0; cc < O; ++cc) {
+                        const TX xv = xa[xo + cc];
+                        if (DO_H) h += (TX)Hv[base + cc] * xv;
+                        if (DO_S) s += (TX)Sv[base + cc] * xv;
+                        if (DO_Z) z += (TX)Hv[base + cc] * xb[xo + cc];
                     }
                 } else {
-                    for (int c = 0; c < o; ++c) {
-                        const TX xv = xa[xo + c];
-                        if (DO_H) h += (TX)Hv[base + c] * xv;
-                        if (DO_S) s += (TX)Sv[base + c] * xv;
-                        if (DO_Z) z += (TX)Hv[base + c] * xb[xo + c];
+                    for (int cc = 0; cc < o; ++cc) {
+                        const TX xv = xa[xo + cc];
+                        if (DO_H) h += (TX)Hv[base + cc] * xv;
+                        if (DO_S) s += (TX)Sv[base + cc] * xv;
+                        if (DO_Z) z += (TX)Hv[base + cc] * xb[xo + cc];
                     }
                 }
             }
@@ -144,7 +238,7 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
     }
 }
 
-template <int R, typename T>
+template <int R, int NT, typename T>
 __device__ __forceinline__ void store_rows(T *dst, const double (&v)[R], int n)
 {
 #pragma unroll
@@ -154,7 +248,7 @@ __device__ __forceinline__ void store_rows(T *dst, const double (&v)[R], int n)
     }
 }
 
-template <int R>
+template <int R, int NT>
 __device__ __forceinline__ double dot_rows(const double (&a)[R], const double (&b)[R], int n)
 {
     double s = 0.0;
@@ -164,13 +258,232 @@ __device__ __forceinline__ double dot_rows(const double (&a)[R], const double (&
     return s;
 }
 
+// ------------------------------------------------------------------------
+// inner CG: S_A s = e_j (a3), shared by both basis kernels
+// ------------------------------------------------------------------------
+// PREC 0: FP64 CG with true-residual restarts.  PREC 1, 2: FP32 CG passes
+// with FP32 accumulation on the normalised FP64 residual, each judged and
+// refined in FP64.  x holds the thread's rows of s_j on return.
+template <int O, int R, int NT, int PREC>
+__device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int c, double *xa,
+                         double *xb, double *red, float *redf, double (&x)[R], int &iters,
+                         int &nres, int &status, int &start)
+{
+    constexpr int NWV = NT / 64;
+    const int o = O ? O : S.o;
+    const int tid = threadIdx.x;
+    const int n = g.n;
+    float *xaF = reinterpret_cast<float *>(xa);
+    float *xbF = reinterpret_cast<float *>(xb);
+    double dummy[R];
+    bool converged = false;
+    iters = nres = status = start = 0;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) x[rr] = 0.0;
+    const int nout = kNbOut * o;
+    if (J.x0) {
+        // predicted coefficients on the orbitals of the kNbOut nearest atoms
+        for (int i = tid; i < n; i += NT) xa[i] = 0.0;
+        __syncthreads();
+        for (int e = tid; e < nout; e += NT) {
+            const int k = e / o, cc = e - k * o;
+            const int la = S.out_loc[(int64_t)g.A * kNbOut + k];
+            if (la >= 0) xa[la * o + cc] = (double)J.x0[(int64_t)c * nout + e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int i = tid + rr * NT;
+            if (i < n) x[rr] = xa[i];
+        }
+        start = 1;
+        __syncthreads();
+    }
+    if (PREC == 0) {
+        double r[R], p[R], q[R];
+        // r = e_j - S x
+        store_rows<R, NT, double>(xa, x, n);
+        __syncthreads();
+        spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
+        double rho2 = block_sum<NWV>(dot_rows<R, NT>(r, r, n), red);
+        ++nres;
+        if (start == 1 && !(rho2 < 1.0)) {
+            // the residual judge rejects the predicted start: zero start
+            start = 2;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                x[rr] = 0.0;
+                r[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+            }
+            rho2 = 1.0;
+        }
+        for (int restart = 0; restart <= 3 && !converged && status == 0; ++restart) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) p[rr] = r[rr];
+            for (int k = 0; k < n && sqrt(rho2) > J.cg_tol; ++k) {
+                store_rows<R, NT, double>(xa, p, n);
+                __syncthreads();
+                spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+                const double pq = block_sum<NWV>(dot_rows<R, NT>(p, q, n), red);
+                if (!(pq > 0.0)) { status = -4; break; }
+                const double alpha = rho2 / pq;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    x[rr] += alpha * p[rr];
+                    r[rr] -= alpha * q[rr];
+                }
+                const double rn = block_sum<NWV>(dot_rows<R, NT>(r, r, n), red);
+                const double beta = rn / rho2;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) p[rr] = r[rr] + beta * p[rr];
+                rho2 = rn;
+                ++iters;
+            }
+            if (status) break;
+            // judge on the true residual
+            store_rows<R, NT, double>(xa, x, n);
+            __syncthreads();
+            spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
+            rho2 = block_sum<NWV>(dot_rows<R, NT>(r, r, n), red);
+            ++nres;
+            if (sqrt(rho2) <= J.cg_tol) converged = true;
+        }
+    } else {
+        double q[R], r64[R];
+        for (int ref = 0; ref <= J.max_refine && status == 0; ++ref) {
+            store_rows<R, NT, double>(xa, x, n);
+            __syncthreads();
+            spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
+            double rho2 = block_sum<NWV>(dot_rows<R, NT>(r64, r64, n), red);
+            ++nres;
+            if (ref == 0 && start == 1 && !(rho2 < 1.0)) {
+                start = 2;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    x[rr] = 0.0;
+                    r64[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+                }
+                rho2 = 1.0;
+            }
+            if (sqrt(rho2) <= J.cg_tol) { converged = true; break; }
+            if (ref == J.max_refine) break;
+            const double rho = sqrt(rho2);
+            float rf[R], pf[R], df[R];
+            double qd[R];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                rf[rr] = (float)(r64[rr] / rho);
+                pf[rr] = rf[rr];
+                df[rr] = 0.0f;
+            }
+            float rrf = 0.0f;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+                if (tid + rr * NT < n) rrf += rf[rr] * rf[rr];
+            rrf = block_sum<NWV>(rrf, redf);
+            const float thr = (float)J.inner_tol;
+            for (int k = 0; k < n && sqrtf(rrf) > thr; ++k) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    if (tid + rr * NT < n) xaF[tid + rr * NT] = pf[rr];
+                __syncthreads();
+                spmv_rows<O, R, NT, float, float, false, true, false>(S, g, o, S.Hf, S.Sf, xaF, xbF, dummy, qd, dummy);
+                float pq = 0.0f;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    if (tid + rr * NT < n) pq += pf[rr] * (float)qd[rr];
+                pq = block_sum<NWV>(pq, redf);
+                if (!(pq > 0.0f)) { status = -4; break; }
+                const float alpha = rrf / pq;
+                float rn = 0.0f;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    df[rr] += alpha * pf[rr];
+                    rf[rr] -= alpha * (float)qd[rr];
+                    if (tid + rr * NT < n) rn += rf[rr] * rf[rr];
+                }
+                rn = block_sum<NWV>(rn, redf);
+                const float beta = rn / rrf;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) pf[rr] = rf[rr] + beta * pf[rr];
+                rrf = rn;
+                ++iters;
+            }
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) x[rr] += rho * (double)df[rr];
+        }
+    }
+    if (status == 0 && !converged) status = -5;
+    if (J.sj_near) {
+        // s_j on the orbitals of the kNbOut nearest atoms (training targets)
+        __syncthreads();
+        store_rows<R, NT, double>(xa, x, n);
+        __syncthreads();
+        for (int e = tid; e < nout; e += NT) {
+            const int k = e / o, cc = e - k * o;
+            const int la = S.out_loc[(int64_t)g.A * kNbOut + k];
+            J.sj_near[(int64_t)c * nout + e] = (status == 0 && la >= 0) ? (float)xa[la * o + cc] : 0.0f;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void write_stats(const DevJob &J, int c, int L, int iters, int nres,
+                                            int status, int start)
+{
+    int32_t *st = J.stats + (int64_t)c * kStats;
+    st[0] = status == 0 ? L : 0;
+    st[1] = iters;
+    st[2] = nres;
+    st[3] = status;
+    st[4] = start;
+    st[5] = st[6] = st[7] = 0;
+    if (status != 0) atomicMin(J.fail, c);
+}
+
+// Persistent loop over the chunk's work queues: queue k serves order
+// positions qbounds[k] .. qbounds[k+1]; a workgroup starts at queue
+// blockIdx.x % nqueues (workgroups are dispatched to the XCDs round-robin)
+// and moves on when a queue is exhausted.  Every queue is visited at most
+// once, so every workgroup leaves the loop.
+template <typename F>
+__device__ __forceinline__ void drain_queues(const DevJob &J, int *s_idx, F &&body)
+{
+    int qi = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int idx = -1;
+            for (; qi < J.nqueues; ++qi) {
+                const int k = (blockIdx.x + qi) % J.nqueues;
+                const int pos = J.qbounds[k] + atomicAdd(J.queue + k, 1);
+                if (pos < J.qbounds[k + 1]) { idx = pos; break; }
+            }
+            *s_idx = idx;
+        }
+        __syncthreads();
+        const int idx = *s_idx;
+        __syncthreads();
+        if (idx < 0) break;
+        body(J.order[idx], idx - J.c0);
+    }
+}
+
+// ------------------------------------------------------------------------
+// large-region basis kernel: basis in the global workspace
+// ------------------------------------------------------------------------
 // out[m] = V[m] . x for m < L (x in LDS).  Each wavefront takes four
 // consecutive m at a time, keeping four independent load streams in flight.
 __device__ __forceinline__ void multidot(const double *__restrict__ V, int64_t ld, int L,
                                          const double *x, int n, double *out)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int m0 = 4 * w; m0 < L; m0 += 4 * NW) {
+    for (int m0 = 4 * w; m0 < L; m0 += 4 * NWG) {
         const int nm = min(4, L - m0);
         const double *v0 = V + m0 * ld;
         const double *v1 = V + (m0 + (nm > 1 ? 1 : 0)) * ld;
@@ -204,7 +517,7 @@ __device__ __forceinline__ void sub_comb(double (&l)[R], const double *__restric
 {
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-        const int i = threadIdx.x + rr * NT;
+        const int i = threadIdx.x + rr * NTG;
         if (i < n) {
             double acc = 0.0;
 #pragma unroll 8
@@ -214,24 +527,15 @@ __device__ __forceinline__ void sub_comb(double (&l)[R], const double *__restric
     }
 }
 
-// ------------------------------------------------------------------------
-// the column kernel
-// ------------------------------------------------------------------------
-struct Smem {
+struct SmemG {
     double *xa, *xb;     // nmax each: SpMV inputs / dot operands
-    double *cf;          // 4 * kMaxNu: coefficients, Ritz data
-    double *mat;         // 3 * nu^2: H~, S~ (then its Cholesky factor), Y (then C)
-    double *red;         // NW
-    float *redf;         // NW
+    double *cf;          // 4 * kMaxNu: coefficients
+    double *red;         // NWG
+    float *redf;         // NWG
 };
 
-// PREC 0: FP64 everywhere.  PREC 1: FP32 operator values, vectors and
-// accumulation in every SpMV.  PREC 2: FP32 operator values, FP64 vectors and
-// accumulation in the basis SpMVs.  PREC 1 and 2 run the CG in FP32 with an
-// FP64 residual judge and refinement; Gram-Schmidt, projection and the
-// eigensolve are FP64 in every mode.
 template <int O, int R, int PREC>
-__device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm, int c,
+__device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &sm, int c, int s,
                              double *U, double *SU, double *K, double *T)
 {
     using TM = typename std::conditional<PREC != 0, float, double>::type;
@@ -240,191 +544,20 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
     const int tid = threadIdx.x;
     const int64_t ld = S.nmax;
     const int nu = J.nu;
-    __shared__ int s_flag;
-
-    Col g;
-    {
-        const int j = J.cols[c];
-        g.A = j / o;
-        g.r = j - g.A * o;
-        const int rid = S.reg_id[g.A];
-        g.n_at = S.reg_len[rid];
-        g.n = g.n_at * o;
-        g.rp = S.lrp + S.lrp_off[rid];
-        g.jl = S.jloc[g.A] * o + g.r;
-    }
+    const Col g = make_col(S, J, c, o);
     const int n = g.n;
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
     TX *xaX = reinterpret_cast<TX *>(sm.xa);
     TX *xbX = reinterpret_cast<TX *>(sm.xb);
-    float *xaF = reinterpret_cast<float *>(sm.xa);
-    float *xbF = reinterpret_cast<float *>(sm.xb);
-    double dummy[R];
 
-    // ---------------- inner CG: S_A s = e_j ----------------
     double x[R];
-    int iters = 0, nres = 0, status = 0, start = 0;
-    bool converged = false;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) x[rr] = 0.0;
-    const int nout = kNbOut * o;
-    if (J.x0) {
-        // predicted coefficients on the orbitals of the kNbOut nearest atoms
-        for (int i = tid; i < n; i += NT) sm.xa[i] = 0.0;
-        __syncthreads();
-        for (int e = tid; e < nout; e += NT) {
-            const int k = e / o, cc = e - k * o;
-            const int la = S.out_loc[(int64_t)g.A * kNbOut + k];
-            if (la >= 0) sm.xa[la * o + cc] = (double)J.x0[(int64_t)c * nout + e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            const int i = tid + rr * NT;
-            if (i < n) x[rr] = sm.xa[i];
-        }
-        start = 1;
-        __syncthreads();
-    }
-    if (PREC == 0) {
-        double r[R], p[R], q[R];
-        // r = e_j - S x
-        store_rows<R, double>(sm.xa, x, n);
-        __syncthreads();
-        spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
-        double rho2 = block_sum(dot_rows<R>(r, r, n), sm.red);
-        ++nres;
-        if (start == 1 && !(rho2 < 1.0)) {
-            // the residual judge rejects the predicted start: zero start
-            start = 2;
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                x[rr] = 0.0;
-                r[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
-            }
-            rho2 = 1.0;
-        }
-        for (int restart = 0; restart <= 3 && !converged && status == 0; ++restart) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) p[rr] = r[rr];
-            for (int k = 0; k < n && sqrt(rho2) > J.cg_tol; ++k) {
-                store_rows<R, double>(sm.xa, p, n);
-                __syncthreads();
-                spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
-                const double pq = block_sum(dot_rows<R>(p, q, n), sm.red);
-                if (!(pq > 0.0)) { status = -4; break; }
-                const double alpha = rho2 / pq;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) {
-                    x[rr] += alpha * p[rr];
-                    r[rr] -= alpha * q[rr];
-                }
-                const double rn = block_sum(dot_rows<R>(r, r, n), sm.red);
-                const double beta = rn / rho2;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) p[rr] = r[rr] + beta * p[rr];
-                rho2 = rn;
-                ++iters;
-            }
-            if (status) break;
-            // judge on the true residual
-            store_rows<R, double>(sm.xa, x, n);
-            __syncthreads();
-            spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
-            rho2 = block_sum(dot_rows<R>(r, r, n), sm.red);
-            ++nres;
-            if (sqrt(rho2) <= J.cg_tol) converged = true;
-        }
-    } else {
-        // FP32 CG passes with FP32 accumulation on the FP64 residual,
-        // judged and refined in FP64.
-        double q[R], r64[R];
-        for (int ref = 0; ref <= J.max_refine && status == 0; ++ref) {
-            store_rows<R, double>(sm.xa, x, n);
-            __syncthreads();
-            spmv_rows<O, R, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, sm.xa, sm.xb, dummy, q, dummy);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
-            double rho2 = block_sum(dot_rows<R>(r64, r64, n), sm.red);
-            ++nres;
-            if (ref == 0 && start == 1 && !(rho2 < 1.0)) {
-                // the residual judge rejects the predicted start: zero start
-                start = 2;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) {
-                    x[rr] = 0.0;
-                    r64[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
-                }
-                rho2 = 1.0;
-            }
-            if (sqrt(rho2) <= J.cg_tol) { converged = true; break; }
-            if (ref == J.max_refine) break;
-            const double rho = sqrt(rho2);
-            float rf[R], pf[R], df[R];
-            double qd[R];
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                rf[rr] = (float)(r64[rr] / rho);
-                pf[rr] = rf[rr];
-                df[rr] = 0.0f;
-            }
-            float rrf = 0.0f;
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr)
-                if (tid + rr * NT < n) rrf += rf[rr] * rf[rr];
-            rrf = block_sum(rrf, sm.redf);
-            const float thr = (float)J.inner_tol;
-            for (int k = 0; k < n && sqrtf(rrf) > thr; ++k) {
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr)
-                    if (tid + rr * NT < n) xaF[tid + rr * NT] = pf[rr];
-                __syncthreads();
-                spmv_rows<O, R, float, float, false, true, false>(S, g, o, S.Hf, S.Sf, xaF, xbF, dummy, qd, dummy);
-                float pq = 0.0f;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr)
-                    if (tid + rr * NT < n) pq += pf[rr] * (float)qd[rr];
-                pq = block_sum(pq, sm.redf);
-                if (!(pq > 0.0f)) { status = -4; break; }
-                const float alpha = rrf / pq;
-                float rn = 0.0f;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) {
-                    df[rr] += alpha * pf[rr];
-                    rf[rr] -= alpha * (float)qd[rr];
-                    if (tid + rr * NT < n) rn += rf[rr] * rf[rr];
-                }
-                rn = block_sum(rn, sm.redf);
-                const float beta = rn / rrf;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) pf[rr] = rf[rr] + beta * pf[rr];
-                rrf = rn;
-                ++iters;
-            }
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) x[rr] += rho * (double)df[rr];
-        }
-    }
-    if (status == 0 && !converged) status = -5;
-    if (J.sj_near) {
-        // s_j on the orbitals of the kNbOut nearest atoms (training targets)
-        __syncthreads();
-        store_rows<R, double>(sm.xa, x, n);
-        __syncthreads();
-        for (int e = tid; e < nout; e += NT) {
-            const int k = e / o, cc = e - k * o;
-            const int la = S.out_loc[(int64_t)g.A * kNbOut + k];
-            J.sj_near[(int64_t)c * nout + e] = (status == 0 && la >= 0) ? (float)sm.xa[la * o + cc] : 0.0f;
-        }
-        __syncthreads();
-    }
+    int iters, nres, status, start;
+    inner_cg<O, R, NTG, PREC>(S, J, g, c, sm.xa, sm.xb, sm.red, sm.redf, x, iters, nres, status,
+                              start);
 
     int L = 0;
+    double *mid = J.mid + (int64_t)s * J.mid_stride;
     if (status == 0) {
         // ---------------- basis of K_p(H;e_j) + K_q(H;s_j) ----------------
         double l[R], w[R], hv[R], zv[R], t[R];
@@ -433,30 +566,30 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         // One candidate (Eqs. 6-8): two classical Gram-Schmidt passes with
         // coefficients u_m^T S l, S-normalisation, breakdown test, and
         // acceptance u = l/beta, S u, H u.  With `chain`, also zv = H t.
-        auto append = [&](bool chain) -> bool {
+        auto append = [&](bool chain) __attribute__((always_inline)) -> bool {
             for (int pass = 0; pass < 2; ++pass) {
                 double *cc = pass ? c2 : c1;
-                store_rows<R, double>(sm.xa, l, n);
+                store_rows<R, NTG, double>(sm.xa, l, n);
                 __syncthreads();
                 multidot(SU, ld, L, sm.xa, n, cc);
                 __syncthreads();
                 sub_comb<R>(l, U, ld, L, cc, n);
             }
-            store_rows<R, TX>(xaX, l, n);
-            if (chain) store_rows<R, TX>(xbX, t, n);
+            store_rows<R, NTG, TX>(xaX, l, n);
+            if (chain) store_rows<R, NTG, TX>(xbX, t, n);
             __syncthreads();
             if (chain)
-                spmv_rows<O, R, TM, TX, true, true, true>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
+                spmv_rows<O, R, NTG, TM, TX, true, true, true>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
             else
-                spmv_rows<O, R, TM, TX, true, true, false>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
-            const double bb = block_sum(dot_rows<R>(l, w, n), sm.red);
+                spmv_rows<O, R, NTG, TM, TX, true, true, false>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
+            const double bb = block_sum<NWG>(dot_rows<R, NTG>(l, w, n), sm.red);
             double b0 = bb;
             for (int m = 0; m < L; ++m) b0 += (c1[m] + c2[m]) * (c1[m] + c2[m]);
             if (!(bb > 0.0) || !(b0 > 0.0) || sqrt(bb) <= J.tau * sqrt(b0)) return false;
             const double inv = 1.0 / sqrt(bb);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
-                const int i = tid + rr * NT;
+                const int i = tid + rr * NTG;
                 if (i < n) {
                     U[L * ld + i] = l[rr] * inv;
                     SU[L * ld + i] = w[rr] * inv;
@@ -470,16 +603,16 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
 
         // block 1: seeds e_j, H u_1, H u_2, ...
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) l[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+        for (int rr = 0; rr < R; ++rr) l[rr] = (tid + rr * NTG) == g.jl ? 1.0 : 0.0;
         for (int step = 0; step < J.p; ++step)
             if (!append(false)) break;
 
         // block 2: chain t_1 = s_j / |s_j|, t_{k+1} = H t_k orthonormalised
         if (J.q > 0) {
-            const double ns = sqrt(block_sum(dot_rows<R>(x, x, n), sm.red));
+            const double ns = sqrt(block_sum<NWG>(dot_rows<R, NTG>(x, x, n), sm.red));
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
-                const int i = tid + rr * NT;
+                const int i = tid + rr * NTG;
                 t[rr] = x[rr] / ns;
                 if (i < n) T[i] = t[rr];
             }
@@ -490,19 +623,19 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                 append(!last);
                 if (last) break;
                 // Euclidean Gram-Schmidt of H t_k against t_1..t_k, twice
-                const double eta0 = sqrt(block_sum(dot_rows<R>(zv, zv, n), sm.red));
+                const double eta0 = sqrt(block_sum<NWG>(dot_rows<R, NTG>(zv, zv, n), sm.red));
                 for (int pass = 0; pass < 2; ++pass) {
-                    store_rows<R, double>(sm.xb, zv, n);
+                    store_rows<R, NTG, double>(sm.xb, zv, n);
                     __syncthreads();
                     multidot(T, ld, k + 1, sm.xb, n, c1);
                     __syncthreads();
                     sub_comb<R>(zv, T, ld, k + 1, c1, n);
                 }
-                const double eta = sqrt(block_sum(dot_rows<R>(zv, zv, n), sm.red));
+                const double eta = sqrt(block_sum<NWG>(dot_rows<R, NTG>(zv, zv, n), sm.red));
                 if (!(eta > J.tau * eta0)) break;
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) {
-                    const int i = tid + rr * NT;
+                    const int i = tid + rr * NTG;
                     t[rr] = zv[rr] / eta;
                     if (i < n) T[(k + 1) * ld + i] = t[rr];
                 }
@@ -510,18 +643,18 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
         }
         __syncthreads();   // basis writes visible to the whole workgroup
 
-        // ---------------- projection H~ = U^T K, S~ = U^T SU ----------------
+        // ---------------- Galerkin pair X = U^T K, S~ = U^T SU ----------------
         // Dense L x L products on the FP64 matrix cores: 16 x 16 output tiles,
         // v_mfma_f64_16x16x4f64 over the region rows, one tile per wavefront
         // at a time.  Lane l feeds A[l%16][l/16] = u_m[i] and
         // B[l/16][l%16] = k_n[i] (resp. (S u_n)[i]) and receives
-        // D[4*j + l/16][l%16], j = 0..3.  Both triangles are formed, then
-        // averaged.
-        double *Ht = sm.mat, *St = sm.mat + nu * nu, *Y = sm.mat + 2 * nu * nu;
+        // D[4*j + l/16][l%16], j = 0..3.  Both triangles are written; the
+        // eigensolver symmetrises.
+        double *Xh = mid, *Xs = mid + (int64_t)nu * nu;
         {
             const int w = tid >> 6, lane = tid & 63;
             const int nt = (L + 15) >> 4;
-            for (int tile = w; tile < nt * nt; tile += NW) {
+            for (int tile = w; tile < nt * nt; tile += NWG) {
                 const int mt = tile / nt, ntc = tile - mt * nt;
                 const int m = mt * 16 + (lane & 15), nn = ntc * 16 + (lane & 15);
                 const int kk = lane >> 4;
@@ -530,7 +663,6 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                 const double *kn = K + (int64_t)(nok ? nn : 0) * ld;
                 const double *sn = SU + (int64_t)(nok ? nn : 0) * ld;
                 dbl4 ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
                 for (int i0 = 0; i0 < n; i0 += 4) {
                     const int i = i0 + kk;
                     const bool iok = i < n;
@@ -544,133 +676,352 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                 for (int jj = 0; jj < 4; ++jj) {
                     const int mr = mt * 16 + 4 * jj + kk, nc = ntc * 16 + (lane & 15);
                     if (mr < L && nc < L) {
-                        Y[mr * L + nc] = ah[jj];          // unsymmetrised u_m . k_n
-                        St[mr * L + nc] = as[jj];         // unsymmetrised u_m . S u_n
+                        Xh[mr * nu + nc] = ah[jj];
+                        Xs[mr * nu + nc] = as[jj];
                     }
                 }
             }
         }
-        __syncthreads();
-        for (int e = tid; e < L * L; e += NT) {
-            const int i = e / L, jj = e - i * L;
-            Ht[e] = 0.5 * (Y[i * L + jj] + Y[jj * L + i]);
+        // rows of U the outputs need: u at row j, S u at row j, u at the pattern rows
+        double *Up = mid + 2 * (int64_t)nu * nu;
+        const int64_t kb0 = S.blk_ptr[g.A];
+        const int npat = (int)(S.blk_ptr[g.A + 1] - kb0) * o;
+        for (int e = tid; e < (npat + 2) * L; e += NTG) {
+            const int row = e / L, m = e - row * L;
+            double v;
+            if (row == 0) v = U[m * ld + g.jl];
+            else if (row == 1) v = SU[m * ld + g.jl];
+            else {
+                const int tt = row - 2;
+                v = U[m * ld + S.blk_loc[kb0 + tt / o] * o + (tt % o)];
+            }
+            Up[row * nu + m] = v;
         }
-        __syncthreads();
-        for (int e = tid; e < L * L; e += NT) {
-            const int i = e / L, jj = e - i * L;
-            if (i < jj) {
-                const double v = 0.5 * (St[i * L + jj] + St[jj * L + i]);
-                St[i * L + jj] = v;
-                St[jj * L + i] = v;
+    }
+    if (tid == 0) write_stats(J, c, L, iters, nres, status, start);
+    __syncthreads();
+}
+
+template <int O, int R, int PREC>
+__global__ void __launch_bounds__(NTG) k_basis_g(DevSystem S, DevJob J)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[NWG];
+    __shared__ float redf[NWG];
+    __shared__ int s_idx;
+    SmemG sm;
+    sm.xa = smem;
+    sm.xb = smem + S.nmax;
+    sm.cf = smem + 2 * S.nmax;
+    sm.red = red;
+    sm.redf = redf;
+    const int64_t ld = S.nmax;
+    double *U = J.ws + (int64_t)blockIdx.x * J.ws_stride;
+    double *SU = U + J.nu * ld;
+    double *K = SU + J.nu * ld;
+    double *T = K + J.nu * ld;
+    drain_queues(J, &s_idx, [&](int c, int s) __attribute__((always_inline)) {
+        basis_global<O, R, PREC>(S, J, sm, c, s, U, SU, K, T);
+    });
+}
+
+// ------------------------------------------------------------------------
+// small-region basis kernel: basis on chip
+// ------------------------------------------------------------------------
+// Thread t owns local row t (n <= NT).  U[m] lives in LDS (row stride
+// nmax), S u_m and the chain vectors t_k in the thread's registers.  The
+// Gram-Schmidt dots are per-row partial products reduced with the transposed
+// wavefront reduction; the Galerkin pair is accumulated as each vector is
+// accepted: X[m][L] = u_m^T H u_L (upper triangle, mirrored),
+// S~[m][L] = u_m^T (S u_L) and S~[L][m] = u_L^T (S u_m).
+template <int O, int NT, int NU, int PREC>
+__device__ void basis_small(const DevSystem &S, const DevJob &J, double *Ub, double *xa,
+                            double *xb, double *scratch, double *cf, double *red, float *redf,
+                            int c, int s)
+{
+    using TM = typename std::conditional<PREC != 0, float, double>::type;
+    using TX = typename std::conditional<PREC == 1, float, double>::type;
+    constexpr int NWV = NT / 64;
+    constexpr int NQ = NU / 2;
+    const int o = O ? O : S.o;
+    const int tid = threadIdx.x;
+    const int ldu = S.nmax;
+    const int nu = J.nu;
+    const Col g = make_col(S, J, c, o);
+    const int n = g.n;
+    const bool own = tid < n;
+    const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
+    const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
+    TX *xaX = reinterpret_cast<TX *>(xa);
+    TX *xbX = reinterpret_cast<TX *>(xb);
+
+    double x[1];
+    int iters, nres, status, start;
+    inner_cg<O, 1, NT, PREC>(S, J, g, c, xa, xb, red, redf, x, iters, nres, status, start);
+
+    double *mid = J.mid + (int64_t)s * J.mid_stride;
+    double *Xh = mid, *Xs = mid + (int64_t)nu * nu, *Up = mid + 2 * (int64_t)nu * nu;
+    double SU[NU];   // (S u_m) at this thread's row
+    double Tc[NQ];   // chain vector t_k at this thread's row
+#pragma unroll
+    for (int m = 0; m < NU; ++m) SU[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) Tc[m] = 0.0;
+    int L = 0;
+    if (status == 0) {
+        double l = (tid == g.jl) ? 1.0 : 0.0;
+        double zv = 0.0, t = 0.0;
+        double *c1 = cf, *c2 = cf + NU, *pr = cf + 2 * NU;
+
+        auto append = [&](bool chain) __attribute__((always_inline)) -> bool {
+            for (int pass = 0; pass < 2; ++pass) {
+                double *cc = pass ? c2 : c1;
+                block_reduce<NWV, NU, 1>([&](int, double (&v)[NU]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int m = 0; m < NU; ++m) v[m] = (m < L && own) ? SU[m] * l : 0.0;
+                }, scratch, cc);
+                if (own) {
+                    double acc = 0.0;
+                    for (int m = 0; m < L; ++m) acc += Ub[m * ldu + tid] * cc[m];
+                    l -= acc;
+                }
+            }
+            if (own) {
+                xaX[tid] = (TX)l;
+                if (chain) xbX[tid] = (TX)t;
+            }
+            __syncthreads();
+            double hv1[1], w1[1], z1[1];
+            if (chain)
+                spmv_rows<O, 1, NT, TM, TX, true, true, true>(S, g, o, Hv, Sv, xaX, xbX, hv1, w1, z1);
+            else
+                spmv_rows<O, 1, NT, TM, TX, true, true, false>(S, g, o, Hv, Sv, xaX, xbX, hv1, w1, z1);
+            if (chain) zv = z1[0];
+            const double bb = block_sum<NWV>(own ? l * w1[0] : 0.0, red);
+            double b0 = bb;
+            for (int m = 0; m < L; ++m) b0 += (c1[m] + c2[m]) * (c1[m] + c2[m]);
+            if (!(bb > 0.0) || !(b0 > 0.0) || sqrt(bb) <= J.tau * sqrt(b0)) return false;
+            const double inv = 1.0 / sqrt(bb);
+            const double u = l * inv, su = w1[0] * inv, kk = hv1[0] * inv;
+            if (own) Ub[L * ldu + tid] = u;
+#pragma unroll
+            for (int m = 0; m < NU; ++m) SU[m] = (m == L) ? su : SU[m];
+            // column L of the Galerkin pair
+            block_reduce<NWV, NU, 3>([&](int gi, double (&v)[NU]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int m = 0; m < NU; ++m) {
+                    const bool ok = own && m <= L;
+                    if (gi == 2) {
+                        v[m] = ok ? SU[m] * u : 0.0;
+                    } else {
+                        const double um = ok ? Ub[m * ldu + tid] : 0.0;
+                        v[m] = um * (gi == 0 ? kk : su);
+                    }
+                }
+            }, scratch, pr);
+            for (int m = tid; m <= L; m += NT) {
+                const double h = pr[m];
+                Xh[m * nu + L] = h;
+                Xh[L * nu + m] = h;
+                Xs[m * nu + L] = pr[NU + m];
+                if (m < L) Xs[L * nu + m] = pr[2 * NU + m];
+            }
+            l = kk;   // next block-1 seed: H u_L
+            ++L;
+            return true;
+        };
+
+        // block 1: seeds e_j, H u_1, H u_2, ...
+        for (int step = 0; step < J.p; ++step)
+            if (!append(false)) break;
+
+        // block 2: chain t_1 = s_j / |s_j|, t_{k+1} = H t_k orthonormalised
+        if (J.q > 0) {
+            const double ns = sqrt(block_sum<NWV>(own ? x[0] * x[0] : 0.0, red));
+            t = x[0] / ns;
+            Tc[0] = t;
+            for (int k = 0; k < J.q; ++k) {
+                l = t;
+                const bool last = (k + 1 == J.q);
+                append(!last);
+                if (last) break;
+                // Euclidean Gram-Schmidt of H t_k against t_1..t_k, twice
+                const double eta0 = sqrt(block_sum<NWV>(own ? zv * zv : 0.0, red));
+                for (int pass = 0; pass < 2; ++pass) {
+                    block_reduce<NWV, NQ, 1>([&](int, double (&v)[NQ]) __attribute__((always_inline)) {
+#pragma unroll
+                        for (int m = 0; m < NQ; ++m) v[m] = (m <= k && own) ? Tc[m] * zv : 0.0;
+                    }, scratch, c1);
+                    double acc = 0.0;
+#pragma unroll
+                    for (int m = 0; m < NQ; ++m) acc += (m <= k) ? Tc[m] * c1[m] : 0.0;
+                    zv -= acc;
+                }
+                const double eta = sqrt(block_sum<NWV>(own ? zv * zv : 0.0, red));
+                if (!(eta > J.tau * eta0)) break;
+                t = zv / eta;
+#pragma unroll
+                for (int m = 0; m < NQ; ++m) Tc[m] = (m == k + 1) ? t : Tc[m];
             }
         }
-        if (tid == 0) s_flag = 0;
-        __syncthreads();
+        __syncthreads();   // U complete in LDS
 
-        // ---------------- reduced generalised eigenproblem ----------------
-        // Wavefront 0 alone (L <= 64) computes the Cholesky factor S~ = Lc Lc^T
-        // and the standard form A = Lc^-1 H~ Lc^-T, with wavefront-level
-        // ordering of its LDS traffic instead of workgroup barriers; the
-        // whole workgroup then runs the Jacobi sweeps; wavefront 0 forms
-        // C = Lc^-T Y and the ranks of the eigenvalues.
-        double *ev = sm.cf;                 // L values
-        int *rank = reinterpret_cast<int *>(sm.cf + kMaxNu);
-        if (tid < 64) {
-            const int lane = tid;
-            for (int jj = 0; jj < L; ++jj) {
-                if (lane == 0) {
-                    double sd = St[jj * L + jj];
-                    for (int k = 0; k < jj; ++k) sd -= St[jj * L + k] * St[jj * L + k];
-                    if (!(sd > 0.0)) { s_flag = 1; sd = 1.0; }
-                    St[jj * L + jj] = sqrt(sd);
-                }
-                wave_sync();
-                for (int i = jj + 1 + lane; i < L; i += 64) {
-                    double t2 = St[i * L + jj];
-                    for (int k = 0; k < jj; ++k) t2 -= St[i * L + k] * St[jj * L + k];
-                    St[i * L + jj] = t2 / St[jj * L + jj];
-                }
-                wave_sync();
+        // rows of U the outputs need: u at row j, S u at row j, u at the pattern rows
+        const int64_t kb0 = S.blk_ptr[g.A];
+        const int npat = (int)(S.blk_ptr[g.A + 1] - kb0) * o;
+        for (int e = tid; e < (npat + 1) * L; e += NT) {
+            const int rr = e / L, m = e - rr * L;
+            int i, row;
+            if (rr == 0) {
+                i = g.jl;
+                row = 0;
+            } else {
+                const int tt = rr - 1;
+                i = S.blk_loc[kb0 + tt / o] * o + (tt % o);
+                row = tt + 2;
             }
-            // W = Lc^-1 H~ -> Y (one column per lane)
-            for (int cc = lane; cc < L; cc += 64)
-                for (int i = 0; i < L; ++i) {
-                    double t2 = Ht[i * L + cc];
-                    for (int k = 0; k < i; ++k) t2 -= St[i * L + k] * Y[k * L + cc];
-                    Y[i * L + cc] = t2 / St[i * L + i];
-                }
-            wave_sync();
-            // A = Lc^-1 W^T -> Ht
-            for (int cc = lane; cc < L; cc += 64)
-                for (int i = 0; i < L; ++i) {
-                    double t2 = Y[cc * L + i];
-                    for (int k = 0; k < i; ++k) t2 -= St[i * L + k] * Ht[k * L + cc];
-                    Ht[i * L + cc] = t2 / St[i * L + i];
-                }
-            wave_sync();
-            for (int e = lane; e < L * L; e += 64) {
-                const int i = e / L, jj = e - i * L;
-                if (i < jj) {
-                    const double v = 0.5 * (Ht[i * L + jj] + Ht[jj * L + i]);
-                    Ht[i * L + jj] = v;
-                    Ht[jj * L + i] = v;
-                }
-            }
-            for (int e = lane; e < L * L; e += 64) Y[e] = (e / L == e % L) ? 1.0 : 0.0;
-            wave_sync();
+            Up[row * nu + m] = Ub[m * ldu + i];
+        }
+        if (tid == g.jl) {
+#pragma unroll
+            for (int m = 0; m < NU; ++m)
+                if (m < L) Up[nu + m] = SU[m];
+        }
+    }
+    if (tid == 0) write_stats(J, c, L, iters, nres, status, start);
+    __syncthreads();   // U, xa, xb are reused by the next column
+}
 
+template <int NT, int NU>
+__host__ __device__ constexpr int small_smem_doubles_fixed()
+{
+    return (NT / 64) * 3 * NU + 5 * NU;
+}
+
+template <int O, int NT, int NU, int PREC>
+__global__ void __launch_bounds__(NT) k_basis_s(DevSystem S, DevJob J)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[NT / 64];
+    __shared__ float redf[NT / 64];
+    __shared__ int s_idx;
+    double *Ub = smem;
+    double *xa = Ub + (int64_t)NU * S.nmax;
+    double *xb = xa + S.nmax;
+    double *scratch = xb + S.nmax;
+    double *cf = scratch + (NT / 64) * 3 * NU;
+    drain_queues(J, &s_idx, [&](int c, int s) __attribute__((always_inline)) {
+        basis_small<O, NT, NU, PREC>(S, J, Ub, xa, xb, scratch, cf, red, redf, c, s);
+    });
+}
+
+// ------------------------------------------------------------------------
+// reduced generalised eigenproblems and column outputs (a6, a7)
+// ------------------------------------------------------------------------
+// One wavefront per column of the chunk.  The pair is symmetrised
+// (1/2 (X + X^T)), S~ = Lc Lc^T by Cholesky, A = Lc^-1 H~ Lc^-T, cyclic
+// Jacobi with circle-method rounds of disjoint rotations applied as 2 x 2
+// block updates, C = Lc^-T Y.  Then v_a at row j, (S v_a)_j, the Ritz values
+// in ascending order and the weights w_a = v_ja (S v_a)_j; then either the
+// amplitudes v_ia v_ja at the pattern rows or, with a given chemical
+// potential, rho_ij, pi_ij (Eqs. 13-14) and E_j, N_j (Eq. 17).
+template <typename TA>
+__global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
+{
+    extern __shared__ double smem[];
+    const int nu = J.nu;
+    double *A = smem, *B = smem + nu * nu, *Y = smem + 2 * nu * nu;
+    double *ev = smem + 3 * nu * nu, *vj = ev + kMaxNu, *svj = vj + kMaxNu, *fw = svj + kMaxNu;
+    double *rot = fw + kMaxNu;
+    int *rank = reinterpret_cast<int *>(rot + kMaxNu);
+    int *prs = rank + kMaxNu;
+    int *inv = prs + kMaxNu;
+    __shared__ int s_flag;
+    const int lane = threadIdx.x;
+    const int o = S.o;
+    for (int s = blockIdx.x; s < J.cn; s += gridDim.x) {
+        const int c = J.order[J.c0 + s];
+        const double *mid = J.mid + (int64_t)s * J.mid_stride;
+        const double *Up = mid + 2 * (int64_t)nu * nu;
+        int32_t *st = J.stats + (int64_t)c * kStats;
+        int L = st[3] == 0 ? st[0] : 0;
+        if (lane == 0) s_flag = 0;
+        for (int e = lane; e < L * L; e += 64) {
+            const int i = e / L, k = e - i * L;
+            A[e] = 0.5 * (mid[i * nu + k] + mid[k * nu + i]);
+            B[e] = 0.5 * (mid[nu * nu + i * nu + k] + mid[nu * nu + k * nu + i]);
         }
         __syncthreads();
+        // Cholesky S~ = Lc Lc^T in the lower triangle of B
+        for (int jj = 0; jj < L; ++jj) {
+            if (lane == 0) {
+                double sd = B[jj * L + jj];
+                for (int k = 0; k < jj; ++k) sd -= B[jj * L + k] * B[jj * L + k];
+                if (!(sd > 0.0)) { s_flag = 1; sd = 1.0; }
+                B[jj * L + jj] = sqrt(sd);
+            }
+            __syncthreads();
+            for (int i = jj + 1 + lane; i < L; i += 64) {
+                double t2 = B[i * L + jj];
+                for (int k = 0; k < jj; ++k) t2 -= B[i * L + k] * B[jj * L + k];
+                B[i * L + jj] = t2 / B[jj * L + jj];
+            }
+            __syncthreads();
+        }
+        // W = Lc^-1 H~ -> Y (one column per lane), then A = Lc^-1 W^T
+        for (int cc = lane; cc < L; cc += 64)
+            for (int i = 0; i < L; ++i) {
+                double t2 = A[i * L + cc];
+                for (int k = 0; k < i; ++k) t2 -= B[i * L + k] * Y[k * L + cc];
+                Y[i * L + cc] = t2 / B[i * L + i];
+            }
+        __syncthreads();
+        for (int cc = lane; cc < L; cc += 64)
+            for (int i = 0; i < L; ++i) {
+                double t2 = Y[cc * L + i];
+                for (int k = 0; k < i; ++k) t2 -= B[i * L + k] * A[k * L + cc];
+                A[i * L + cc] = t2 / B[i * L + i];
+            }
+        __syncthreads();
+        for (int e = lane; e < L * L; e += 64) {
+            const int i = e / L, k = e - i * L;
+            if (i < k) {
+                const double v = 0.5 * (A[i * L + k] + A[k * L + i]);
+                A[i * L + k] = v;
+                A[k * L + i] = v;
+            }
+        }
+        for (int e = lane; e < L * L; e += 64) Y[e] = (e / L == e % L) ? 1.0 : 0.0;
+        __syncthreads();
 
-        // Cyclic Jacobi on A (all wavefronts).  Each round applies L2/2
-        // disjoint rotations (circle-method pairing); A <- J^T A J is done as
-        // independent 2x2 block updates (rows of pair k1 x columns of pair
-        // k2), Y <- Y J as independent row pairs, so a round needs only the
-        // barrier after the angles and the one after the updates.
+        // cyclic Jacobi on A, accumulating Y <- Y J
         {
-            double *rot = sm.cf + 2 * kMaxNu;                          // c, s per pair
-            int *prs = reinterpret_cast<int *>(sm.cf + 3 * kMaxNu);   // p, q per pair
             const int L2 = L + (L & 1);
             const int npair = L2 / 2;
-            constexpr int kMaxBlk = (kMaxNu / 2) * (kMaxNu / 2) / NT;   // 4
-            constexpr int kMaxYi = kMaxNu * (kMaxNu / 2) / NT;          // 8
-            int bk1[kMaxBlk], bk2[kMaxBlk], yr[kMaxYi], yk[kMaxYi];
-#pragma unroll
-            for (int u = 0; u < kMaxBlk; ++u) {
-                const int e = tid + u * NT;
-                bk1[u] = e < npair * npair ? e / npair : -1;
-                bk2[u] = e < npair * npair ? e - (e / npair) * npair : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < kMaxYi; ++u) {
-                const int e = tid + u * NT;
-                yr[u] = e < L * npair ? e / npair : -1;
-                yk[u] = e < L * npair ? e - (e / npair) * npair : -1;
-            }
             double off_prev = INFINITY;
             for (int sweep = 0; sweep < 60 && L > 1; ++sweep) {
                 double off = 0.0, fro = 0.0;
-                for (int e = tid; e < L * L; e += NT) {
-                    const double v = Ht[e] * Ht[e];
+                for (int e = lane; e < L * L; e += 64) {
+                    const double v = A[e] * A[e];
                     fro += v;
                     if (e / L != e % L) off += v;
                 }
-                off = block_sum(off, sm.red);
-                fro = block_sum(fro, sm.red);
+                off = wave_sum(off);
+                fro = wave_sum(fro);
                 if (off == 0.0 || off <= 1e-30 * fro) break;
                 // no longer decreasing once at rounding level
                 if (off <= 1e-24 * fro && off > 0.25 * off_prev) break;
                 off_prev = off;
                 for (int round = 0; round < L2 - 1; ++round) {
-                    if (tid < npair) {
-                        const int ia = tid == 0 ? 0 : 1 + (tid - 1 + round) % (L2 - 1);
-                        const int ib = 1 + (L2 - 2 - tid + round) % (L2 - 1);
+                    if (lane < npair) {
+                        const int ia = lane == 0 ? 0 : 1 + (lane - 1 + round) % (L2 - 1);
+                        const int ib = 1 + (L2 - 2 - lane + round) % (L2 - 1);
                         const int pp = min(ia, ib), qq = max(ia, ib);
                         double cs = 1.0, sn = 0.0;
                         if (qq < L) {
-                            const double apq = Ht[pp * L + qq];
+                            const double apq = A[pp * L + qq];
                             if (apq != 0.0) {
-                                const double theta = (Ht[qq * L + qq] - Ht[pp * L + pp]) / (2.0 * apq);
+                                const double theta = (A[qq * L + qq] - A[pp * L + pp]) / (2.0 * apq);
                                 double tt;
                                 if (fabs(theta) > 1e150) tt = 0.5 / theta;
                                 else tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
@@ -678,40 +1029,37 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                                 sn = tt * cs;
                             }
                         }
-                        rot[2 * tid] = cs;
-                        rot[2 * tid + 1] = sn;
-                        prs[2 * tid] = pp;
-                        prs[2 * tid + 1] = qq;
+                        rot[2 * lane] = cs;
+                        rot[2 * lane + 1] = sn;
+                        prs[2 * lane] = pp;
+                        prs[2 * lane + 1] = qq;
                     }
                     __syncthreads();
-#pragma unroll
-                    for (int u = 0; u < kMaxBlk; ++u) {
-                        if (bk1[u] < 0) continue;
-                        const int ra = prs[2 * bk1[u]], rb = prs[2 * bk1[u] + 1];
-                        const int ca = prs[2 * bk2[u]], cb = prs[2 * bk2[u] + 1];
-                        const double c1 = rot[2 * bk1[u]], s1 = rot[2 * bk1[u] + 1];
-                        const double c2 = rot[2 * bk2[u]], s2 = rot[2 * bk2[u] + 1];
+                    for (int e = lane; e < npair * npair; e += 64) {
+                        const int k1 = e / npair, k2 = e - k1 * npair;
+                        const int ra = prs[2 * k1], rb = prs[2 * k1 + 1];
+                        const int ca = prs[2 * k2], cb = prs[2 * k2 + 1];
+                        const double c1 = rot[2 * k1], s1 = rot[2 * k1 + 1];
+                        const double c2 = rot[2 * k2], s2 = rot[2 * k2 + 1];
                         const bool rbo = rb < L, cbo = cb < L;
-                        const double x_ac = Ht[ra * L + ca];
-                        const double x_ad = cbo ? Ht[ra * L + cb] : 0.0;
-                        const double x_bc = rbo ? Ht[rb * L + ca] : 0.0;
-                        const double x_bd = (rbo && cbo) ? Ht[rb * L + cb] : 0.0;
+                        const double x_ac = A[ra * L + ca];
+                        const double x_ad = cbo ? A[ra * L + cb] : 0.0;
+                        const double x_bc = rbo ? A[rb * L + ca] : 0.0;
+                        const double x_bd = (rbo && cbo) ? A[rb * L + cb] : 0.0;
                         // rows (J^T .): a' = c1 a - s1 b, b' = s1 a + c1 b
                         const double y_ac = c1 * x_ac - s1 * x_bc, y_bc = s1 * x_ac + c1 * x_bc;
                         const double y_ad = c1 * x_ad - s1 * x_bd, y_bd = s1 * x_ad + c1 * x_bd;
                         // columns (. J): c' = c2 c - s2 d, d' = s2 c + c2 d
-                        Ht[ra * L + ca] = c2 * y_ac - s2 * y_ad;
-                        if (cbo) Ht[ra * L + cb] = s2 * y_ac + c2 * y_ad;
-                        if (rbo) Ht[rb * L + ca] = c2 * y_bc - s2 * y_bd;
-                        if (rbo && cbo) Ht[rb * L + cb] = s2 * y_bc + c2 * y_bd;
+                        A[ra * L + ca] = c2 * y_ac - s2 * y_ad;
+                        if (cbo) A[ra * L + cb] = s2 * y_ac + c2 * y_ad;
+                        if (rbo) A[rb * L + ca] = c2 * y_bc - s2 * y_bd;
+                        if (rbo && cbo) A[rb * L + cb] = s2 * y_bc + c2 * y_bd;
                     }
-#pragma unroll
-                    for (int u = 0; u < kMaxYi; ++u) {
-                        if (yr[u] < 0) continue;
-                        const int pp = prs[2 * yk[u]], qq = prs[2 * yk[u] + 1];
+                    for (int e = lane; e < L * npair; e += 64) {
+                        const int row = e / npair, k = e - row * npair;
+                        const int pp = prs[2 * k], qq = prs[2 * k + 1];
                         if (qq >= L) continue;
-                        const double cs = rot[2 * yk[u]], sn = rot[2 * yk[u] + 1];
-                        const int row = yr[u];
+                        const double cs = rot[2 * k], sn = rot[2 * k + 1];
                         const double ykp = Y[row * L + pp], ykq = Y[row * L + qq];
                         Y[row * L + pp] = cs * ykp - sn * ykq;
                         Y[row * L + qq] = sn * ykp + cs * ykq;
@@ -720,129 +1068,106 @@ __device__ void solve_column(const DevSystem &S, const DevJob &J, const Smem &sm
                 }
             }
         }
-        if (tid < 64) {
-            const int lane = tid;
-            // eigenvalues and their ascending ranks
-            for (int a = lane; a < L; a += 64) ev[a] = Ht[a * L + a];
-            wave_sync();
-            for (int a = lane; a < L; a += 64) {
-                int rk = 0;
-                const double va = ev[a];
-                for (int bb = 0; bb < L; ++bb)
-                    if (ev[bb] < va || (ev[bb] == va && bb < a)) ++rk;
-                rank[a] = rk;
+        // eigenvalues and their ascending ranks; C = Lc^-T Y -> A
+        for (int a = lane; a < L; a += 64) ev[a] = A[a * L + a];
+        __syncthreads();
+        for (int a = lane; a < L; a += 64) {
+            int rk = 0;
+            const double va = ev[a];
+            for (int bb = 0; bb < L; ++bb)
+                if (ev[bb] < va || (ev[bb] == va && bb < a)) ++rk;
+            rank[a] = rk;
+        }
+        for (int cc = lane; cc < L; cc += 64)
+            for (int i = L - 1; i >= 0; --i) {
+                double t2 = Y[i * L + cc];
+                for (int k = i + 1; k < L; ++k) t2 -= B[k * L + i] * A[k * L + cc];
+                A[i * L + cc] = t2 / B[i * L + i];
             }
-            // C = Lc^-T Y -> Ht
-            for (int cc = lane; cc < L; cc += 64)
-                for (int i = L - 1; i >= 0; --i) {
-                    double t2 = Y[i * L + cc];
-                    for (int k = i + 1; k < L; ++k) t2 -= St[k * L + i] * Ht[k * L + cc];
-                    Ht[i * L + cc] = t2 / St[i * L + i];
+        __syncthreads();
+        if (s_flag) {
+            L = 0;
+            if (lane == 0) {
+                st[0] = 0;
+                st[3] = -4;
+                atomicMin(J.fail, c);
+            }
+        }
+        const double *C = A;
+        // v_a and (S v_a) at row j
+        for (int a = lane; a < L; a += 64) {
+            double v1 = 0.0, v2 = 0.0;
+            for (int m = 0; m < L; ++m) {
+                v1 += Up[m] * C[m * L + a];
+                v2 += Up[nu + m] * C[m * L + a];
+            }
+            vj[a] = v1;
+            svj[a] = v2;
+        }
+        __syncthreads();
+        double *eps_o = J.eps + (int64_t)c * nu, *wts_o = J.wts + (int64_t)c * nu;
+        for (int a = lane; a < nu; a += 64) {
+            if (a < L) {
+                eps_o[rank[a]] = ev[a];
+                wts_o[rank[a]] = vj[a] * svj[a];
+                inv[rank[a]] = a;
+            } else {
+                eps_o[a] = NAN;
+                wts_o[a] = 0.0;
+            }
+        }
+        const int j = J.cols[c];
+        const int At = j / o, r = j - At * o;
+        const int64_t kb0 = S.blk_ptr[At];
+        const int npat = (int)(S.blk_ptr[At + 1] - kb0) * o;
+        if (!J.direct) {
+            TA *amp = reinterpret_cast<TA *>(J.amp) + J.amp_off[c];
+            for (int e = lane; e < npat * nu; e += 64) {
+                const int tt = e / nu, a = e - tt * nu;
+                if (a < L) {
+                    double v = 0.0;
+                    for (int m = 0; m < L; ++m) v += Up[(2 + tt) * nu + m] * C[m * L + a];
+                    amp[tt * nu + rank[a]] = (TA)(v * vj[a]);
+                } else {
+                    amp[tt * nu + a] = (TA)0.0;
                 }
-        }
-        __syncthreads();
-        if (s_flag) status = -4;
-    }
-
-    // ---------------- outputs: Ritz values, weights, amplitudes ----------------
-    double *ev = sm.cf;
-    int *rank = reinterpret_cast<int *>(sm.cf + kMaxNu);
-    double *vj = sm.cf + 2 * kMaxNu, *svj = sm.cf + 3 * kMaxNu;
-    const double *C = sm.mat;
-    if (status != 0) L = 0;
-    for (int a = tid; a < L; a += NT) {
-        double v1 = 0.0, v2 = 0.0;
-        for (int m = 0; m < L; ++m) {
-            v1 += U[m * ld + g.jl] * C[m * L + a];
-            v2 += SU[m * ld + g.jl] * C[m * L + a];
-        }
-        vj[a] = v1;
-        svj[a] = v2;
-    }
-    __syncthreads();
-    double *eps_o = J.eps + (int64_t)c * nu, *wts_o = J.wts + (int64_t)c * nu;
-    for (int a = tid; a < nu; a += NT) {
-        if (a < L) {
-            eps_o[rank[a]] = ev[a];
-            wts_o[rank[a]] = vj[a] * svj[a];
-        } else {
-            eps_o[a] = NAN;
-            wts_o[a] = 0.0;
-        }
-    }
-    const int64_t kb0 = S.blk_ptr[g.A];
-    const int npat = (int)(S.blk_ptr[g.A + 1] - kb0) * o;
-    double *amp = J.amp + (int64_t)c * S.maxpat * nu;
-    for (int e = tid; e < npat * nu; e += NT) {
-        const int tt = e / nu, a = e - tt * nu;
-        if (a < L) {
-            const int i = S.blk_loc[kb0 + tt / o] * o + (tt % o);
-            double v = 0.0;
-            for (int m = 0; m < L; ++m) v += U[m * ld + i] * C[m * L + a];
-            amp[tt * nu + rank[a]] = v * vj[a];
-        } else {
-            amp[tt * nu + a] = 0.0;
-        }
-    }
-    if (tid == 0) {
-        int32_t *st = J.stats + (int64_t)c * kStats;
-        st[0] = L;
-        st[1] = iters;
-        st[2] = nres;
-        st[3] = status;
-        st[4] = start;
-        st[5] = st[6] = st[7] = 0;
-        if (status != 0) atomicMin(J.fail, c);
-    }
-    __syncthreads();
-}
-
-template <int O, int R, int PREC>
-__global__ void __launch_bounds__(NT) k_solve(DevSystem S, DevJob J)
-{
-    extern __shared__ double smem[];
-    __shared__ double red[NW];
-    __shared__ float redf[NW];
-    __shared__ int s_idx;
-    Smem sm;
-    sm.xa = smem;
-    sm.xb = smem + S.nmax;
-    sm.cf = smem + vec_doubles(S.nmax, J.nu);
-    sm.mat = sm.cf + 4 * kMaxNu;
-    sm.red = red;
-    sm.redf = redf;
-    const int64_t ld = S.nmax;
-    double *U = J.ws + (int64_t)blockIdx.x * J.ws_stride;
-    double *SU = U + J.nu * ld;
-    double *K = SU + J.nu * ld;
-    double *T = K + J.nu * ld;
-    // Work queues: queue k serves order[qbounds[k] .. qbounds[k+1]); a
-    // workgroup starts at queue blockIdx.x % nqueues and moves to the next
-    // queue when one is exhausted.  Every queue is visited at most once, so
-    // every workgroup leaves the loop.
-    int qi = 0;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int idx = -1;
-            for (; qi < J.nqueues; ++qi) {
-                const int k = (blockIdx.x + qi) % J.nqueues;
-                const int pos = J.qbounds[k] + atomicAdd(J.queue + k, 1);
-                if (pos < J.qbounds[k + 1]) { idx = pos; break; }
             }
-            s_idx = idx;
+        } else {
+            __syncthreads();
+            for (int k = lane; k < L; k += 64) fw[k] = fermi((ev[inv[k]] - J.mu) / J.kT);
+            __syncthreads();
+            double ep = 0.0, np_ = 0.0;
+            for (int tt = lane; tt < npat; tt += 64) {
+                double sr = 0.0, sp = 0.0;
+                for (int k = 0; k < L; ++k) {
+                    const int a = inv[k];
+                    double v = 0.0;
+                    for (int m = 0; m < L; ++m) v += Up[(2 + tt) * nu + m] * C[m * L + a];
+                    const double am = v * vj[a];
+                    sr += fw[k] * am;
+                    sp += (fw[k] * ev[a]) * am;
+                }
+                const int64_t slot = ((kb0 + tt / o) * o + r) * o + (tt % o);
+                if (J.rho) J.rho[slot] = sr;
+                if (J.pi) J.pi[slot] = sp;
+                ep += sr * S.Hd[slot];
+                np_ += sr * S.Sd[slot];
+            }
+            ep = wave_sum(ep);
+            np_ = wave_sum(np_);
+            if (lane == 0) {
+                J.Ecol[c] = ep;
+                J.Ncol[c] = np_;
+            }
         }
-        __syncthreads();
-        const int idx = s_idx;
-        __syncthreads();
-        if (idx < 0) break;
-        solve_column<O, R, PREC>(S, J, sm, J.order[idx], U, SU, K, T);
+        __syncthreads();   // LDS is reused by the next column
     }
 }
 
-__global__ void k_reset(int *queue, int *fail)
+__global__ void k_reset(int *queue, int *fail, int reset_fail)
 {
     for (int k = 0; k < kMaxQueues; ++k) queue[k] = 0;
-    fail[0] = INT_MAX;
+    if (reset_fail) fail[0] = INT_MAX;
 }
 
 // ------------------------------------------------------------------------
@@ -940,14 +1265,16 @@ __global__ void k_bracket(const double *partial, int nblocks, double n_target, d
 }
 
 // rho, pi at the pattern slots of each column (Eqs. 13-14) and
-// E_j = sum_i rho_ij H_ji, N_j = sum_i rho_ij S_ji (Eq. 17).
-__global__ void __launch_bounds__(128) k_rho(DevSystem S, DevJob J, const double *mu_ptr, double mu_in,
+// E_j = sum_i rho_ij H_ji, N_j = sum_i rho_ij S_ji (Eq. 17), from the stored
+// amplitudes at the midpoint of the final bracket.
+template <typename TA>
+__global__ void __launch_bounds__(128) k_rho(DevSystem S, DevJob J, const double *mu_ptr,
                                              double kT, double *rho, double *pi, double *Ecol,
                                              double *Ncol)
 {
     __shared__ double f[kMaxNu], fe[kMaxNu];
     __shared__ double red[2][2];
-    const double mu = mu_ptr ? 0.5 * (mu_ptr[0] + mu_ptr[1]) : mu_in;
+    const double mu = 0.5 * (mu_ptr[0] + mu_ptr[1]);
     const int o = S.o, nu = J.nu;
     for (int c = blockIdx.x; c < J.ncols; c += gridDim.x) {
         const int j = J.cols[c];
@@ -962,13 +1289,14 @@ __global__ void __launch_bounds__(128) k_rho(DevSystem S, DevJob J, const double
         __syncthreads();
         const int64_t kb0 = S.blk_ptr[A];
         const int npat = (int)(S.blk_ptr[A + 1] - kb0) * o;
-        const double *amp = J.amp + (int64_t)c * S.maxpat * nu;
+        const TA *amp = reinterpret_cast<const TA *>(J.amp) + J.amp_off[c];
         double ep = 0.0, np_ = 0.0;
         for (int t = threadIdx.x; t < npat; t += blockDim.x) {
             double sr = 0.0, sp = 0.0;
             for (int a = 0; a < L; ++a) {
-                sr += f[a] * amp[t * nu + a];
-                sp += fe[a] * amp[t * nu + a];
+                const double am = (double)amp[t * nu + a];
+                sr += f[a] * am;
+                sp += fe[a] * am;
             }
             const int64_t slot = ((kb0 + t / o) * o + r) * o + (t % o);
             if (rho) rho[slot] = sr;
@@ -1019,81 +1347,149 @@ __global__ void __launch_bounds__(1024) k_sum2(const double *a, const double *b,
     }
 }
 
-template <int O, int R, int PREC>
-hipError_t launch_solve_t(const DevSystem &S, const DevJob &J, int slots, hipStream_t st)
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+template <typename K>
+hipError_t launch_with_smem(K kern, int grid, int block, size_t smem, hipStream_t st,
+                            const DevSystem &S, const DevJob &J)
 {
-    const size_t smem = solve_smem_bytes(S.nmax, J.nu);
-    auto kern = k_solve<O, R, PREC>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(slots), dim3(NT), smem, st, S, J);
-    return hipGetLastError();
+    DevSystem s_arg = S;
+    DevJob j_arg = J;
+    void *args[] = {&s_arg, &j_arg};
+    return hipLaunchKernel((const void *)kern, dim3(grid), dim3(block), args, smem, st);
 }
 
-template <int O, int R, int PREC>
-hipError_t occupancy_t(const DevSystem &S, const DevJob &J, int *bpc)
+template <typename K>
+hipError_t occupancy_of(K kern, int block, size_t smem, int *bpc)
 {
-    const size_t smem = solve_smem_bytes(S.nmax, J.nu);
-    auto kern = k_solve<O, R, PREC>;
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, kern, NT, smem);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, kern, block, smem);
 }
 
-#define MA_DISPATCH_R(FN, O, PREC, ...)                                   \
-    switch (R) {                                                          \
-    case 1: return FN<O, 1, PREC>(__VA_ARGS__);                           \
-    case 2: return FN<O, 2, PREC>(__VA_ARGS__);                           \
-    case 3: return FN<O, 3, PREC>(__VA_ARGS__);                           \
-    case 4: return FN<O, 4, PREC>(__VA_ARGS__);                           \
-    case 6: return FN<O, 6, PREC>(__VA_ARGS__);                           \
-    default: return FN<O, 8, PREC>(__VA_ARGS__);                          \
+int small_threads(int nmax) { return nmax <= 256 ? 256 : 512; }
+int small_nu_cap(int nu) { return nu <= 16 ? 16 : 32; }
+
+// Dispatch of the small-region kernel: O in {4, generic} x NT x NU x PREC.
+template <int O, int NT, int NU>
+void *small_kernel_p(int prec)
+{
+    if (prec == 1) return (void *)k_basis_s<O, NT, NU, 1>;
+    if (prec == 2) return (void *)k_basis_s<O, NT, NU, 2>;
+    return (void *)k_basis_s<O, NT, NU, 0>;
+}
+
+void *small_kernel(int o, int nt, int nucap, int prec)
+{
+    if (o == 4) {
+        if (nt == 256) return nucap == 16 ? small_kernel_p<4, 256, 16>(prec) : small_kernel_p<4, 256, 32>(prec);
+        return nucap == 16 ? small_kernel_p<4, 512, 16>(prec) : small_kernel_p<4, 512, 32>(prec);
     }
+    if (nt == 256) return nucap == 16 ? small_kernel_p<0, 256, 16>(prec) : small_kernel_p<0, 256, 32>(prec);
+    return nucap == 16 ? small_kernel_p<0, 512, 16>(prec) : small_kernel_p<0, 512, 32>(prec);
+}
 
-#define MA_DISPATCH_P(FN, O, ...)                                         \
-    if (J.precision == 1) { MA_DISPATCH_R(FN, O, 1, __VA_ARGS__) }       \
-    else if (J.precision == 2) { MA_DISPATCH_R(FN, O, 2, __VA_ARGS__) }  \
-    else { MA_DISPATCH_R(FN, O, 0, __VA_ARGS__) }
+template <int O, int R>
+void *global_kernel_r(int prec)
+{
+    if (prec == 1) return (void *)k_basis_g<O, R, 1>;
+    if (prec == 2) return (void *)k_basis_g<O, R, 2>;
+    return (void *)k_basis_g<O, R, 0>;
+}
 
-#define MA_DISPATCH(FN, ...)                                              \
-    const int R = solve_rows_per_thread(S.nmax);                          \
-    if (S.o == 4) { MA_DISPATCH_P(FN, 4, __VA_ARGS__) }                   \
-    else if (S.o == 9) { MA_DISPATCH_P(FN, 9, __VA_ARGS__) }              \
-    else { MA_DISPATCH_P(FN, 0, __VA_ARGS__) }
+template <int O>
+void *global_kernel_o(int R, int prec)
+{
+    switch (R) {
+    case 1: return global_kernel_r<O, 1>(prec);
+    case 2: return global_kernel_r<O, 2>(prec);
+    case 3: return global_kernel_r<O, 3>(prec);
+    case 4: return global_kernel_r<O, 4>(prec);
+    case 6: return global_kernel_r<O, 6>(prec);
+    default: return global_kernel_r<O, 8>(prec);
+    }
+}
+
+void *global_kernel(int o, int R, int prec)
+{
+    if (o == 4) return global_kernel_o<4>(R, prec);
+    if (o == 9) return global_kernel_o<9>(R, prec);
+    return global_kernel_o<0>(R, prec);
+}
+
+typedef void (*basis_fn)(DevSystem, DevJob);
 
 }  // namespace
 
-int solve_rows_per_thread(int nmax)
+bool basis_small_fits(int nmax, int nu, int q, int o)
 {
-    const int r = (nmax + NT - 1) / NT;
+    (void)o;
+    if (nmax > kSmallRows || nu > 32) return false;
+    const int nucap = small_nu_cap(nu);
+    if (q > nucap / 2) return false;
+    return basis_smem_bytes(nmax, nu, true) <= 160 * 1024;
+}
+
+int basis_rows_per_thread(int nmax)
+{
+    const int r = (nmax + NTG - 1) / NTG;
     if (r <= 4) return r < 1 ? 1 : r;
     if (r <= 6) return 6;
     return 8;
 }
 
-// LDS: vector area (the two SpMV inputs, or the projection tiles), the
-// coefficient area and the three nu x nu matrices.
-size_t solve_smem_bytes(int nmax, int nu)
+size_t basis_smem_bytes(int nmax, int nu, bool small)
 {
-    return sizeof(double) * ((size_t)vec_doubles(nmax, nu) + 4 * kMaxNu + 3 * nu * nu);
+    if (small) {
+        const int nt = small_threads(nmax), nucap = small_nu_cap(nu);
+        return sizeof(double) * ((size_t)nucap * nmax + 2 * (size_t)nmax + (nt / 64) * 3 * nucap + 5 * nucap);
+    }
+    return sizeof(double) * (2 * (size_t)nmax + 4 * kMaxNu);
 }
 
-hipError_t launch_reset(int *queue, int *fail, hipStream_t st)
+hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, queue, fail);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, queue, fail, reset_fail);
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const DevSystem &S, const DevJob &J, int slots, hipStream_t st)
+hipError_t launch_basis(const DevSystem &S, const DevJob &J, bool small, int slots, hipStream_t st)
 {
-    MA_DISPATCH(launch_solve_t, S, J, slots, st)
+    const size_t smem = basis_smem_bytes(S.nmax, J.nu, small);
+    if (small) {
+        const int nt = small_threads(S.nmax);
+        basis_fn k = (basis_fn)small_kernel(S.o, nt, small_nu_cap(J.nu), J.precision);
+        return launch_with_smem(k, slots, nt, smem, st, S, J);
+    }
+    basis_fn k = (basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision);
+    return launch_with_smem(k, slots, NTG, smem, st, S, J);
 }
 
-hipError_t solve_occupancy(const DevSystem &S, const DevJob &J, int *bpc)
+hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, bool small, int *bpc)
 {
-    MA_DISPATCH(occupancy_t, S, J, bpc)
+    const size_t smem = basis_smem_bytes(S.nmax, J.nu, small);
+    if (small) {
+        const int nt = small_threads(S.nmax);
+        return occupancy_of((basis_fn)small_kernel(S.o, nt, small_nu_cap(J.nu), J.precision), nt,
+                            smem, bpc);
+    }
+    return occupancy_of((basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision),
+                        NTG, smem, bpc);
+}
+
+hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
+{
+    const size_t smem = sizeof(double) * (3 * (size_t)J.nu * J.nu + 5 * kMaxNu) +
+                        sizeof(int) * 3 * kMaxNu;
+    const int grid = J.cn < (1 << 20) ? J.cn : (1 << 20);
+    if (grid < 1) return hipSuccess;
+    if (J.precision == 0) return launch_with_smem(k_eig<double>, grid, 64, smem, st, S, J);
+    return launch_with_smem(k_eig<float>, grid, 64, smem, st, S, J);
 }
 
 hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int nu, double kT,
@@ -1116,13 +1512,16 @@ hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *st
     return hipGetLastError();
 }
 
-hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr, double mu,
-                      double kT, double *rho, double *pi, double *Ecol, double *Ncol,
-                      hipStream_t st)
+hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr, double kT,
+                      double *rho, double *pi, double *Ecol, double *Ncol, hipStream_t st)
 {
     const int grid = J.ncols < 65536 ? J.ncols : 65536;
-    hipLaunchKernelGGL(k_rho, dim3(grid), dim3(128), 0, st, S, J, mu_ptr, mu, kT, rho, pi, Ecol,
-                       Ncol);
+    if (J.precision == 0)
+        hipLaunchKernelGGL(k_rho<double>, dim3(grid), dim3(128), 0, st, S, J, mu_ptr, kT, rho, pi,
+                           Ecol, Ncol);
+    else
+        hipLaunchKernelGGL(k_rho<float>, dim3(grid), dim3(128), 0, st, S, J, mu_ptr, kT, rho, pi,
+                           Ecol, Ncol);
     return hipGetLastError();
 }
 

@@ -86,13 +86,14 @@ def _compare(s, ora, cols, gpu, rho_tol, e_tol, mu_tol=1e-9):
     return d_rho, d_e
 
 
-def test_fp64_diamond64_all_columns_bisected(ctx, torch_cuda):
+@pytest.mark.parametrize("kernel", ["onchip", "workspace"])
+def test_fp64_diamond64_all_columns_bisected(ctx, torch_cuda, kernel):
     import oracle
     s = synth.config_diamond64()
-    _say("diamond64 fp64 build")
+    _say(f"diamond64 fp64 build ({kernel} basis)")
     ctx.build_tb(s)
     _say("diamond64 fp64 solve, 256 columns, mu bisected")
-    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT)
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
     ora = oracle.solve(s)
     _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL, mu_tol=1e-10)
     # Ritz values and weights per column
@@ -124,18 +125,19 @@ def test_fp64_breakdown_identity_overlap(ctx, torch_cuda):
     _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda):
+@pytest.mark.parametrize("kernel", ["onchip", "workspace"])
+def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda, kernel):
     """Full-size 4,096-atom system, regions of 120 atoms (480 orbitals),
     p = q = 15, a seeded sample of columns spanning every orbital type."""
     import oracle
     s = synth.config_diamond4096()
-    _say("diamond4096 build")
+    _say(f"diamond4096 build ({kernel} basis)")
     ctx.build_tb(s)
     rng = np.random.default_rng(7)
     cols = np.sort(np.concatenate([rng.choice(s.M, 190, replace=False), [8178, 8179]]))
     cols = np.unique(cols).astype(np.int32)
     _say(f"diamond4096 fp64 solve {len(cols)} sampled columns")
-    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT)
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.95, s.kT, basis_kernel=kernel)
     ora = oracle.solve(s, cols=cols, mu=0.95)
     _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
@@ -182,13 +184,15 @@ def _compare_mixed(s, raw, cols, gpu, mu_oracle, prec):
     assert d_pi <= MIXED_RHO_TOL[prec] * max(1.0, np.abs(pi_o).max())
 
 
+@pytest.mark.parametrize("kernel", ["onchip", "workspace"])
 @pytest.mark.parametrize("prec", ["mixed", "mixed_f64acc"])
-def test_mixed_diamond64(ctx, torch_cuda, prec):
+def test_mixed_diamond64(ctx, torch_cuda, prec, kernel):
     import oracle
     s = synth.config_diamond64()
     ctx.build_tb(s)
-    _say(f"diamond64 {prec}")
-    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, precision=prec)
+    _say(f"diamond64 {prec} ({kernel} basis)")
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, precision=prec,
+                     basis_kernel=kernel)
     raw = oracle.solve_raw(s)
     _compare_mixed(s, raw, None, gpu, oracle.find_mu(raw, s.kT, s.n_target), prec)
 
@@ -205,6 +209,76 @@ def test_mixed_diamond4096_sampled(ctx, torch_cuda, prec):
     _compare_mixed(s, raw, cols, gpu, 0.95, prec)
 
 
+def test_given_mu_matches_bisected_path(ctx, torch_cuda):
+    """With the chemical potential given, the eigensolver kernel writes rho,
+    pi and E_j directly; at the bisected mu this equals the stored-amplitude
+    path of the bisection."""
+    s = synth.config_diamond64()
+    ctx.build_tb(s)
+    for kernel in ["onchip", "workspace"]:
+        _say(f"diamond64 bisected vs given mu ({kernel} basis)")
+        a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
+        b = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, a[0].mu, s.kT, basis_kernel=kernel)
+        assert b[0].mu == a[0].mu
+        assert np.abs(a[1] - b[1]).max() <= 1e-14
+        assert np.abs(a[2] - b[2]).max() <= 1e-13
+        assert abs(a[0].energy - b[0].energy) <= 1e-12 * abs(a[0].energy)
+        assert np.array_equal(a[3], b[3], equal_nan=True)
+
+
+def test_chunked_solve_matches_single_chunk(ctx, torch_cuda):
+    """Columns split into several chunks (eager launches, per-chunk queues and
+    chunk buffer reuse) give the single-chunk result bit for bit."""
+    s = synth.config_diamond4096()
+    ctx.build_tb(s)
+    cols = np.arange(0, s.M, 11, dtype=np.int32)
+    for kernel in ["onchip", "workspace"]:
+        _say(f"diamond4096 {len(cols)} columns, chunks of 97 vs one chunk ({kernel} basis)")
+        a = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
+        b = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, math.nan, s.kT, basis_kernel=kernel,
+                       chunk_columns=97)
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert a[0].energy == b[0].energy and a[0].mu == b[0].mu
+        assert np.array_equal(a[5], b[5])
+
+
+def test_onchip_and_workspace_kernels_agree(ctx, torch_cuda):
+    """The two basis kernels (same method, different storage and reduction
+    order) agree to rounding on a whole 4,096-atom solve."""
+    s = synth.config_diamond4096()
+    ctx.build_tb(s)
+    _say("diamond4096 all columns, onchip vs workspace basis")
+    a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel="onchip")
+    b = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel="workspace")
+    d = np.abs(a[1] - b[1]).max()
+    _say(f"max|drho| {d:.3e}, energies {a[0].energy:.12f} {b[0].energy:.12f}")
+    assert np.array_equal(a[5][:, 0], b[5][:, 0])
+    assert d <= 1e-10
+    assert abs(a[0].energy - b[0].energy) <= 1e-12 * abs(a[0].energy)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f64acc"])
+def test_fcc_spd_regions(ctx, torch_cuda, prec):
+    """spd fcc metal (9 orbitals per atom), regions of radius 7 A (about 83
+    atoms, about 750 orbitals, beyond the on-chip kernel), p = q = 15,
+    kT = 0.2: a seeded sample of columns on a 4x4x4-cell piece of the
+    262,144-atom configuration."""
+    import oracle
+    s = synth.config_fcc_spd(cells=(4, 4, 4))
+    _say(f"fcc spd {s.n_atoms} atoms build")
+    ctx.build_tb(s)
+    info = ctx.info()
+    cols = np.sort(np.random.default_rng(17).choice(s.M, 72, replace=False)).astype(np.int32)
+    _say(f"fcc spd {prec} {len(cols)} columns, nmax {info['nmax']}")
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.3, s.kT, precision=prec)
+    if prec == "fp64":
+        ora = oracle.solve(s, cols=cols, mu=0.3)
+        _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
+    else:
+        raw = oracle.solve_raw(s, cols)
+        _compare_mixed(s, raw, cols, gpu, 0.3, prec)
+
+
 def test_invalid_arguments_rejected(ctx, torch_cuda):
     import paper_1202_0098_amd as ma
     s = synth.config_diamond64()
@@ -217,6 +291,15 @@ def test_invalid_arguments_rejected(ctx, torch_cuda):
         ctx.solve_columns(np.array([s.M], np.int32), 4, 4, mu=0.0, kT=0.1)
     with pytest.raises(ma.MarnoldiError):
         ctx.solve_columns(np.array([0], np.int32), 4, 4, mu=0.0, kT=0.0)
+    with pytest.raises(ma.MarnoldiError):
+        ctx.solve_columns(np.array([0], np.int32), 4, 4, mu=0.0, kT=0.1,
+                          opts=ma.default_opts(basis_kernel=7))
+    big = synth.config_disordered8000(3001)
+    ctx.build_tb(big)
+    with pytest.raises(ma.MarnoldiError) as ei:   # regions of up to 1,040 orbitals
+        ctx.solve_columns(np.array([0], np.int32), 20, 20, mu=0.0, kT=0.1,
+                          opts=ma.default_opts(basis_kernel="onchip"))
+    assert ei.value.status == ma.MA_EINVAL
     bad = synth.config_diamond4096(nrp=3)
     with pytest.raises(ma.MarnoldiError) as ei:
         ctx.build_tb(bad)
