@@ -43,8 +43,10 @@ def workload(name):
         return synth.config_diamond64()
     if name == "disordered8000":
         return synth.config_disordered8000()
-    if name.startswith("fcc_spd"):
+    if name == "fcc_spd":
         return synth.config_fcc_spd()
+    if name == "fcc_spd16384":
+        return synth.config_fcc_spd(cells=(16, 16, 16))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -57,7 +59,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_f64acc"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="",
-                    help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE' instead of the autotuner")
+                    help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE[,BASIS_KERNEL]' instead of "
+                         "the autotuner")
     ap.add_argument("--no-graph", action="store_true", help="launch without hipGraph replay")
     ap.add_argument("--basis-kernel", default="auto", choices=["auto", "onchip", "workspace"],
                     help="basis kernel: on-chip basis (regions up to 512 orbitals) or workspace")
@@ -77,8 +80,10 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    t_gen = time.perf_counter()
     s = workload(args.workload)
-    log(f"workload {s.name}: atoms={s.n_atoms} M={s.M} blocks={s.nblk} p={s.p} q={s.q}")
+    log(f"workload {s.name}: atoms={s.n_atoms} M={s.M} blocks={s.nblk} p={s.p} q={s.q} "
+        f"(generated in {time.perf_counter() - t_gen:.1f} s)")
     ctx = ma.Context(0)
     t0 = time.perf_counter()
     ctx.build_tb(s)
@@ -95,22 +100,30 @@ def main():
                            basis_kernel=args.basis_kernel)
     tuning = None
     if args.tuning:
-        slots, sched = args.tuning.split(",")
-        ctx.set_tuning(s.p, s.q, args.precision, int(slots), sched)
-        tuning = {"slots_per_cu": int(slots), "schedule": sched}
+        slots, sched = args.tuning.split(",")[:2]
+        kern = args.tuning.split(",")[2] if args.tuning.count(",") >= 2 else args.basis_kernel
+        ctx.set_tuning(s.p, s.q, args.precision, int(slots), sched, kern)
+        tuning = {"slots_per_cu": int(slots), "schedule": sched, "basis_kernel": kern}
         log(f"fixed tuning {tuning}")
     elif not args.no_autotune:
         t0 = time.perf_counter()
-        first = ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
-        tuning = ctx.autotune(None, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
-        log(f"autotune ({time.perf_counter() - t0:.1f}s): {tuning['slots_per_cu']} slots/CU, "
-            f"schedule {tuning['schedule']}, column kernel {tuning['best_ms']:.2f} ms; "
-            f"tried {[(a, b, round(c, 2)) for a, b, c in tuning['tried']]}")
+        # large systems: tune on a seeded sample of 65,536 columns
+        tcols = None
+        if s.M > 65536:
+            tcols = np.sort(np.random.default_rng(99).choice(s.M, 65536, replace=False)).astype(np.int32)
+        first = ctx.solve_columns(tcols, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
+        log(f"first solve {first.elapsed_ms:.1f} ms (mu {first.mu:.6f}); autotuning")
+        tuning = ctx.autotune(tcols, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
+        log(f"autotune ({time.perf_counter() - t0:.1f}s): {tuning['basis_kernel']} basis kernel, "
+            f"{tuning['slots_per_cu']} slots/CU, schedule {tuning['schedule']}, "
+            f"{tuning['best_ms']:.2f} ms; tried "
+            f"{[(k, a, b, round(c, 2)) for a, b, c, k in tuning['tried']]}")
 
     def step():
         return ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts,
                                  rho=rho, pi=pi, col_stats=stats)
 
+    log("warmup")
     for w in range(args.warmup):
         r = step()
         log(f"warmup {w}: {r.elapsed_ms:.2f} ms (basis {r.kernel_ms:.2f} ms, eig {r.eig_ms:.2f} ms) E={r.energy:.6f} "
@@ -122,6 +135,8 @@ def main():
         r = step()
         kernel_ms.append(r.kernel_ms)
         eig_ms.append(r.eig_ms)
+        if s.M > 65536:
+            log(f"step {k}: {r.elapsed_ms:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
@@ -161,7 +176,8 @@ def main():
 
     # ---- CPU baseline: the oracle on a bounded sample ----------------------
     cpu = None
-    sample = min(s.M, 16384) if args.cpu_sample < 0 else min(args.cpu_sample, s.M)
+    default_sample = 16384 if s.n_orb <= 4 else 4096   # about 10-30 s on 16 host cores
+    sample = min(s.M, default_sample) if args.cpu_sample < 0 else min(args.cpu_sample, s.M)
     if sample > 0:
         import oracle
         cols = np.sort(np.random.default_rng(12345).choice(s.M, sample,
@@ -195,7 +211,8 @@ def main():
                    "build_s": round(build_s, 3), "hipgraph": not args.no_graph,
                    "basis_kernel": args.basis_kernel,
                    "tuning": None if tuning is None else {
-                       "slots_per_cu": tuning["slots_per_cu"], "schedule": tuning["schedule"]}},
+                       "slots_per_cu": tuning["slots_per_cu"], "schedule": tuning["schedule"],
+                       "basis_kernel": tuning["basis_kernel"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

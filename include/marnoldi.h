@@ -169,11 +169,13 @@ typedef struct {
 typedef struct {
     int32_t slots_per_cu;       /* chosen */
     int32_t schedule;           /* chosen */
-    double best_ms;             /* column-kernel time of the chosen configuration */
+    double best_ms;             /* basis-kernel time of the chosen configuration */
     int32_t n_tried;
     int32_t tried_slots[64];
     int32_t tried_schedule[64];
-    double tried_ms[64];        /* column-kernel time of each candidate (best of reps) */
+    double tried_ms[64];        /* basis-kernel time of each candidate (best of reps) */
+    int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP or MA_BASIS_WORKSPACE */
+    int32_t tried_kernel[64];
 } ma_tuning;
 
 /* Library version string. */
@@ -275,19 +277,22 @@ MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, c
 MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
                                    int64_t n, float lr, double *loss);
 
-/* Autotuner: time the column kernel on cols[0..ncols) (NULL = all) for every
- * candidate (slots per CU from 1 to the occupancy limit, x every schedule),
+/* Autotuner: time the basis kernel on cols[0..ncols) (NULL = all) for every
+ * candidate -- basis kernel (on-chip when the shape fits, and workspace) x
+ * slots per CU from 1 to that kernel's occupancy limit x every schedule --
  * `reps` times each at chemical potential mu (finite), and keep the fastest
  * configuration for this (p, q, opts->precision) in the context; solves with
- * slots_per_cu = 0 and schedule = -1 then use it.  Outputs (rho, pi) are not
- * written. */
+ * basis_kernel = MA_BASIS_AUTO, slots_per_cu = 0 and schedule = -1 then use
+ * it.  Outputs (rho, pi) are not written. */
 MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
                              int32_t q, double mu, double kT, const ma_opts *opts, int32_t reps,
                              ma_tuning *out);
 
-/* Store a previously found tuning for (p, q, precision) (e.g. from a cache). */
+/* Store a previously found tuning for (p, q, precision) (e.g. from a cache);
+ * basis_kernel is MA_BASIS_ONCHIP or MA_BASIS_WORKSPACE (MA_BASIS_AUTO keeps
+ * the automatic choice). */
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
-                               int32_t slots_per_cu, int32_t schedule);
+                               int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel);
 
 #ifdef __cplusplus
 }

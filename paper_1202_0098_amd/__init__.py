@@ -64,7 +64,8 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("slots_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("n_tried", ctypes.c_int32),
                 ("tried_slots", ctypes.c_int32 * 64), ("tried_schedule", ctypes.c_int32 * 64),
-                ("tried_ms", ctypes.c_double * 64)]
+                ("tried_ms", ctypes.c_double * 64), ("basis_kernel", ctypes.c_int32),
+                ("tried_kernel", ctypes.c_int32 * 64)]
 
 
 SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
@@ -103,6 +104,9 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise MarnoldiError(MA_ESTATE, f"{LIB_PATH} is missing: run __graft_entry__.build() "
                             "(or python paper_1202_0098_amd/build.py)")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so the process holds one runtime (and the caller's streams are its streams)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.ma_version.restype = ctypes.c_char_p
@@ -121,7 +125,7 @@ def load_library():
     lib.ma_region_atoms.restype = ctypes.c_int64
     lib.ma_autotune.argtypes = [P, i64, P, i32, i32, f64, f64, ctypes.POINTER(_Opts), i32,
                                 ctypes.POINTER(_Tuning)]
-    lib.ma_set_tuning.argtypes = [P, i32, i32, i32, i32, i32]
+    lib.ma_set_tuning.argtypes = [P, i32, i32, i32, i32, i32, i32]
     lib.ma_mlp_shape_of.argtypes = [P, ctypes.POINTER(_MlpShape)]
     lib.ma_mlp_init.argtypes = [P, ctypes.c_uint64]
     lib.ma_mlp_set_params.argtypes = [P, P, i64]
@@ -282,14 +286,18 @@ class Context:
         self._check(self._lib.ma_autotune(self._h, n, cptr, int(p), int(q), float(mu), float(kT),
                                           ctypes.byref(o), int(reps), ctypes.byref(t)))
         names = {v: k for k, v in SCHEDULES.items()}
+        knames = {v: k for k, v in BASIS_KERNELS.items()}
         return dict(slots_per_cu=t.slots_per_cu, schedule=names[t.schedule], best_ms=t.best_ms,
-                    tried=[(t.tried_slots[i], names[t.tried_schedule[i]], t.tried_ms[i])
-                           for i in range(t.n_tried)])
+                    basis_kernel=knames[t.basis_kernel],
+                    tried=[(t.tried_slots[i], names[t.tried_schedule[i]], t.tried_ms[i],
+                            knames[t.tried_kernel[i]]) for i in range(t.n_tried)])
 
-    def set_tuning(self, p, q, precision, slots_per_cu, schedule):
+    def set_tuning(self, p, q, precision, slots_per_cu, schedule, basis_kernel="auto"):
         prec = PREC[precision] if isinstance(precision, str) else int(precision)
         sch = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
-        self._check(self._lib.ma_set_tuning(self._h, int(p), int(q), prec, int(slots_per_cu), sch))
+        kern = BASIS_KERNELS[basis_kernel] if isinstance(basis_kernel, str) else int(basis_kernel)
+        self._check(self._lib.ma_set_tuning(self._h, int(p), int(q), prec, int(slots_per_cu), sch,
+                                            kern))
 
     # ---- learned CG start ----------------------------------------------------
     def mlp_shape(self):

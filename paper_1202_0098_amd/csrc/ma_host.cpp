@@ -140,7 +140,7 @@ struct ma_ctx {
     std::vector<unsigned char> gkey;
 
     // autotuned (slots per CU, schedule) per (p, q, precision)
-    struct Tune { int p, q, prec, slots, sched; };
+    struct Tune { int p, q, prec, slots, sched, kernel; };
     std::vector<Tune> tunes;
     const Tune *find_tune(int p, int q, int prec) const
     {
@@ -884,7 +884,12 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     if (opts.basis_kernel == MA_BASIS_ONCHIP && !fits)
         return ctx->fail(MA_EINVAL, "the on-chip basis kernel cannot hold regions of %d orbitals "
                          "with p = %d, q = %d", ctx->nmax, p, q);
-    P.small = opts.basis_kernel == MA_BASIS_WORKSPACE ? false : fits;
+    // automatic choice: the autotuned kernel if there is one, else the
+    // workspace kernel (it keeps several columns in flight per CU)
+    if (opts.basis_kernel == MA_BASIS_AUTO)
+        P.small = fits && tn && tn->kernel == MA_BASIS_ONCHIP;
+    else
+        P.small = opts.basis_kernel == MA_BASIS_ONCHIP;
     J.ws_stride = P.small ? 0 : (int64_t)(3 * P.nu + q) * ctx->nmax;
     int bpc = 0;
     hipError_t e = ma::basis_occupancy(S, J, P.small, &bpc);
@@ -1043,7 +1048,8 @@ hipError_t enqueue_post(ma_ctx *ctx, const Plan &P)
     const ma::DevJob &J = P.J;
     hipError_t e;
     if (P.bisect) {
-        if ((e = ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, P.kT, ctx->lohi.as<double>(), st)) != hipSuccess) return e;
+        if ((e = ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, P.kT, ctx->lohi.as<double>(),
+                                   ctx->partial.as<double>(), st)) != hipSuccess) return e;
         if ((e = ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, J.nu, P.kT, P.n_target,
                                    ctx->lohi.as<double>(), ctx->partial.as<double>(), st)) != hipSuccess) return e;
         if ((e = ma::launch_rho(S, J, ctx->lohi.as<double>(), P.kT, P.rho, P.pi,
@@ -1201,18 +1207,20 @@ MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *col
 }
 
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
-                               int32_t slots_per_cu, int32_t schedule)
+                               int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel)
 {
     if (!ctx) return MA_EINVAL;
-    if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT)
+    if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT ||
+        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_WORKSPACE)
         return ctx->fail(MA_EINVAL, "invalid tuning");
     for (auto &t : ctx->tunes)
         if (t.p == p && t.q == q && t.prec == precision) {
             t.slots = slots_per_cu;
             t.sched = schedule;
+            t.kernel = basis_kernel;
             return MA_OK;
         }
-    ctx->tunes.push_back({p, q, precision, slots_per_cu, schedule});
+    ctx->tunes.push_back({p, q, precision, slots_per_cu, schedule, basis_kernel});
     return MA_OK;
 }
 
@@ -1228,38 +1236,45 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     ma_default_opts(&o);
     if (opts_in) o = *opts_in;
     o.use_graph = 0;
-    // occupancy limit of this shape
-    Plan P0;
-    ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
-                            nullptr, nullptr, 1 << 20, MA_SCHED_LPT, P0);
-    if (s != MA_OK) return s;
-    const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
     std::memset(out, 0, sizeof(*out));
     out->best_ms = INFINITY;
-    for (int sched = 0; sched <= MA_SCHED_XCD_LPT; ++sched)
-        for (int bpc = 1; bpc <= max_bpc && out->n_tried < 64; ++bpc) {
-            Plan P;
-            s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, nullptr, bpc, sched, P);
-            if (s != MA_OK) return s;
-            double best = INFINITY;
-            for (int r = 0; r < reps; ++r) {
-                ma_result res{};
-                s = run_plan(ctx, P, &res);
+    for (int kern = MA_BASIS_ONCHIP; kern <= MA_BASIS_WORKSPACE; ++kern) {
+        if (kern == MA_BASIS_ONCHIP && !ma::basis_small_fits(ctx->nmax, p + q, q, ctx->o)) continue;
+        o.basis_kernel = kern;
+        // occupancy limit of this kernel and shape
+        Plan P0;
+        ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, 1 << 20, MA_SCHED_LPT, P0);
+        if (s != MA_OK) return s;
+        const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
+        for (int sched = 0; sched <= MA_SCHED_XCD_LPT; ++sched)
+            for (int bpc = 1; bpc <= max_bpc && out->n_tried < 64; ++bpc) {
+                Plan P;
+                s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, bpc, sched, P);
                 if (s != MA_OK) return s;
-                best = std::min(best, res.kernel_ms);
+                double best = INFINITY;
+                for (int r = 0; r < reps; ++r) {
+                    ma_result res{};
+                    s = run_plan(ctx, P, &res);
+                    if (s != MA_OK) return s;
+                    best = std::min(best, res.kernel_ms);
+                }
+                const int t = out->n_tried++;
+                out->tried_slots[t] = bpc;
+                out->tried_schedule[t] = sched;
+                out->tried_kernel[t] = kern;
+                out->tried_ms[t] = best;
+                if (best < out->best_ms) {
+                    out->best_ms = best;
+                    out->slots_per_cu = bpc;
+                    out->schedule = sched;
+                    out->basis_kernel = kern;
+                }
             }
-            const int t = out->n_tried++;
-            out->tried_slots[t] = bpc;
-            out->tried_schedule[t] = sched;
-            out->tried_ms[t] = best;
-            if (best < out->best_ms) {
-                out->best_ms = best;
-                out->slots_per_cu = bpc;
-                out->schedule = sched;
-            }
-        }
-    return ma_set_tuning(ctx, p, q, o.precision, out->slots_per_cu, out->schedule);
+    }
+    return ma_set_tuning(ctx, p, q, o.precision, out->slots_per_cu, out->schedule,
+                         out->basis_kernel);
 }
 
 }  // extern "C"

@@ -10,8 +10,8 @@ namespace ma {
 constexpr int kThreads = 256;            // workgroup size of the column kernel
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxNu = 64;
-constexpr int kBisectTrials = 63;        // trial potentials per bisection pass
-constexpr int kBisectPasses = 9;         // 64^9 narrows any bracket below 1e-15
+constexpr int kBisectTrials = 15;        // trial potentials per bisection pass
+constexpr int kBisectPasses = 14;        // 16^14 = 7.2e16: any bracket narrows below 1e-15
 constexpr int kCountBlocks = 256;        // fixed grid of the electron-count kernel
 constexpr int kNbDesc = 48;              // neighbours in a column descriptor
 constexpr int kNbOut = 12;               // atoms whose s_j coefficients the network predicts
@@ -115,7 +115,7 @@ hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st);
 
 // Fermi weighting, chemical potential, reductions.
 hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int nu,
-                         double kT, double *lohi, hipStream_t st);
+                         double kT, double *lohi, double *partial, hipStream_t st);
 hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *stats,
                          int ncols, int nu, double kT, double n_target, double *lohi,
                          double *partial, hipStream_t st);

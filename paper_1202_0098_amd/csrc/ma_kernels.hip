@@ -918,11 +918,18 @@ __global__ void __launch_bounds__(NT) k_basis_s(DevSystem S, DevJob J)
 // ------------------------------------------------------------------------
 // reduced generalised eigenproblems and column outputs (a6, a7)
 // ------------------------------------------------------------------------
-// One wavefront per column of the chunk.  The pair is symmetrised
-// (1/2 (X + X^T)), S~ = Lc Lc^T by Cholesky, A = Lc^-1 H~ Lc^-T, cyclic
-// Jacobi with circle-method rounds of disjoint rotations applied as 2 x 2
-// block updates, C = Lc^-T Y.  Then v_a at row j, (S v_a)_j, the Ritz values
-// in ascending order and the weights w_a = v_ja (S v_a)_j; then either the
+// One wavefront per column of the chunk, everything in LDS:
+//   1/2 (X + X^T) -> H~, S~; Cholesky S~ = Lc Lc^T (right-looking);
+//   A = Lc^-1 H~ Lc^-T (two right-looking triangular solves, a lane per column);
+//   Householder reduction A = Q T Q^T to tridiagonal T, Q accumulated backwards;
+//   implicit QL iterations with shifts on T (the published QL algorithm for
+//   symmetric tridiagonal matrices: Bowdler, Martin, Reinsch and Wilkinson,
+//   Numer. Math. 11 (1968)), each plane rotation applied to the rows of Z = Q
+//   by one lane per row;
+//   C = Lc^-T Z.
+// Every lane runs the scalar recurrences of the QL sweeps redundantly, so they
+// need no broadcasts.  Then v_a at row j, (S v_a)_j, the Ritz values in
+// ascending order and the weights w_a = v_ja (S v_a)_j; then either the
 // amplitudes v_ia v_ja at the pattern rows or, with a given chemical
 // potential, rho_ij, pi_ij (Eqs. 13-14) and E_j, N_j (Eq. 17).
 template <typename TA>
@@ -930,13 +937,13 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
 {
     extern __shared__ double smem[];
     const int nu = J.nu;
-    double *A = smem, *B = smem + nu * nu, *Y = smem + 2 * nu * nu;
+    double *A = smem, *B = smem + nu * nu, *Z = smem + 2 * nu * nu;   // Z column-major
     double *ev = smem + 3 * nu * nu, *vj = ev + kMaxNu, *svj = vj + kMaxNu, *fw = svj + kMaxNu;
-    double *rot = fw + kMaxNu;
-    int *rank = reinterpret_cast<int *>(rot + kMaxNu);
-    int *prs = rank + kMaxNu;
-    int *inv = prs + kMaxNu;
-    __shared__ int s_flag;
+    double *hh = fw + kMaxNu, *ee = hh + kMaxNu, *qv = ee + kMaxNu, *rd = qv + kMaxNu;
+    int *rank = reinterpret_cast<int *>(rd + kMaxNu);
+    int *inv = rank + kMaxNu;
+    __shared__ double hv[kMaxNu];   // current Householder vector (separate objects: the
+    __shared__ double hq[kMaxNu];   // compiler may keep their loads ahead of A's stores)
     const int lane = threadIdx.x;
     const int o = S.o;
     for (int s = blockIdx.x; s < J.cn; s += gridDim.x) {
@@ -945,42 +952,57 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
         const double *Up = mid + 2 * (int64_t)nu * nu;
         int32_t *st = J.stats + (int64_t)c * kStats;
         int L = st[3] == 0 ? st[0] : 0;
-        if (lane == 0) s_flag = 0;
+        int status = 0;
         for (int e = lane; e < L * L; e += 64) {
             const int i = e / L, k = e - i * L;
             A[e] = 0.5 * (mid[i * nu + k] + mid[k * nu + i]);
             B[e] = 0.5 * (mid[nu * nu + i * nu + k] + mid[nu * nu + k * nu + i]);
         }
         __syncthreads();
+
         // Cholesky S~ = Lc Lc^T in the lower triangle of B
-        for (int jj = 0; jj < L; ++jj) {
-            if (lane == 0) {
-                double sd = B[jj * L + jj];
-                for (int k = 0; k < jj; ++k) sd -= B[jj * L + k] * B[jj * L + k];
-                if (!(sd > 0.0)) { s_flag = 1; sd = 1.0; }
-                B[jj * L + jj] = sqrt(sd);
+        for (int k = 0; k < L; ++k) {
+            double dk = B[k * L + k];
+            if (!(dk > 0.0)) {
+                status = -4;
+                dk = 1.0;
             }
+            const double lk = sqrt(dk), rl = 1.0 / lk;
+            for (int i = k + 1 + lane; i < L; i += 64) B[i * L + k] *= rl;
             __syncthreads();
-            for (int i = jj + 1 + lane; i < L; i += 64) {
-                double t2 = B[i * L + jj];
-                for (int k = 0; k < jj; ++k) t2 -= B[i * L + k] * B[jj * L + k];
-                B[i * L + jj] = t2 / B[jj * L + jj];
+            for (int j = k + 1 + lane; j < L; j += 64) {
+                const double bjk = B[j * L + k];
+                #pragma unroll 4
+                for (int i = j; i < L; ++i) B[i * L + j] -= B[i * L + k] * bjk;
+            }
+            if (lane == 0) {
+                B[k * L + k] = lk;
+                rd[k] = rl;
             }
             __syncthreads();
         }
-        // W = Lc^-1 H~ -> Y (one column per lane), then A = Lc^-1 W^T
-        for (int cc = lane; cc < L; cc += 64)
-            for (int i = 0; i < L; ++i) {
-                double t2 = A[i * L + cc];
-                for (int k = 0; k < i; ++k) t2 -= B[i * L + k] * Y[k * L + cc];
-                Y[i * L + cc] = t2 / B[i * L + i];
+        // W = Lc^-1 H~ into Z (row-major here), then A = Lc^-1 W^T
+        for (int e = lane; e < L * L; e += 64) Z[e] = A[e];
+        __syncthreads();
+        for (int k = 0; k < L; ++k)
+            for (int cc = lane; cc < L; cc += 64) {
+                const double wk = Z[k * L + cc] * rd[k];
+                Z[k * L + cc] = wk;
+                #pragma unroll 4
+                for (int i = k + 1; i < L; ++i) Z[i * L + cc] -= B[i * L + k] * wk;
             }
         __syncthreads();
-        for (int cc = lane; cc < L; cc += 64)
-            for (int i = 0; i < L; ++i) {
-                double t2 = Y[cc * L + i];
-                for (int k = 0; k < i; ++k) t2 -= B[i * L + k] * A[k * L + cc];
-                A[i * L + cc] = t2 / B[i * L + i];
+        for (int e = lane; e < L * L; e += 64) {
+            const int i = e / L, k = e - i * L;
+            A[e] = Z[k * L + i];
+        }
+        __syncthreads();
+        for (int k = 0; k < L; ++k)
+            for (int cc = lane; cc < L; cc += 64) {
+                const double ak = A[k * L + cc] * rd[k];
+                A[k * L + cc] = ak;
+                #pragma unroll 4
+                for (int i = k + 1; i < L; ++i) A[i * L + cc] -= B[i * L + k] * ak;
             }
         __syncthreads();
         for (int e = lane; e < L * L; e += 64) {
@@ -991,115 +1013,193 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
                 A[k * L + i] = v;
             }
         }
-        for (int e = lane; e < L * L; e += 64) Y[e] = (e / L == e % L) ? 1.0 : 0.0;
         __syncthreads();
 
-        // cyclic Jacobi on A, accumulating Y <- Y J
-        {
-            const int L2 = L + (L & 1);
-            const int npair = L2 / 2;
-            double off_prev = INFINITY;
-            for (int sweep = 0; sweep < 60 && L > 1; ++sweep) {
-                double off = 0.0, fro = 0.0;
-                for (int e = lane; e < L * L; e += 64) {
-                    const double v = A[e] * A[e];
-                    fro += v;
-                    if (e / L != e % L) off += v;
+        // Householder reduction to tridiagonal form.  Step k reflects
+        // x = A[k+1.., k] onto alpha e_1 with P = I - v v^T / h,
+        // v = x - alpha e_1, h = |v|^2 / 2; v stays in column k below the
+        // diagonal, h in hh[k], alpha is the sub-diagonal ee[k].
+        for (int k = 0; k + 2 < L; ++k) {
+            const int i = k + 1 + lane;
+            const double xi = i < L ? A[i * L + k] : 0.0;
+            const double sig = wave_sum(xi * xi);
+            const double x0 = A[(k + 1) * L + k];
+            double alpha = x0, h = 0.0;
+            if (sig > 0.0) {
+                alpha = x0 >= 0.0 ? -sqrt(sig) : sqrt(sig);
+                h = sig - x0 * alpha;
+            }
+            if (lane == 0) {
+                ee[k] = alpha;
+                hh[k] = h;
+            }
+            if (h > 0.0) {
+                // v = x - alpha e_1, kept in column k and in hv
+                const double vi = (i == k + 1) ? x0 - alpha : xi;
+                if (i < L) {
+                    hv[i] = vi;
+                    A[i * L + k] = vi;
                 }
-                off = wave_sum(off);
-                fro = wave_sum(fro);
-                if (off == 0.0 || off <= 1e-30 * fro) break;
-                // no longer decreasing once at rounding level
-                if (off <= 1e-24 * fro && off > 0.25 * off_prev) break;
-                off_prev = off;
-                for (int round = 0; round < L2 - 1; ++round) {
-                    if (lane < npair) {
-                        const int ia = lane == 0 ? 0 : 1 + (lane - 1 + round) % (L2 - 1);
-                        const int ib = 1 + (L2 - 2 - lane + round) % (L2 - 1);
-                        const int pp = min(ia, ib), qq = max(ia, ib);
-                        double cs = 1.0, sn = 0.0;
-                        if (qq < L) {
-                            const double apq = A[pp * L + qq];
-                            if (apq != 0.0) {
-                                const double theta = (A[qq * L + qq] - A[pp * L + pp]) / (2.0 * apq);
-                                double tt;
-                                if (fabs(theta) > 1e150) tt = 0.5 / theta;
-                                else tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                                cs = 1.0 / sqrt(tt * tt + 1.0);
-                                sn = tt * cs;
-                            }
+                __syncthreads();
+                // p = A' v / h, K = v^T p / (2 h), q = p - K v (a lane per column j)
+                const int j = k + 1 + lane;
+                double pj = 0.0, vjj = 0.0;
+                if (j < L) {
+                    #pragma unroll 4
+                    for (int ii = k + 1; ii < L; ++ii) pj += A[ii * L + j] * hv[ii];
+                    pj /= h;
+                    vjj = hv[j];
+                }
+                const double K = wave_sum(vjj * pj) / (2.0 * h);
+                const double qj = pj - K * vjj;
+                if (j < L) hq[j] = qj;
+                __syncthreads();
+                // A' -= v q^T + q v^T
+                if (j < L)
+                    #pragma unroll 4
+                    for (int ii = k + 1; ii < L; ++ii)
+                        A[ii * L + j] -= hv[ii] * qj + hq[ii] * vjj;
+            }
+            __syncthreads();
+        }
+        for (int i = lane; i < L; i += 64) ev[i] = A[i * L + i];
+        if (lane == 0 && L >= 2) ee[L - 2] = A[(L - 1) * L + L - 2];
+        if (lane == 0 && L >= 1) ee[L - 1] = 0.0;
+        // Z = P_0 P_1 ... P_{L-3} (column-major), accumulated from the last
+        // reflector; P_k leaves columns 0..k unchanged
+        for (int e = lane; e < L * L; e += 64) Z[e] = (e / L == e % L) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int k = L - 3; k >= 0; --k) {
+            const double h = hh[k];
+            if (!(h > 0.0)) continue;
+            for (int cc = k + 1 + lane; cc < L; cc += 64) {
+                double t = 0.0;
+                #pragma unroll 4
+                for (int i = k + 1; i < L; ++i) t += A[i * L + k] * Z[cc * L + i];
+                t /= h;
+                #pragma unroll 4
+                for (int i = k + 1; i < L; ++i) Z[cc * L + i] -= A[i * L + k] * t;
+            }
+        }
+        __syncthreads();
+
+        // Implicit QL sweeps on (ev, ee).  For the leading unreduced block
+        // [l, m] (ee[m] negligible against its diagonal neighbours), a shift
+        // from the 2 x 2 at l, then plane rotations chasing the bulge from m
+        // up to l.  At most 64 sweeps per eigenvalue.  The rotation loop is
+        // software-pipelined: the entries of the next rotation are loaded one
+        // rotation ahead, and the rotated column i stays in a register for the
+        // next rotation (columns i + 1 are final once written).
+        for (int l = 0; l < L && status == 0; ++l) {
+            int sweeps = 0;
+            for (;;) {
+                int m = l;
+                for (; m < L - 1; ++m)
+                    if (fabs(ee[m]) <= DBL_EPSILON * (fabs(ev[m]) + fabs(ev[m + 1]))) break;
+                if (m == l) break;
+                if (++sweeps > 64) {
+                    status = -5;
+                    break;
+                }
+                const double el = ee[l], dl0 = ev[l], dl1 = ev[l + 1], dm = ev[m];
+                const double t0 = (dl1 - dl0) / (2.0 * el);
+                const double r0 = sqrt(t0 * t0 + 1.0);
+                double g = dm - dl0 + el / (t0 + (t0 >= 0.0 ? r0 : -r0));
+                double sn = 1.0, cs = 1.0, p = 0.0;
+                bool underflow = false;
+                const bool row = lane < L;
+                double e_i = ee[m - 1], d_i = ev[m - 1], d_i1 = dm;
+                double z_i1 = row ? Z[m * L + lane] : 0.0;
+                double z_i = row ? Z[(m - 1) * L + lane] : 0.0;
+                for (int i = m - 1; i >= l; --i) {
+                    double e_n = 0.0, d_n = 0.0, z_n = 0.0;
+                    if (i > l) {
+                        e_n = ee[i - 1];
+                        d_n = ev[i - 1];
+                        z_n = row ? Z[(i - 1) * L + lane] : 0.0;
+                    }
+                    const double f = sn * e_i, b = cs * e_i;
+                    const double r2 = f * f + g * g;
+                    if (r2 == 0.0) {
+                        const double dnew = d_i1 - p;
+                        if (lane == 0) {
+                            ee[i + 1] = 0.0;
+                            ev[i + 1] = dnew;
+                            ee[m] = 0.0;
                         }
-                        rot[2 * lane] = cs;
-                        rot[2 * lane + 1] = sn;
-                        prs[2 * lane] = pp;
-                        prs[2 * lane + 1] = qq;
+                        if (row) Z[(i + 1) * L + lane] = z_i1;
+                        underflow = true;
+                        break;
                     }
-                    __syncthreads();
-                    for (int e = lane; e < npair * npair; e += 64) {
-                        const int k1 = e / npair, k2 = e - k1 * npair;
-                        const int ra = prs[2 * k1], rb = prs[2 * k1 + 1];
-                        const int ca = prs[2 * k2], cb = prs[2 * k2 + 1];
-                        const double c1 = rot[2 * k1], s1 = rot[2 * k1 + 1];
-                        const double c2 = rot[2 * k2], s2 = rot[2 * k2 + 1];
-                        const bool rbo = rb < L, cbo = cb < L;
-                        const double x_ac = A[ra * L + ca];
-                        const double x_ad = cbo ? A[ra * L + cb] : 0.0;
-                        const double x_bc = rbo ? A[rb * L + ca] : 0.0;
-                        const double x_bd = (rbo && cbo) ? A[rb * L + cb] : 0.0;
-                        // rows (J^T .): a' = c1 a - s1 b, b' = s1 a + c1 b
-                        const double y_ac = c1 * x_ac - s1 * x_bc, y_bc = s1 * x_ac + c1 * x_bc;
-                        const double y_ad = c1 * x_ad - s1 * x_bd, y_bd = s1 * x_ad + c1 * x_bd;
-                        // columns (. J): c' = c2 c - s2 d, d' = s2 c + c2 d
-                        A[ra * L + ca] = c2 * y_ac - s2 * y_ad;
-                        if (cbo) A[ra * L + cb] = s2 * y_ac + c2 * y_ad;
-                        if (rbo) A[rb * L + ca] = c2 * y_bc - s2 * y_bd;
-                        if (rbo && cbo) A[rb * L + cb] = s2 * y_bc + c2 * y_bd;
+                    const double ir = rsqrt(r2);
+                    sn = f * ir;
+                    cs = g * ir;
+                    g = d_i1 - p;
+                    const double rr = (d_i - g) * sn + 2.0 * cs * b;
+                    p = sn * rr;
+                    if (lane == 0) {
+                        ee[i + 1] = r2 * ir;
+                        ev[i + 1] = g + p;
                     }
-                    for (int e = lane; e < L * npair; e += 64) {
-                        const int row = e / npair, k = e - row * npair;
-                        const int pp = prs[2 * k], qq = prs[2 * k + 1];
-                        if (qq >= L) continue;
-                        const double cs = rot[2 * k], sn = rot[2 * k + 1];
-                        const double ykp = Y[row * L + pp], ykq = Y[row * L + qq];
-                        Y[row * L + pp] = cs * ykp - sn * ykq;
-                        Y[row * L + qq] = sn * ykp + cs * ykq;
-                    }
-                    __syncthreads();
+                    g = cs * rr - b;
+                    const double zn1 = sn * z_i + cs * z_i1;
+                    const double zn0 = cs * z_i - sn * z_i1;
+                    if (row) Z[(i + 1) * L + lane] = zn1;
+                    z_i1 = zn0;
+                    z_i = z_n;
+                    e_i = e_n;
+                    d_i1 = d_i;
+                    d_i = d_n;
+                }
+                if (underflow) continue;
+                if (row) Z[l * L + lane] = z_i1;
+                if (lane == 0) {
+                    ev[l] = dl0 - p;
+                    ee[l] = g;
+                    ee[m] = 0.0;
                 }
             }
         }
-        // eigenvalues and their ascending ranks; C = Lc^-T Y -> A
-        for (int a = lane; a < L; a += 64) ev[a] = A[a * L + a];
         __syncthreads();
+        // ascending ranks of the eigenvalues
         for (int a = lane; a < L; a += 64) {
             int rk = 0;
             const double va = ev[a];
+            #pragma unroll 4
             for (int bb = 0; bb < L; ++bb)
                 if (ev[bb] < va || (ev[bb] == va && bb < a)) ++rk;
             rank[a] = rk;
         }
-        for (int cc = lane; cc < L; cc += 64)
-            for (int i = L - 1; i >= 0; --i) {
-                double t2 = Y[i * L + cc];
-                for (int k = i + 1; k < L; ++k) t2 -= B[k * L + i] * A[k * L + cc];
-                A[i * L + cc] = t2 / B[i * L + i];
+        // C = Lc^-T Z -> A (row-major), a lane per column
+        for (int a = lane; a < L; a += 64) {
+            #pragma unroll 4
+            for (int i = 0; i < L; ++i) A[i * L + a] = Z[a * L + i];
+            for (int k = L - 1; k >= 0; --k) {
+                const double ck = A[k * L + a] * rd[k];
+                A[k * L + a] = ck;
+                #pragma unroll 4
+                for (int i = 0; i < k; ++i) A[i * L + a] -= B[k * L + i] * ck;
             }
+        }
         __syncthreads();
-        if (s_flag) {
+        if (status != 0) {
             L = 0;
             if (lane == 0) {
                 st[0] = 0;
-                st[3] = -4;
+                st[3] = status;
                 atomicMin(J.fail, c);
             }
         }
         const double *C = A;
-        // v_a and (S v_a) at row j
+        // v_a and (S v_a) at row j (a lane per Ritz vector; the basis rows
+        // are read at the same address by every lane)
         for (int a = lane; a < L; a += 64) {
             double v1 = 0.0, v2 = 0.0;
+            #pragma unroll 4
             for (int m = 0; m < L; ++m) {
-                v1 += Up[m] * C[m * L + a];
-                v2 += Up[nu + m] * C[m * L + a];
+                const double cma = C[m * L + a];
+                v1 += Up[m] * cma;
+                v2 += Up[nu + m] * cma;
             }
             vj[a] = v1;
             svj[a] = v2;
@@ -1122,14 +1222,17 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
         const int npat = (int)(S.blk_ptr[At + 1] - kb0) * o;
         if (!J.direct) {
             TA *amp = reinterpret_cast<TA *>(J.amp) + J.amp_off[c];
-            for (int e = lane; e < npat * nu; e += 64) {
-                const int tt = e / nu, a = e - tt * nu;
-                if (a < L) {
+            for (int a = lane; a < nu; a += 64) {
+                const int ra = a < L ? rank[a] : a;
+                const double vja = a < L ? vj[a] : 0.0;
+                for (int tt = 0; tt < npat; ++tt) {
                     double v = 0.0;
-                    for (int m = 0; m < L; ++m) v += Up[(2 + tt) * nu + m] * C[m * L + a];
-                    amp[tt * nu + rank[a]] = (TA)(v * vj[a]);
-                } else {
-                    amp[tt * nu + a] = (TA)0.0;
+                    if (a < L) {
+                        const double *ur = Up + (2 + tt) * nu;
+                        #pragma unroll 4
+                        for (int m = 0; m < L; ++m) v += ur[m] * C[m * L + a];
+                    }
+                    amp[tt * nu + ra] = (TA)(v * vja);
                 }
             }
         } else {
@@ -1142,6 +1245,7 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
                 for (int k = 0; k < L; ++k) {
                     const int a = inv[k];
                     double v = 0.0;
+                    #pragma unroll 4
                     for (int m = 0; m < L; ++m) v += Up[(2 + tt) * nu + m] * C[m * L + a];
                     const double am = v * vj[a];
                     sr += fw[k] * am;
@@ -1173,12 +1277,16 @@ __global__ void k_reset(int *queue, int *fail, int reset_fail)
 // ------------------------------------------------------------------------
 // Fermi weighting and the chemical potential
 // ------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_minmax(const double *eps, const int32_t *stats, int ncols,
-                                                 int nu, double kT, double *lohi)
+// Bracket of the chemical potential: [min eps - 50 kT, max eps + 50 kT] over
+// the accepted Ritz values.  Per-block extremes, then one block combines them.
+__global__ void __launch_bounds__(256) k_minmax(const double *eps, const int32_t *stats, int ncols,
+                                                int nu, double *part)
 {
-    __shared__ double smin[16], smax[16];
+    __shared__ double smin[4], smax[4];
     double lo = INFINITY, hi = -INFINITY;
-    for (int64_t e = threadIdx.x; e < (int64_t)ncols * nu; e += blockDim.x) {
+    const int64_t total = (int64_t)ncols * nu;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = e / nu;
         if (e - c * nu < stats[c * kStats]) {
             lo = fmin(lo, eps[e]);
@@ -1195,15 +1303,27 @@ __global__ void __launch_bounds__(1024) k_minmax(const double *eps, const int32_
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+        for (int k = 1; k < 4; ++k) {
             lo = fmin(lo, smin[k]);
             hi = fmax(hi, smax[k]);
         }
         lo = fmin(lo, smin[0]);
         hi = fmax(hi, smax[0]);
-        lohi[0] = lo - 50.0 * kT;
-        lohi[1] = hi + 50.0 * kT;
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
     }
+}
+
+__global__ void k_minmax_final(const double *part, int nblocks, double kT, double *lohi)
+{
+    if (threadIdx.x != 0) return;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int b = 0; b < nblocks; ++b) {
+        lo = fmin(lo, part[2 * b]);
+        hi = fmax(hi, part[2 * b + 1]);
+    }
+    lohi[0] = lo - 50.0 * kT;
+    lohi[1] = hi + 50.0 * kT;
 }
 
 // Electron count sum_j sum_a f((eps_a - mu_t)/kT) w_a for the kBisectTrials
@@ -1484,8 +1604,8 @@ hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, bool small, int 
 
 hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
 {
-    const size_t smem = sizeof(double) * (3 * (size_t)J.nu * J.nu + 5 * kMaxNu) +
-                        sizeof(int) * 3 * kMaxNu;
+    const size_t smem = sizeof(double) * (3 * (size_t)J.nu * J.nu + 8 * kMaxNu) +
+                        sizeof(int) * 2 * kMaxNu;
     const int grid = J.cn < (1 << 20) ? J.cn : (1 << 20);
     if (grid < 1) return hipSuccess;
     if (J.precision == 0) return launch_with_smem(k_eig<double>, grid, 64, smem, st, S, J);
@@ -1493,9 +1613,10 @@ hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
 }
 
 hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int nu, double kT,
-                         double *lohi, hipStream_t st)
+                         double *lohi, double *partial, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_minmax, dim3(1), dim3(1024), 0, st, eps, stats, ncols, nu, kT, lohi);
+    hipLaunchKernelGGL(k_minmax, dim3(kCountBlocks), dim3(256), 0, st, eps, stats, ncols, nu, partial);
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, st, partial, kCountBlocks, kT, lohi);
     return hipGetLastError();
 }
 
