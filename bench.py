@@ -62,7 +62,7 @@ def main():
                     help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE[,BASIS_KERNEL]' instead of "
                          "the autotuner")
     ap.add_argument("--no-graph", action="store_true", help="launch without hipGraph replay")
-    ap.add_argument("--basis-kernel", default="auto", choices=["auto", "onchip", "workspace"],
+    ap.add_argument("--basis-kernel", default="auto", choices=["auto", "onchip", "workspace", "group"],
                     help="basis kernel: on-chip basis (regions up to 512 orbitals) or workspace")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB five times "

@@ -71,7 +71,7 @@ typedef enum {
 enum { MA_REGION_ALL = 0, MA_REGION_RADIUS = 1, MA_REGION_NEAREST = 2 };
 enum { MA_PREC_FP64 = 0, MA_PREC_MIXED = 1, MA_PREC_MIXED_F64ACC = 2 };
 enum { MA_START_ZERO = 0, MA_START_LEARNED = 1 };
-enum { MA_BASIS_AUTO = 0, MA_BASIS_ONCHIP = 1, MA_BASIS_WORKSPACE = 2 };
+enum { MA_BASIS_AUTO = 0, MA_BASIS_ONCHIP = 1, MA_BASIS_WORKSPACE = 2, MA_BASIS_GROUP = 3 };
 
 /* The pencil and its geometry.  All pointers are host memory owned by the
  * caller; ma_build_system copies what it needs. */
@@ -121,11 +121,17 @@ typedef struct {
                                value if available, else MA_SCHED_LPT */
     int32_t use_graph;      /* 1: capture the launch sequence in a hipGraph and replay it
                                while the configuration and buffers are unchanged */
-    int32_t basis_kernel;   /* MA_BASIS_AUTO: the on-chip basis kernel whenever every
-                               region has at most 512 orbitals, p + q <= 32 and
-                               q <= 16 (q <= 8 when p + q <= 16), else the workspace
-                               kernel; MA_BASIS_ONCHIP / MA_BASIS_WORKSPACE force one
-                               (MA_EINVAL if the on-chip kernel cannot hold the shape) */
+    int32_t basis_kernel;   /* MA_BASIS_AUTO: the autotuned kernel for (p, q, precision)
+                               if ma_autotune ran, else MA_BASIS_GROUP where it applies,
+                               else MA_BASIS_WORKSPACE.  MA_BASIS_WORKSPACE: one column
+                               per workgroup, basis in a device workspace.
+                               MA_BASIS_ONCHIP: one column per workgroup, basis in LDS
+                               and registers (regions of at most 512 orbitals,
+                               p + q <= 32, q <= 16; q <= 8 when p + q <= 16).
+                               MA_BASIS_GROUP: the requested columns of one atom in
+                               lockstep, one SpMM per step for all of them (o = 4 or
+                               9).  A forced kernel that cannot hold the shape is
+                               MA_EINVAL. */
     int32_t chunk_columns;  /* columns per chunk of the processing order (0 = as many
                                as a 4 GiB chunk buffer holds); a solve of several
                                chunks launches eagerly instead of replaying graphs */
@@ -174,7 +180,7 @@ typedef struct {
     int32_t tried_slots[64];
     int32_t tried_schedule[64];
     double tried_ms[64];        /* basis-kernel time of each candidate (best of reps) */
-    int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP or MA_BASIS_WORKSPACE */
+    int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE or MA_BASIS_GROUP */
     int32_t tried_kernel[64];
 } ma_tuning;
 
@@ -278,7 +284,7 @@ MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, 
                                    int64_t n, float lr, double *loss);
 
 /* Autotuner: time the basis kernel on cols[0..ncols) (NULL = all) for every
- * candidate -- basis kernel (on-chip when the shape fits, and workspace) x
+ * candidate -- basis kernel (each one that can hold the shape) x
  * slots per CU from 1 to that kernel's occupancy limit x every schedule --
  * `reps` times each at chemical potential mu (finite), and keep the fastest
  * configuration for this (p, q, opts->precision) in the context; solves with
@@ -289,8 +295,8 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
                              ma_tuning *out);
 
 /* Store a previously found tuning for (p, q, precision) (e.g. from a cache);
- * basis_kernel is MA_BASIS_ONCHIP or MA_BASIS_WORKSPACE (MA_BASIS_AUTO keeps
- * the automatic choice). */
+ * basis_kernel is MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE or MA_BASIS_GROUP
+ * (MA_BASIS_AUTO keeps the automatic choice). */
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
                                int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel);
 

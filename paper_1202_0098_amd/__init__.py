@@ -69,7 +69,7 @@ class _Tuning(ctypes.Structure):
 
 
 SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
-BASIS_KERNELS = {"auto": 0, "onchip": 1, "workspace": 2}
+BASIS_KERNELS = {"auto": 0, "onchip": 1, "workspace": 2, "group": 3}
 
 
 class _Result(ctypes.Structure):

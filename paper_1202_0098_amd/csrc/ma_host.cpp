@@ -126,8 +126,8 @@ struct ma_ctx {
     DevBuf feat, x0;                  // per-solve descriptors and predicted starts
 
     // device solve buffers
-    DevBuf cols, order, qbounds, ws, eps, wts, amp, amp_off, mid, stats, ctl, lohi, partial, Ecol,
-        Ncol, sums;
+    DevBuf cols, order, qbounds, gstart, ws, eps, wts, amp, amp_off, mid, stats, ctl, lohi, partial,
+        Ecol, Ncol, sums;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr, eve1 = nullptr;
     std::vector<hipEvent_t> chunk_ev;  // per-chunk timing of eager multi-chunk solves
     uint64_t generation = 0;          // bumped by every ma_build_system
@@ -795,8 +795,10 @@ struct Plan {
     int p = 0, q = 0, nu = 0, slots = 0, sched = 0;
     double mu = 0, kT = 0, n_target = 0;
     bool bisect = false;
-    bool small = false;          // basis kernel keeps the basis on chip
-    int chunk = 0, nchunks = 0;  // columns per chunk of the processing order
+    int kind = ma::kBasisWorkspace;   // basis kernel
+    int nchunks = 0, max_cn = 0;      // chunks of the processing order
+    std::vector<int32_t> ch_c0, ch_cn, ch_items;   // per chunk: first column position,
+                                                   // columns, work items
     std::vector<int32_t> hcols;
     ma::DevSystem S;
     ma::DevJob J;                // J.c0, J.cn, J.qbounds describe chunk 0
@@ -805,8 +807,8 @@ struct Plan {
     ma::DevJob chunk_job(int k) const
     {
         ma::DevJob Jk = J;
-        Jk.c0 = k * chunk;
-        Jk.cn = std::min(chunk, J.ncols - Jk.c0);
+        Jk.c0 = ch_c0[k];
+        Jk.cn = ch_cn[k];
         Jk.qbounds = qb_dev + (int64_t)k * (J.nqueues + 1);
         return Jk;
     }
@@ -877,22 +879,33 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     J.inner_tol = opts.inner_tol;
     J.tau = opts.breakdown_tau;
     J.max_refine = opts.max_refine;
-    if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_WORKSPACE)
+    if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_GROUP)
         return ctx->fail(MA_EINVAL, "unknown basis kernel %d", opts.basis_kernel);
     if (opts.chunk_columns < 0) return ctx->fail(MA_EINVAL, "chunk_columns must be >= 0");
     const bool fits = ma::basis_small_fits(ctx->nmax, P.nu, q, ctx->o);
+    const bool gfits = ma::basis_group_fits(ctx->nmax, P.nu, ctx->o);
     if (opts.basis_kernel == MA_BASIS_ONCHIP && !fits)
         return ctx->fail(MA_EINVAL, "the on-chip basis kernel cannot hold regions of %d orbitals "
                          "with p = %d, q = %d", ctx->nmax, p, q);
+    if (opts.basis_kernel == MA_BASIS_GROUP && !gfits)
+        return ctx->fail(MA_EINVAL, "the atom-group basis kernel needs 4 or 9 orbitals per atom "
+                         "and regions it can stage (o = %d, %d orbitals)", ctx->o, ctx->nmax);
     // automatic choice: the autotuned kernel if there is one, else the
-    // workspace kernel (it keeps several columns in flight per CU)
-    if (opts.basis_kernel == MA_BASIS_AUTO)
-        P.small = fits && tn && tn->kernel == MA_BASIS_ONCHIP;
-    else
-        P.small = opts.basis_kernel == MA_BASIS_ONCHIP;
-    J.ws_stride = P.small ? 0 : (int64_t)(3 * P.nu + q) * ctx->nmax;
+    // atom-group kernel where it applies, else the workspace kernel
+    int want_kernel = opts.basis_kernel;
+    if (want_kernel == MA_BASIS_AUTO)
+        want_kernel = tn && tn->kernel != MA_BASIS_AUTO ? tn->kernel
+                      : gfits ? MA_BASIS_GROUP : MA_BASIS_WORKSPACE;
+    if ((want_kernel == MA_BASIS_ONCHIP && !fits) || (want_kernel == MA_BASIS_GROUP && !gfits))
+        want_kernel = MA_BASIS_WORKSPACE;
+    P.kind = want_kernel == MA_BASIS_ONCHIP ? ma::kBasisOnchip
+             : want_kernel == MA_BASIS_GROUP ? ma::kBasisGroup : ma::kBasisWorkspace;
+    const int o = ctx->o;
+    J.ws_stride = P.kind == ma::kBasisOnchip ? 0
+                  : (int64_t)(P.kind == ma::kBasisGroup ? ma::basis_group_width(o) : 1) *
+                        (3 * P.nu + q) * ctx->nmax;
     int bpc = 0;
-    hipError_t e = ma::basis_occupancy(S, J, P.small, &bpc);
+    hipError_t e = ma::basis_occupancy(S, J, P.kind, &bpc);
     if (e != hipSuccess) return ctx->hip_fail(e, "occupancy");
     if (bpc < 1)
         return ctx->fail(MA_EINVAL, "basis kernel does not fit on a compute unit (nu=%d, nmax=%d)",
@@ -901,36 +914,107 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
                : opts.slots_per_cu > 0 ? opts.slots_per_cu : (tn ? tn->slots : bpc);
     bpc = std::min(bpc, std::max(1, want));
 
-    // chunks of the processing order
-    J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
-    const int64_t per_chunk = std::max<int64_t>(1, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
-    P.chunk = (int)std::min<int64_t>(ncols, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
-    P.nchunks = (int)((ncols + P.chunk - 1) / P.chunk);
-    P.slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, P.chunk);
+    // Work items: single columns, or (atom-group kernel) the requested
+    // columns of one atom.  items[w] lists the output rows of item w.
+    std::vector<int32_t> item_start, item_cols;
+    if (P.kind == ma::kBasisGroup) {
+        // the requested columns of each atom (atoms in order of first
+        // appearance), cut into runs of at most the kernel's width
+        const int width = ma::basis_group_width(o);
+        std::vector<int32_t> first(ctx->n_atoms, -1), count(ctx->n_atoms, 0);
+        std::vector<int32_t> atoms;
+        for (int64_t c = 0; c < ncols; ++c) {
+            const int A = P.hcols[c] / o;
+            if (first[A] < 0) {
+                first[A] = (int32_t)atoms.size();
+                atoms.push_back(A);
+            }
+            ++count[A];
+        }
+        std::vector<int32_t> astart(atoms.size() + 1, 0);
+        for (size_t g = 0; g < atoms.size(); ++g) astart[g + 1] = astart[g] + count[atoms[g]];
+        std::vector<int32_t> bycol(ncols), fill(atoms.size(), 0);
+        for (int64_t c = 0; c < ncols; ++c) {
+            const int g = first[P.hcols[c] / o];
+            bycol[astart[g] + fill[g]++] = (int32_t)c;
+        }
+        item_cols = bycol;
+        item_start.clear();
+        for (size_t g = 0; g < atoms.size(); ++g)
+            for (int32_t u = astart[g]; u < astart[g + 1]; u += width) item_start.push_back(u);
+        item_start.push_back((int32_t)ncols);
+    } else {
+        item_start.resize(ncols + 1);
+        std::iota(item_start.begin(), item_start.end(), 0);
+        item_cols.resize(ncols);
+        std::iota(item_cols.begin(), item_cols.end(), 0);
+    }
+    const int nitems = (int)item_start.size() - 1;
+    auto item_len = [&](int w) { return item_start[w + 1] - item_start[w]; };
+    auto item_region = [&](int w) { return ctx->reg_len_of_atom[P.hcols[item_cols[item_start[w]]] / o]; };
 
-    // processing order and per-chunk queue bounds
-    std::vector<int32_t> order(ncols);
-    std::iota(order.begin(), order.end(), 0);
+    // chunks: whole work items, at most the chunk budget of columns each
+    J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
+    const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
+    const int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
+    std::vector<int32_t> ch_item0;   // first work item of each chunk
+    {
+        int64_t cols_in = 0;
+        for (int w = 0; w < nitems; ++w) {
+            if (w == 0 || cols_in + item_len(w) > budget) {
+                ch_item0.push_back(w);
+                cols_in = 0;
+            }
+            cols_in += item_len(w);
+        }
+        ch_item0.push_back(nitems);
+    }
+    P.nchunks = (int)ch_item0.size() - 1;
+
+    // processing order of the work items, per chunk and queue
+    std::vector<int32_t> witem(nitems);
+    std::iota(witem.begin(), witem.end(), 0);
     auto lpt = [&](std::vector<int32_t>::iterator b, std::vector<int32_t>::iterator e2) {
-        std::stable_sort(b, e2, [&](int32_t x, int32_t y) {
-            return ctx->reg_len_of_atom[P.hcols[x] / ctx->o] > ctx->reg_len_of_atom[P.hcols[y] / ctx->o];
-        });
+        std::stable_sort(b, e2, [&](int32_t x, int32_t y) { return item_region(x) > item_region(y); });
     };
     const bool xcd = P.sched == MA_SCHED_XCD_INPUT || P.sched == MA_SCHED_XCD_LPT;
     J.nqueues = xcd ? ma::kMaxQueues : 1;
     std::vector<int32_t> qb((size_t)P.nchunks * (J.nqueues + 1));
+    P.ch_c0.assign(P.nchunks, 0);
+    P.ch_cn.assign(P.nchunks, 0);
+    P.ch_items.assign(P.nchunks, 0);
     for (int k = 0; k < P.nchunks; ++k) {
-        const int64_t c0 = (int64_t)k * P.chunk, cn = std::min<int64_t>(P.chunk, ncols - c0);
+        const int w0 = ch_item0[k], w1 = ch_item0[k + 1], nw = w1 - w0;
         for (int i = 0; i <= J.nqueues; ++i)
-            qb[(size_t)k * (J.nqueues + 1) + i] = (int32_t)(c0 + cn * i / J.nqueues);
-        if (P.sched == MA_SCHED_LPT) lpt(order.begin() + c0, order.begin() + c0 + cn);
+            qb[(size_t)k * (J.nqueues + 1) + i] = (int32_t)(w0 + (int64_t)nw * i / J.nqueues);
+        if (P.sched == MA_SCHED_LPT) lpt(witem.begin() + w0, witem.begin() + w1);
         if (P.sched == MA_SCHED_XCD_LPT)
             for (int i = 0; i < J.nqueues; ++i)
-                lpt(order.begin() + qb[(size_t)k * (J.nqueues + 1) + i],
-                    order.begin() + qb[(size_t)k * (J.nqueues + 1) + i + 1]);
+                lpt(witem.begin() + qb[(size_t)k * (J.nqueues + 1) + i],
+                    witem.begin() + qb[(size_t)k * (J.nqueues + 1) + i + 1]);
+        P.ch_items[k] = nw;
     }
+    // column order: the columns of the work items in processing order;
+    // gstart[w] is the first column position of the w-th processed item
+    std::vector<int32_t> order(ncols), gstart(nitems + 1, 0);
+    {
+        int32_t pos = 0;
+        for (int w = 0; w < nitems; ++w) {
+            gstart[w] = pos;
+            const int it = witem[w];
+            for (int u = item_start[it]; u < item_start[it + 1]; ++u) order[pos++] = item_cols[u];
+        }
+        gstart[nitems] = pos;
+        for (int k = 0; k < P.nchunks; ++k) {
+            P.ch_c0[k] = gstart[ch_item0[k]];
+            P.ch_cn[k] = gstart[ch_item0[k + 1]] - gstart[ch_item0[k]];
+            P.max_cn = std::max(P.max_cn, P.ch_cn[k]);
+        }
+    }
+    int max_items = 0;
+    for (int k = 0; k < P.nchunks; ++k) max_items = std::max(max_items, P.ch_items[k]);
+    P.slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, max_items);
     // amplitudes (only while the chemical potential is unknown), compact per column
-    const int o = ctx->o;
     std::vector<int64_t> aoff;
     size_t amp_elems = 0;
     if (P.bisect) {
@@ -948,8 +1032,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, ctx->cols.reserve(sizeof(int32_t) * ncols), "cols");
     HIPCHK(ctx, ctx->order.reserve(sizeof(int32_t) * ncols), "order");
     HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * qb.size()), "queues");
-    if (!P.small) HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
-    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.chunk), "chunk buffer");
+    if (P.kind != ma::kBasisOnchip)
+        HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
+    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.max_cn), "chunk buffer");
+    HIPCHK(ctx, ctx->gstart.reserve(sizeof(int32_t) * (nitems + 1)), "work items");
     HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
     HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
     if (P.bisect) {
@@ -972,6 +1058,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, P.hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
     HIPCHK(ctx, hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "order");
     HIPCHK(ctx, hipMemcpyAsync(ctx->qbounds.p, qb.data(), sizeof(int32_t) * qb.size(), hipMemcpyHostToDevice, st), "queues");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->gstart.p, gstart.data(), sizeof(int32_t) * gstart.size(), hipMemcpyHostToDevice, st), "work items");
     if (P.bisect)
         HIPCHK(ctx, hipMemcpyAsync(ctx->amp_off.p, aoff.data(), sizeof(int64_t) * (ncols + 1), hipMemcpyHostToDevice, st), "amplitude offsets");
     // the copies read pageable host vectors: finish them before those go away
@@ -981,11 +1068,12 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     J.order = ctx->order.as<int32_t>();
     P.qb_dev = ctx->qbounds.as<int32_t>();
     J.qbounds = P.qb_dev;
-    J.c0 = 0;
-    J.cn = P.chunk;
+    J.c0 = P.ch_c0[0];
+    J.cn = P.ch_cn[0];
+    J.gstart = ctx->gstart.as<int32_t>();
     J.queue = ctx->ctl.as<int>();
     J.fail = ctx->ctl.as<int>() + ma::kMaxQueues;
-    J.ws = P.small ? nullptr : ctx->ws.as<double>();
+    J.ws = P.kind == ma::kBasisOnchip ? nullptr : ctx->ws.as<double>();
     J.mid = ctx->mid.as<double>();
     J.eps = eps ? eps : ctx->eps.as<double>();
     J.wts = wts ? wts : ctx->wts.as<double>();
@@ -1013,7 +1101,7 @@ hipError_t enqueue_basis(ma_ctx *ctx, const Plan &P, int k)
     const ma::DevJob Jk = P.chunk_job(k);
     hipError_t e = ma::launch_reset(Jk.queue, Jk.fail, k == 0 ? 1 : 0, st);
     if (e != hipSuccess) return e;
-    return ma::launch_basis(P.S, Jk, P.small, (int)std::min<int64_t>(P.slots, Jk.cn), st);
+    return ma::launch_basis(P.S, Jk, P.kind, (int)std::min<int64_t>(P.slots, P.ch_items[k]), st);
 }
 
 hipError_t enqueue_eig(ma_ctx *ctx, const Plan &P, int k)
@@ -1087,7 +1175,7 @@ std::vector<unsigned char> graph_key(const ma_ctx *ctx, const Plan &P)
     key_add(k, ctx->generation);
     key_add(k, P.J);          // sizes, tolerances, mu, and every device pointer
     key_add(k, P.slots);
-    key_add(k, P.small);
+    key_add(k, P.kind);
     key_add(k, P.bisect);
     key_add(k, P.kT);
     key_add(k, P.n_target);
@@ -1211,7 +1299,7 @@ MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precis
 {
     if (!ctx) return MA_EINVAL;
     if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT ||
-        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_WORKSPACE)
+        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_GROUP)
         return ctx->fail(MA_EINVAL, "invalid tuning");
     for (auto &t : ctx->tunes)
         if (t.p == p && t.q == q && t.prec == precision) {
@@ -1238,8 +1326,9 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     o.use_graph = 0;
     std::memset(out, 0, sizeof(*out));
     out->best_ms = INFINITY;
-    for (int kern = MA_BASIS_ONCHIP; kern <= MA_BASIS_WORKSPACE; ++kern) {
+    for (int kern = MA_BASIS_ONCHIP; kern <= MA_BASIS_GROUP; ++kern) {
         if (kern == MA_BASIS_ONCHIP && !ma::basis_small_fits(ctx->nmax, p + q, q, ctx->o)) continue;
+        if (kern == MA_BASIS_GROUP && !ma::basis_group_fits(ctx->nmax, p + q, ctx->o)) continue;
         o.basis_kernel = kern;
         // occupancy limit of this kernel and shape
         Plan P0;

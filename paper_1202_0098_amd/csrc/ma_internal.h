@@ -62,6 +62,8 @@ struct DevJob {
     int nqueues;               // 1, or 8 (one per XCD)
     const int32_t *qbounds;    // nqueues + 1 absolute offsets into order, this chunk
     int *fail;                 // [0] = first failing c (INT_MAX none)
+    const int32_t *gstart;     // atom-group kernel: columns of group g are order positions
+                               // gstart[g] .. gstart[g+1]
     double *ws;                // basis workspace of the large-region kernel, slots * ws_stride
     int64_t ws_stride;
     // chunk: order positions c0 .. c0 + cn; slot s = position - c0
@@ -96,18 +98,23 @@ inline int64_t mid_stride_of(int nu, int maxpat) { return 2 * (int64_t)nu * nu +
 constexpr int kStats = 8;      // nu_eff, CG iterations, FP64 residual evaluations, status,
                                // start used (0 zero, 1 learned, 2 learned rejected), 3 spare
 
-// Basis kernels.  The small-region kernel keeps the basis on chip (U in LDS,
-// S U and the block-2 chain in registers) and is used when every region has
-// at most kSmallRows orbitals, nu <= 32 and q <= nu_cap / 2; otherwise the
-// large-region kernel keeps U, S U, H U and the chain in a global workspace.
+// Basis kernels.  Workspace kernel: one column per workgroup, U, S U, H U
+// and the chain in a global workspace.  On-chip kernel: one column per
+// workgroup, U in LDS and S U, chain in registers (regions of at most
+// kSmallRows orbitals, nu <= 32, q <= nu_cap / 2).  Atom-group kernel: the
+// requested columns of one atom in lockstep (o = 4 or 9), one SpMM per step
+// for all of them, bases in the workspace.
 constexpr int kMaxQueues = 8;
 constexpr int kSmallRows = 512;
+enum { kBasisWorkspace = 0, kBasisOnchip = 1, kBasisGroup = 2 };
 bool basis_small_fits(int nmax, int nu, int q, int o);
-size_t basis_smem_bytes(int nmax, int nu, bool small);
+bool basis_group_fits(int nmax, int nu, int o);
+int basis_group_width(int o);   // columns of one atom solved together
+size_t basis_smem_bytes(int nmax, int nu, int kind, int o);
 int basis_rows_per_thread(int nmax);
 hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st);
-hipError_t launch_basis(const DevSystem &S, const DevJob &J, bool small, int slots, hipStream_t st);
-hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, bool small, int *blocks_per_cu);
+hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots, hipStream_t st);
+hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *blocks_per_cu);
 
 // Batched reduced eigenproblems and column outputs, one wavefront per column
 // of the chunk.

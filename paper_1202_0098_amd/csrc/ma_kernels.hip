@@ -210,6 +210,9 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
             const int a = i / o;
             const int ri = i - a * o;
             const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
+            // several blocks in flight: the index and value loads of a block
+            // do not depend on the previous block
+#pragma unroll 4
             for (int64_t kb = k0; kb < k1; ++kb) {
                 const int2 e = S.lblk[kb];
                 const int64_t base = (int64_t)e.y * (o * o) + ri * o;
@@ -474,6 +477,30 @@ __device__ __forceinline__ void drain_queues(const DevJob &J, int *s_idx, F &&bo
     }
 }
 
+// The same loop over work items that are not single columns (the
+// atom-group kernel: idx is a group position).
+template <typename F>
+__device__ __forceinline__ void drain_queues_raw(const DevJob &J, int *s_idx, F &&body)
+{
+    int qi = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int idx = -1;
+            for (; qi < J.nqueues; ++qi) {
+                const int k = (blockIdx.x + qi) % J.nqueues;
+                const int pos = J.qbounds[k] + atomicAdd(J.queue + k, 1);
+                if (pos < J.qbounds[k + 1]) { idx = pos; break; }
+            }
+            *s_idx = idx;
+        }
+        __syncthreads();
+        const int idx = *s_idx;
+        __syncthreads();
+        if (idx < 0) break;
+        body(idx);
+    }
+}
+
 // ------------------------------------------------------------------------
 // large-region basis kernel: basis in the global workspace
 // ------------------------------------------------------------------------
@@ -722,6 +749,830 @@ __global__ void __launch_bounds__(NTG) k_basis_g(DevSystem S, DevJob J)
     double *T = K + J.nu * ld;
     drain_queues(J, &s_idx, [&](int c, int s) __attribute__((always_inline)) {
         basis_global<O, R, PREC>(S, J, sm, c, s, U, SU, K, T);
+    });
+}
+
+// ------------------------------------------------------------------------
+// atom-group basis kernel: the columns of one atom in lockstep
+// ------------------------------------------------------------------------
+// The columns j = (A, r) of atom A share its region and region operator.
+// One workgroup runs their CGs, Gram-Schmidt recurrences and Galerkin
+// projections together: every SpMV is an SpMM that reads each operator value
+// once for all of them, and every workgroup reduction carries one value per
+// column.  Each column keeps its own basis (U, S U, H U, chain) in the
+// workspace; CG convergence and breakdowns are per column (masks).  Thread t
+// owns local rows t, t + NT, ...; the B vectors an SpMM reads are staged in
+// LDS, vector k at offset k * ldx.
+
+// pad B values to a power of two for the transposed reduction
+template <int B>
+__host__ __device__ constexpr int pow2_at_least() { return B <= 1 ? 1 : B <= 2 ? 2 : B <= 4 ? 4 : B <= 8 ? 8 : 16; }
+
+// out[k] = sum over the workgroup of v[k], k < B (LDS `out`, B entries).
+template <int NWV, int B, typename F>
+__device__ __forceinline__ void group_sum(F &&gen, double *scratch, double *out)
+{
+    constexpr int NV = pow2_at_least<B>();
+    block_reduce<NWV, NV, 1>([&](int, double (&v)[NV]) __attribute__((always_inline)) {
+        double t[B];
+        gen(t);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = k < B ? t[k] : 0.0;
+    }, scratch, out);
+}
+
+// Fused SpMM on the thread's rows: hy[k] = H xa_k, sy[k] = S xa_k, zy[k] = H xb_k.
+template <int O, int R, int NT, int B, typename TM, typename TX, bool DO_H, bool DO_S, bool DO_Z>
+__device__ __forceinline__ void spmm_rows(const DevSystem &S, const Col &g, const TM *__restrict__ Hv,
+                                          const TM *__restrict__ Sv, const TX *xa, const TX *xb,
+                                          int ldx, double (&hy)[R][B], double (&sy)[R][B],
+                                          double (&zy)[R][B])
+{
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        const int i = threadIdx.x + rr * NT;
+        TX h[B], s[B], z[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) h[k] = s[k] = z[k] = 0;
+        if (i < g.n) {
+            const int a = i / O;
+            const int ri = i - a * O;
+            const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
+#pragma unroll 4
+            for (int64_t kb = k0; kb < k1; ++kb) {
+                const int2 e = S.lblk[kb];
+                const int64_t base = (int64_t)e.y * (O * O) + ri * O;
+                const int xo = e.x * O;
+#pragma unroll
+                for (int cc = 0; cc < O; ++cc) {
+                    const TX hvv = DO_H || DO_Z ? (TX)Hv[base + cc] : (TX)0;
+                    const TX svv = DO_S ? (TX)Sv[base + cc] : (TX)0;
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        if (DO_H) h[k] += hvv * xa[k * ldx + xo + cc];
+                        if (DO_S) s[k] += svv * xa[k * ldx + xo + cc];
+                        if (DO_Z) z[k] += hvv * xb[k * ldx + xo + cc];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            hy[rr][k] = (double)h[k];
+            sy[rr][k] = (double)s[k];
+            zy[rr][k] = (double)z[k];
+        }
+    }
+}
+
+// out[k * kMaxNu + m] = V_k[m] . x_k for k < nb, m < cnt[k] (x_k in LDS at
+// k * ldx).  The dot products of all columns are spread over the wavefronts,
+// four consecutive ones at a time.
+template <int NWV, int B>
+__device__ __forceinline__ void multidot_group(double *const (&V)[B], int64_t ld, const int (&cnt)[B],
+                                               int nb, const double *x, int ldx, int n, double *out)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int total = 0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) total += k < nb ? cnt[k] : 0;
+    for (int t0 = 4 * w; t0 < total; t0 += 4 * NWV) {
+        const double *vp[4];
+        const double *xp[4];
+        int dst[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int t = t0 + u < total ? t0 + u : t0;
+            int kk = 0;
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (k < nb && t >= cnt[k] && kk == k) {
+                    t -= cnt[k];
+                    kk = k + 1;
+                }
+            vp[u] = V[0];
+            xp[u] = x;
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (k == kk) {
+                    vp[u] = V[k] + (int64_t)t * ld;
+                    xp[u] = x + k * ldx;
+                }
+            dst[u] = t0 + u < total ? kk * kMaxNu + t : -1;
+        }
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            a0 += vp[0][i] * xp[0][i];
+            a1 += vp[1][i] * xp[1][i];
+            a2 += vp[2][i] * xp[2][i];
+            a3 += vp[3][i] * xp[3][i];
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        a3 = wave_sum(a3);
+        if (lane == 0) {
+            if (dst[0] >= 0) out[dst[0]] = a0;
+            if (dst[1] >= 0) out[dst[1]] = a1;
+            if (dst[2] >= 0) out[dst[2]] = a2;
+            if (dst[3] >= 0) out[dst[3]] = a3;
+        }
+    }
+}
+
+struct SmemM {
+    double *xa, *xb;     // B * ldx doubles each: staged vectors
+    double *cf;          // 2 * B * kMaxNu: Gram-Schmidt coefficients per column
+    double *gs;          // group sums (up to 16 values)
+    double *scratch;     // transposed-reduction scratch
+    int ldx;
+};
+
+template <int O, int B, int NT, int R, int PREC>
+__device__ void basis_group(const DevSystem &S, const DevJob &J, const SmemM &sm, int gpos,
+                            double *ws)
+{
+    constexpr int NWV = NT / 64;
+    using TM = typename std::conditional<PREC != 0, float, double>::type;
+    using TX = typename std::conditional<PREC == 1, float, double>::type;
+    const int tid = threadIdx.x;
+    const int nu = J.nu;
+    const int64_t ld = S.nmax;
+    const int ldx = sm.ldx;
+    const int p0 = J.gstart[gpos];
+    const int nb = J.gstart[gpos + 1] - p0;
+    // the group's columns: output rows, slots and orbitals
+    int cc_[B], slot[B], orb[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        const int pos = p0 + (k < nb ? k : 0);
+        cc_[k] = J.order[pos];
+        slot[k] = pos - J.c0;
+        orb[k] = J.cols[cc_[k]] % O;
+    }
+    const int A = J.cols[cc_[0]] / O;
+    Col g;
+    {
+        const int rid = S.reg_id[A];
+        g.A = A;
+        g.r = 0;
+        g.n_at = S.reg_len[rid];
+        g.n = g.n_at * O;
+        g.rp = S.lrp + S.lrp_off[rid];
+        g.jl = S.jloc[A] * O;   // local row of orbital 0 of atom A
+    }
+    const int n = g.n;
+    int jl[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) jl[k] = g.jl + orb[k];
+    auto valid = [&](int k) __attribute__((always_inline)) { return k < nb; };
+    auto own = [&](int rr) __attribute__((always_inline)) { return tid + rr * NT < n; };
+    auto unit = [&](int rr, int k) __attribute__((always_inline)) {
+        return (tid + rr * NT) == jl[k] ? 1.0 : 0.0;
+    };
+    double *gs = sm.gs;
+    double dmy[R][B];
+
+    // ---------------- inner CGs: S_A s_k = e_jk, in lockstep ----------------
+    double x[R][B];
+    int iters[B], nres[B], status[B], start[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        iters[k] = nres[k] = start[k] = 0;
+        status[k] = valid(k) ? 0 : 1;   // 1: not a column of this group
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) x[rr][k] = 0.0;
+    }
+    const int nout = kNbOut * O;
+    if (J.x0) {
+        for (int e = tid; e < B * ldx; e += NT) sm.xa[e] = 0.0;
+        __syncthreads();
+        for (int e = tid; e < nb * nout; e += NT) {
+            const int k = e / nout, f = e - k * nout;
+            const int kn = f / O, c2 = f - kn * O;
+            const int la = S.out_loc[(int64_t)A * kNbOut + kn];
+            int ck = cc_[0];
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk)
+                if (kk == k) ck = cc_[kk];
+            if (la >= 0) sm.xa[k * ldx + la * O + c2] = (double)J.x0[(int64_t)ck * nout + f];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (own(rr) && valid(k)) x[rr][k] = sm.xa[k * ldx + tid + rr * NT];
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (valid(k)) start[k] = 1;
+        __syncthreads();
+    }
+    // stage x (FP64), S x for every column
+    auto stage64 = [&](const double (&v)[R][B], double *dst) __attribute__((always_inline)) {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (own(rr)) dst[k * ldx + tid + rr * NT] = v[rr][k];
+    };
+    double q[R][B], rv[R][B];
+    auto true_residual = [&]() __attribute__((always_inline)) {
+        stage64(x, sm.xa);
+        __syncthreads();
+        spmm_rows<O, R, NT, B, double, double, false, true, false>(S, g, S.Hd, S.Sd, sm.xa, sm.xb, ldx, dmy, q, dmy);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int k = 0; k < B; ++k) rv[rr][k] = unit(rr, k) - q[rr][k];
+        group_sum<NWV, B>([&](double (&t)[B]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                double a = 0.0;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    if (own(rr)) a += rv[rr][k] * rv[rr][k];
+                t[k] = a;
+            }
+        }, sm.scratch, gs);
+    };
+    double rho2[B];
+    bool conv[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) conv[k] = false;
+    true_residual();
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        rho2[k] = gs[k];
+        if (valid(k)) ++nres[k];
+        if (valid(k) && start[k] == 1 && !(rho2[k] < 1.0)) {
+            // the residual judge rejects the predicted start: zero start
+            start[k] = 2;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                x[rr][k] = 0.0;
+                rv[rr][k] = unit(rr, k);
+            }
+            rho2[k] = 1.0;
+        }
+    }
+    if (PREC == 0) {
+        double pv[R][B];
+        for (int restart = 0; restart <= 3; ++restart) {
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < B; ++k) any |= status[k] == 0 && !conv[k];
+            if (!any) break;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                for (int k = 0; k < B; ++k) pv[rr][k] = rv[rr][k];
+            int it[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) it[k] = 0;
+            for (;;) {
+                bool act[B];
+                bool anyact = false;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    act[k] = status[k] == 0 && !conv[k] && it[k] < n && sqrt(rho2[k]) > J.cg_tol;
+                    anyact |= act[k];
+                }
+                if (!anyact) break;
+                stage64(pv, sm.xa);
+                __syncthreads();
+                spmm_rows<O, R, NT, B, double, double, false, true, false>(S, g, S.Hd, S.Sd, sm.xa, sm.xb, ldx, dmy, q, dmy);
+                group_sum<NWV, B>([&](double (&t)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        double a = 0.0;
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr)
+                            if (own(rr)) a += pv[rr][k] * q[rr][k];
+                        t[k] = a;
+                    }
+                }, sm.scratch, gs);
+                double alpha[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    const double pq = gs[k];
+                    alpha[k] = 0.0;
+                    if (act[k]) {
+                        if (!(pq > 0.0)) {
+                            status[k] = -4;
+                            act[k] = false;
+                        } else {
+                            alpha[k] = rho2[k] / pq;
+                        }
+                    }
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        if (act[k]) {
+                            x[rr][k] += alpha[k] * pv[rr][k];
+                            rv[rr][k] -= alpha[k] * q[rr][k];
+                        }
+                }
+                group_sum<NWV, B>([&](double (&t)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        double a = 0.0;
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr)
+                            if (own(rr)) a += rv[rr][k] * rv[rr][k];
+                        t[k] = a;
+                    }
+                }, sm.scratch, gs);
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (act[k]) {
+                        const double rn = gs[k];
+                        const double beta = rn / rho2[k];
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr) pv[rr][k] = rv[rr][k] + beta * pv[rr][k];
+                        rho2[k] = rn;
+                        ++iters[k];
+                        ++it[k];
+                    }
+            }
+            // judge on the true residual
+            true_residual();
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (status[k] == 0 && !conv[k]) {
+                    rho2[k] = gs[k];
+                    ++nres[k];
+                    if (sqrt(rho2[k]) <= J.cg_tol) conv[k] = true;
+                }
+        }
+    } else {
+        // FP32 CG passes on the normalised FP64 residual, refined in FP64
+        TX *xaX = reinterpret_cast<TX *>(sm.xa);
+        float *xaF = reinterpret_cast<float *>(sm.xa);
+        for (int ref = 0; ref <= J.max_refine; ++ref) {
+            if (ref > 0) {
+                true_residual();
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (status[k] == 0 && !conv[k]) {
+                        rho2[k] = gs[k];
+                        ++nres[k];
+                    }
+            }
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                if (status[k] == 0 && !conv[k] && sqrt(rho2[k]) <= J.cg_tol) conv[k] = true;
+                any |= status[k] == 0 && !conv[k];
+            }
+            if (!any || ref == J.max_refine) break;
+            double rho[B];
+            float rf[R][B], pf[R][B], df[R][B];
+            float rrf[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                rho[k] = sqrt(rho2[k]);
+                rrf[k] = 0.0f;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const bool on = status[k] == 0 && !conv[k];
+                    rf[rr][k] = on ? (float)(rv[rr][k] / rho[k]) : 0.0f;
+                    pf[rr][k] = rf[rr][k];
+                    df[rr][k] = 0.0f;
+                }
+            }
+            group_sum<NWV, B>([&](double (&t)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    float a = 0.0f;
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        if (own(rr)) a += rf[rr][k] * rf[rr][k];
+                    t[k] = (double)a;
+                }
+            }, sm.scratch, gs);
+#pragma unroll
+            for (int k = 0; k < B; ++k) rrf[k] = (float)gs[k];
+            const float thr = (float)J.inner_tol;
+            int it[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) it[k] = 0;
+            for (;;) {
+                bool act[B];
+                bool anyact = false;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    act[k] = status[k] == 0 && !conv[k] && it[k] < n && sqrtf(rrf[k]) > thr;
+                    anyact |= act[k];
+                }
+                if (!anyact) break;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                    for (int k = 0; k < B; ++k)
+                        if (own(rr)) xaF[k * ldx + tid + rr * NT] = pf[rr][k];
+                __syncthreads();
+                float qf[R][B];
+                {
+                    double qd[R][B];
+                    spmm_rows<O, R, NT, B, float, float, false, true, false>(S, g, S.Hf, S.Sf, xaF, xaF, ldx, dmy, qd, dmy);
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                        for (int k = 0; k < B; ++k) qf[rr][k] = (float)qd[rr][k];
+                }
+                group_sum<NWV, B>([&](double (&t)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        float a = 0.0f;
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr)
+                            if (own(rr)) a += pf[rr][k] * qf[rr][k];
+                        t[k] = (double)a;
+                    }
+                }, sm.scratch, gs);
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    const float pq = (float)gs[k];
+                    float alpha = 0.0f;
+                    if (act[k]) {
+                        if (!(pq > 0.0f)) {
+                            status[k] = -4;
+                            act[k] = false;
+                        } else {
+                            alpha = rrf[k] / pq;
+                        }
+                    }
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        if (act[k]) {
+                            df[rr][k] += alpha * pf[rr][k];
+                            rf[rr][k] -= alpha * qf[rr][k];
+                        }
+                }
+                group_sum<NWV, B>([&](double (&t)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        float a = 0.0f;
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr)
+                            if (own(rr)) a += rf[rr][k] * rf[rr][k];
+                        t[k] = (double)a;
+                    }
+                }, sm.scratch, gs);
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (act[k]) {
+                        const float rn = (float)gs[k];
+                        const float beta = rn / rrf[k];
+#pragma unroll
+                        for (int rr = 0; rr < R; ++rr) pf[rr][k] = rf[rr][k] + beta * pf[rr][k];
+                        rrf[k] = rn;
+                        ++iters[k];
+                        ++it[k];
+                    }
+            }
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    if (status[k] == 0 && !conv[k]) x[rr][k] += rho[k] * (double)df[rr][k];
+        }
+        (void)xaX;
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+        if (status[k] == 0 && !conv[k]) status[k] = -5;
+    if (J.sj_near) {
+        __syncthreads();
+        stage64(x, sm.xa);
+        __syncthreads();
+        for (int e = tid; e < nb * nout; e += NT) {
+            const int k = e / nout, f = e - k * nout;
+            const int kn = f / O, c2 = f - kn * O;
+            const int la = S.out_loc[(int64_t)A * kNbOut + kn];
+            int ck = cc_[0], stk = 0;
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk)
+                if (kk == k) {
+                    ck = cc_[kk];
+                    stk = status[kk];
+                }
+            J.sj_near[(int64_t)ck * nout + f] = (stk == 0 && la >= 0) ? (float)sm.xa[k * ldx + la * O + c2] : 0.0f;
+        }
+        __syncthreads();
+    }
+
+    // ---------------- bases of K_p(H;e_j) + K_q(H;s_j), in lockstep ----------------
+    const int64_t cstride = (int64_t)(3 * nu + J.q) * ld;
+    double *U[B], *SU[B], *K[B], *T[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        U[k] = ws + k * cstride;
+        SU[k] = U[k] + nu * ld;
+        K[k] = SU[k] + nu * ld;
+        T[k] = K[k] + nu * ld;
+    }
+    // first chain vector t_1 = s_j / |s_j| (kept in the workspace; s_j dies here)
+    if (J.q > 0) {
+        group_sum<NWV, B>([&](double (&tt)[B]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                double a = 0.0;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    if (own(rr)) a += x[rr][k] * x[rr][k];
+                tt[k] = a;
+            }
+        }, sm.scratch, gs);
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (status[k] != 0) continue;
+            const double ns = sqrt(gs[k]);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int i = tid + rr * NT;
+                if (i < n) T[k][i] = x[rr][k] / ns;
+            }
+        }
+    }
+    int L[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) L[k] = 0;
+    double l[R][B], zv[R][B];
+    double *c1 = sm.cf, *c2 = sm.cf + B * kMaxNu;
+    TX *xaX = reinterpret_cast<TX *>(sm.xa);
+    TX *xbX = reinterpret_cast<TX *>(sm.xb);
+    const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
+    const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
+
+    // One candidate per active column (Eqs. 6-8): two classical Gram-Schmidt
+    // passes with coefficients u_m^T S l, S-normalisation, breakdown test,
+    // acceptance u = l/beta, S u, H u.  With `chain`, also zv = H t.  Returns
+    // the mask of accepted columns.
+    auto append = [&](const bool (&act)[B], bool chain, int kk) __attribute__((always_inline)) -> unsigned {
+        int cnt[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) cnt[k] = act[k] ? L[k] : 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            double *cc = pass ? c2 : c1;
+            stage64(l, sm.xa);
+            __syncthreads();
+            multidot_group<NWV, B>(SU, ld, cnt, nb, sm.xa, ldx, n, cc);
+            __syncthreads();
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int i = tid + rr * NT;
+                if (i < n) {
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        double acc = 0.0;
+                        for (int m = 0; m < cnt[k]; ++m) acc += U[k][m * ld + i] * cc[k * kMaxNu + m];
+                        l[rr][k] -= acc;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (own(rr)) {
+                    const int i = tid + rr * NT;
+                    xaX[k * ldx + i] = (TX)l[rr][k];
+                    if (chain) xbX[k * ldx + i] = act[k] ? (TX)T[k][kk * ld + i] : (TX)0;
+                }
+        __syncthreads();
+        double hv[R][B], w[R][B];
+        if (chain)
+            spmm_rows<O, R, NT, B, TM, TX, true, true, true>(S, g, Hv, Sv, xaX, xbX, ldx, hv, w, zv);
+        else
+            spmm_rows<O, R, NT, B, TM, TX, true, true, false>(S, g, Hv, Sv, xaX, xbX, ldx, hv, w, dmy);
+        group_sum<NWV, B>([&](double (&tt)[B]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                double a = 0.0;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    if (own(rr)) a += l[rr][k] * w[rr][k];
+                tt[k] = a;
+            }
+        }, sm.scratch, gs);
+        unsigned acc_mask = 0;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (!act[k]) continue;
+            const double bb = gs[k];
+            double b0 = bb;
+            for (int m = 0; m < cnt[k]; ++m) {
+                const double cs = c1[k * kMaxNu + m] + c2[k * kMaxNu + m];
+                b0 += cs * cs;
+            }
+            if (!(bb > 0.0) || !(b0 > 0.0) || sqrt(bb) <= J.tau * sqrt(b0)) continue;
+            const double inv = 1.0 / sqrt(bb);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int i = tid + rr * NT;
+                if (i < n) {
+                    U[k][L[k] * ld + i] = l[rr][k] * inv;
+                    SU[k][L[k] * ld + i] = w[rr][k] * inv;
+                    K[k][L[k] * ld + i] = hv[rr][k] * inv;
+                }
+                l[rr][k] = hv[rr][k] * inv;   // next block-1 seed: H u_L
+            }
+            ++L[k];
+            acc_mask |= 1u << k;
+        }
+        return acc_mask;
+    };
+
+    bool act1[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        act1[k] = status[k] == 0;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) l[rr][k] = unit(rr, k);
+    }
+    // block 1: seeds e_j, H u_1, H u_2, ...
+    for (int step = 0; step < J.p; ++step) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < B; ++k) any |= act1[k];
+        if (!any) break;
+        const unsigned ok = append(act1, false, 0);
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (act1[k] && !(ok & (1u << k))) act1[k] = false;
+    }
+    // block 2: chains t_1 = s_j / |s_j|, t_{k+1} = H t_k orthonormalised
+    if (J.q > 0) {
+        bool alive[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) alive[k] = status[k] == 0;
+        for (int kk = 0; kk < J.q; ++kk) {
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < B; ++k) any |= alive[k];
+            if (!any) break;
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int i = tid + rr * NT;
+                    l[rr][k] = (alive[k] && i < n) ? T[k][kk * ld + i] : 0.0;
+                }
+            const bool last = (kk + 1 == J.q);
+            append(alive, !last, kk);
+            if (last) break;
+            // Euclidean Gram-Schmidt of H t_k against t_1..t_k, twice
+            group_sum<NWV, B>([&](double (&tt)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        if (own(rr)) a += zv[rr][k] * zv[rr][k];
+                    tt[k] = a;
+                }
+            }, sm.scratch, gs);
+            double eta0[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) eta0[k] = sqrt(gs[k]);
+            int cnt[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) cnt[k] = alive[k] ? kk + 1 : 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                stage64(zv, sm.xb);
+                __syncthreads();
+                multidot_group<NWV, B>(T, ld, cnt, nb, sm.xb, ldx, n, c1);
+                __syncthreads();
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int i = tid + rr * NT;
+                    if (i < n) {
+#pragma unroll
+                        for (int k = 0; k < B; ++k) {
+                            double acc = 0.0;
+                            for (int m = 0; m < cnt[k]; ++m) acc += T[k][m * ld + i] * c1[k * kMaxNu + m];
+                            zv[rr][k] -= acc;
+                        }
+                    }
+                }
+            }
+            group_sum<NWV, B>([&](double (&tt)[B]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        if (own(rr)) a += zv[rr][k] * zv[rr][k];
+                    tt[k] = a;
+                }
+            }, sm.scratch, gs);
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                if (!alive[k]) continue;
+                const double eta = sqrt(gs[k]);
+                if (!(eta > J.tau * eta0[k])) {
+                    alive[k] = false;
+                    continue;
+                }
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int i = tid + rr * NT;
+                    if (i < n) T[k][(kk + 1) * ld + i] = zv[rr][k] / eta;
+                }
+            }
+        }
+    }
+    __syncthreads();   // basis writes visible to the whole workgroup
+
+    // ---------------- Galerkin pairs and basis rows, per column ----------------
+    const int64_t kb0 = S.blk_ptr[A];
+    const int npat = (int)(S.blk_ptr[A + 1] - kb0) * O;
+    for (int k = 0; k < nb; ++k) {
+        int Lk = 0, stk = 0, sk = 0, jk = 0;
+        const double *Uk = U[0], *SUk = SU[0], *Kk = K[0];
+#pragma unroll
+        for (int kk = 0; kk < B; ++kk)
+            if (kk == k) {
+                Lk = L[kk];
+                stk = status[kk];
+                sk = slot[kk];
+                jk = jl[kk];
+                Uk = U[kk];
+                SUk = SU[kk];
+                Kk = K[kk];
+            }
+        if (stk != 0) continue;
+        double *mid = J.mid + (int64_t)sk * J.mid_stride;
+        double *Xh = mid, *Xs = mid + (int64_t)nu * nu;
+        const int w = tid >> 6, lane = tid & 63;
+        const int ntl = (Lk + 15) >> 4;
+        for (int tile = w; tile < ntl * ntl; tile += NWV) {
+            const int mt = tile / ntl, ntc = tile - mt * ntl;
+            const int m = mt * 16 + (lane & 15), nn = ntc * 16 + (lane & 15);
+            const int kq = lane >> 4;
+            const bool mok = m < Lk, nok = nn < Lk;
+            const double *um = Uk + (int64_t)(mok ? m : 0) * ld;
+            const double *kn = Kk + (int64_t)(nok ? nn : 0) * ld;
+            const double *sn = SUk + (int64_t)(nok ? nn : 0) * ld;
+            dbl4 ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
+            for (int i0 = 0; i0 < n; i0 += 4) {
+                const int i = i0 + kq;
+                const bool iok = i < n;
+                const double a = (mok && iok) ? um[i] : 0.0;
+                const double bh = (nok && iok) ? kn[i] : 0.0;
+                const double bs = (nok && iok) ? sn[i] : 0.0;
+                ah = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh, ah, 0, 0, 0);
+                as = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, as, 0, 0, 0);
+            }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int mr = mt * 16 + 4 * jj + kq, nc = ntc * 16 + (lane & 15);
+                if (mr < Lk && nc < Lk) {
+                    Xh[mr * nu + nc] = ah[jj];
+                    Xs[mr * nu + nc] = as[jj];
+                }
+            }
+        }
+        double *Up = mid + 2 * (int64_t)nu * nu;
+        for (int e = tid; e < (npat + 2) * Lk; e += NT) {
+            const int row = e / Lk, m = e - row * Lk;
+            double v;
+            if (row == 0) v = Uk[m * ld + jk];
+            else if (row == 1) v = SUk[m * ld + jk];
+            else {
+                const int tt = row - 2;
+                v = Uk[m * ld + S.blk_loc[kb0 + tt / O] * O + (tt % O)];
+            }
+            Up[row * nu + m] = v;
+        }
+    }
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (valid(k)) write_stats(J, cc_[k], L[k], iters[k], nres[k], status[k], start[k]);
+    }
+    __syncthreads();
+}
+
+template <int O, int B, int NT, int R, int PREC>
+__global__ void __launch_bounds__(NT) k_basis_m(DevSystem S, DevJob J)
+{
+    extern __shared__ double smem[];
+    __shared__ int s_idx;
+    __shared__ double gsum[16];
+    SmemM sm;
+    sm.ldx = S.nmax;
+    sm.xa = smem;
+    sm.xb = smem + B * S.nmax;
+    sm.cf = smem + 2 * B * S.nmax;
+    sm.scratch = sm.cf + 2 * B * kMaxNu;
+    sm.gs = gsum;
+    double *ws = J.ws + (int64_t)blockIdx.x * J.ws_stride;
+    drain_queues_raw(J, &s_idx, [&](int idx) __attribute__((always_inline)) {
+        basis_group<O, B, NT, R, PREC>(S, J, sm, idx, ws);
     });
 }
 
@@ -1221,18 +2072,30 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
         const int64_t kb0 = S.blk_ptr[At];
         const int npat = (int)(S.blk_ptr[At + 1] - kb0) * o;
         if (!J.direct) {
+            // V at the pattern rows on the FP64 matrix cores: 16 x 16 tiles of
+            // (basis rows of the chunk buffer, npat x L) x (C, L x L, LDS), with
+            // v_mfma_f64_16x16x4f64: lane l feeds A[l%16][l/16], B[l/16][l%16]
+            // and receives D[4 j + l/16][l%16]
             TA *amp = reinterpret_cast<TA *>(J.amp) + J.amp_off[c];
-            for (int a = lane; a < nu; a += 64) {
-                const int ra = a < L ? rank[a] : a;
-                const double vja = a < L ? vj[a] : 0.0;
-                for (int tt = 0; tt < npat; ++tt) {
-                    double v = 0.0;
-                    if (a < L) {
-                        const double *ur = Up + (2 + tt) * nu;
-                        #pragma unroll 4
-                        for (int m = 0; m < L; ++m) v += ur[m] * C[m * L + a];
+            const int nrt = (npat + 15) >> 4, nct = (nu + 15) >> 4;
+            const int kq = lane >> 4, l16 = lane & 15;
+            for (int tile = 0; tile < nrt * nct; ++tile) {
+                const int mt = tile / nct, ct = tile - mt * nct;
+                const int arow = mt * 16 + l16, bcol = ct * 16 + l16;
+                dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < L; k0 += 4) {
+                    const int kk = k0 + kq;
+                    const double av = (arow < npat && kk < L) ? Up[(2 + arow) * nu + kk] : 0.0;
+                    const double bv = (bcol < L && kk < L) ? C[kk * L + bcol] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int tr = mt * 16 + 4 * jj + kq;
+                    if (tr < npat && bcol < nu) {
+                        if (bcol < L) amp[tr * nu + rank[bcol]] = (TA)(acc[jj] * vj[bcol]);
+                        else amp[tr * nu + bcol] = (TA)0.0;
                     }
-                    amp[tt * nu + ra] = (TA)(v * vja);
                 }
             }
         } else {
@@ -1544,7 +2407,32 @@ void *global_kernel(int o, int R, int prec)
 
 typedef void (*basis_fn)(DevSystem, DevJob);
 
+// Atom-group kernel shapes: 512 threads; sp3 (o = 4) regions up to 512
+// orbitals with the 4 columns of an atom together, spd (o = 9) regions up to
+// 1,024 orbitals (two rows per thread) with 3 columns together.
+template <int O, int B, int R>
+void *group_kernel_p(int prec)
+{
+    if (prec == 1) return (void *)k_basis_m<O, B, 512, R, 1>;
+    if (prec == 2) return (void *)k_basis_m<O, B, 512, R, 2>;
+    return (void *)k_basis_m<O, B, 512, R, 0>;
+}
+
+void *group_kernel(int o, int nmax, int prec)
+{
+    (void)nmax;
+    return o == 9 ? group_kernel_p<9, 3, 2>(prec) : group_kernel_p<4, 4, 1>(prec);
+}
+
 }  // namespace
+
+int basis_group_width(int o) { return o == 9 ? 3 : o == 4 ? 4 : 0; }
+
+bool basis_group_fits(int nmax, int nu, int o)
+{
+    if (!((o == 4 && nmax <= 512) || (o == 9 && nmax <= 1024))) return false;
+    return basis_smem_bytes(nmax, nu, kBasisGroup, o) <= 160 * 1024;
+}
 
 bool basis_small_fits(int nmax, int nu, int q, int o)
 {
@@ -1552,7 +2440,7 @@ bool basis_small_fits(int nmax, int nu, int q, int o)
     if (nmax > kSmallRows || nu > 32) return false;
     const int nucap = small_nu_cap(nu);
     if (q > nucap / 2) return false;
-    return basis_smem_bytes(nmax, nu, true) <= 160 * 1024;
+    return basis_smem_bytes(nmax, nu, kBasisOnchip, o) <= 160 * 1024;
 }
 
 int basis_rows_per_thread(int nmax)
@@ -1563,11 +2451,15 @@ int basis_rows_per_thread(int nmax)
     return 8;
 }
 
-size_t basis_smem_bytes(int nmax, int nu, bool small)
+size_t basis_smem_bytes(int nmax, int nu, int kind, int o)
 {
-    if (small) {
+    if (kind == kBasisOnchip) {
         const int nt = small_threads(nmax), nucap = small_nu_cap(nu);
         return sizeof(double) * ((size_t)nucap * nmax + 2 * (size_t)nmax + (nt / 64) * 3 * nucap + 5 * nucap);
+    }
+    if (kind == kBasisGroup) {
+        const int b = basis_group_width(o);
+        return sizeof(double) * (2 * (size_t)b * nmax + 2 * (size_t)b * kMaxNu + (512 / 64) * 16);
     }
     return sizeof(double) * (2 * (size_t)nmax + 4 * kMaxNu);
 }
@@ -1578,26 +2470,32 @@ hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_basis(const DevSystem &S, const DevJob &J, bool small, int slots, hipStream_t st)
+hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots, hipStream_t st)
 {
-    const size_t smem = basis_smem_bytes(S.nmax, J.nu, small);
-    if (small) {
+    const size_t smem = basis_smem_bytes(S.nmax, J.nu, kind, S.o);
+    if (kind == kBasisOnchip) {
         const int nt = small_threads(S.nmax);
         basis_fn k = (basis_fn)small_kernel(S.o, nt, small_nu_cap(J.nu), J.precision);
         return launch_with_smem(k, slots, nt, smem, st, S, J);
+    }
+    if (kind == kBasisGroup) {
+        basis_fn k = (basis_fn)group_kernel(S.o, S.nmax, J.precision);
+        return launch_with_smem(k, slots, 512, smem, st, S, J);
     }
     basis_fn k = (basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision);
     return launch_with_smem(k, slots, NTG, smem, st, S, J);
 }
 
-hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, bool small, int *bpc)
+hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *bpc)
 {
-    const size_t smem = basis_smem_bytes(S.nmax, J.nu, small);
-    if (small) {
+    const size_t smem = basis_smem_bytes(S.nmax, J.nu, kind, S.o);
+    if (kind == kBasisOnchip) {
         const int nt = small_threads(S.nmax);
         return occupancy_of((basis_fn)small_kernel(S.o, nt, small_nu_cap(J.nu), J.precision), nt,
                             smem, bpc);
     }
+    if (kind == kBasisGroup)
+        return occupancy_of((basis_fn)group_kernel(S.o, S.nmax, J.precision), 512, smem, bpc);
     return occupancy_of((basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision),
                         NTG, smem, bpc);
 }

@@ -86,7 +86,7 @@ def _compare(s, ora, cols, gpu, rho_tol, e_tol, mu_tol=1e-9):
     return d_rho, d_e
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace"])
+@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
 def test_fp64_diamond64_all_columns_bisected(ctx, torch_cuda, kernel):
     import oracle
     s = synth.config_diamond64()
@@ -125,7 +125,7 @@ def test_fp64_breakdown_identity_overlap(ctx, torch_cuda):
     _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace"])
+@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
 def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda, kernel):
     """Full-size 4,096-atom system, regions of 120 atoms (480 orbitals),
     p = q = 15, a seeded sample of columns spanning every orbital type."""
@@ -184,7 +184,7 @@ def _compare_mixed(s, raw, cols, gpu, mu_oracle, prec):
     assert d_pi <= MIXED_RHO_TOL[prec] * max(1.0, np.abs(pi_o).max())
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace"])
+@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
 @pytest.mark.parametrize("prec", ["mixed", "mixed_f64acc"])
 def test_mixed_diamond64(ctx, torch_cuda, prec, kernel):
     import oracle
@@ -215,7 +215,7 @@ def test_given_mu_matches_bisected_path(ctx, torch_cuda):
     path of the bisection."""
     s = synth.config_diamond64()
     ctx.build_tb(s)
-    for kernel in ["onchip", "workspace"]:
+    for kernel in ["onchip", "workspace", "group"]:
         _say(f"diamond64 bisected vs given mu ({kernel} basis)")
         a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
         b = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, a[0].mu, s.kT, basis_kernel=kernel)
@@ -232,7 +232,7 @@ def test_chunked_solve_matches_single_chunk(ctx, torch_cuda):
     s = synth.config_diamond4096()
     ctx.build_tb(s)
     cols = np.arange(0, s.M, 11, dtype=np.int32)
-    for kernel in ["onchip", "workspace"]:
+    for kernel in ["onchip", "workspace", "group"]:
         _say(f"diamond4096 {len(cols)} columns, chunks of 97 vs one chunk ({kernel} basis)")
         a = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
         b = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, math.nan, s.kT, basis_kernel=kernel,
@@ -242,23 +242,26 @@ def test_chunked_solve_matches_single_chunk(ctx, torch_cuda):
         assert np.array_equal(a[5], b[5])
 
 
-def test_onchip_and_workspace_kernels_agree(ctx, torch_cuda):
-    """The two basis kernels (same method, different storage and reduction
-    order) agree to rounding on a whole 4,096-atom solve."""
+@pytest.mark.parametrize("other", ["onchip", "group"])
+def test_basis_kernels_agree(ctx, torch_cuda, other):
+    """The basis kernels (same method, different storage, grouping and
+    reduction order) agree to rounding on a whole 4,096-atom solve."""
     s = synth.config_diamond4096()
     ctx.build_tb(s)
-    _say("diamond4096 all columns, onchip vs workspace basis")
-    a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel="onchip")
+    _say(f"diamond4096 all columns, {other} vs workspace basis")
+    a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=other)
     b = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel="workspace")
     d = np.abs(a[1] - b[1]).max()
     _say(f"max|drho| {d:.3e}, energies {a[0].energy:.12f} {b[0].energy:.12f}")
     assert np.array_equal(a[5][:, 0], b[5][:, 0])
+    assert np.array_equal(a[5][:, 1], b[5][:, 1])
     assert d <= 1e-10
     assert abs(a[0].energy - b[0].energy) <= 1e-12 * abs(a[0].energy)
 
 
+@pytest.mark.parametrize("kernel", ["workspace", "group"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_f64acc"])
-def test_fcc_spd_regions(ctx, torch_cuda, prec):
+def test_fcc_spd_regions(ctx, torch_cuda, prec, kernel):
     """spd fcc metal (9 orbitals per atom), regions of radius 7 A (about 83
     atoms, about 750 orbitals, beyond the on-chip kernel), p = q = 15,
     kT = 0.2: a seeded sample of columns on a 4x4x4-cell piece of the
@@ -269,8 +272,9 @@ def test_fcc_spd_regions(ctx, torch_cuda, prec):
     ctx.build_tb(s)
     info = ctx.info()
     cols = np.sort(np.random.default_rng(17).choice(s.M, 72, replace=False)).astype(np.int32)
-    _say(f"fcc spd {prec} {len(cols)} columns, nmax {info['nmax']}")
-    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.3, s.kT, precision=prec)
+    _say(f"fcc spd {prec} {len(cols)} columns, nmax {info['nmax']} ({kernel} basis)")
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.3, s.kT, precision=prec,
+                     basis_kernel=kernel)
     if prec == "fp64":
         ora = oracle.solve(s, cols=cols, mu=0.3)
         _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
@@ -296,10 +300,11 @@ def test_invalid_arguments_rejected(ctx, torch_cuda):
                           opts=ma.default_opts(basis_kernel=7))
     big = synth.config_disordered8000(3001)
     ctx.build_tb(big)
-    with pytest.raises(ma.MarnoldiError) as ei:   # regions of up to 1,040 orbitals
-        ctx.solve_columns(np.array([0], np.int32), 20, 20, mu=0.0, kT=0.1,
-                          opts=ma.default_opts(basis_kernel="onchip"))
-    assert ei.value.status == ma.MA_EINVAL
+    for kern in ["onchip", "group"]:   # regions of up to 1,040 orbitals
+        with pytest.raises(ma.MarnoldiError) as ei:
+            ctx.solve_columns(np.array([0], np.int32), 20, 20, mu=0.0, kT=0.1,
+                              opts=ma.default_opts(basis_kernel=kern))
+        assert ei.value.status == ma.MA_EINVAL
     bad = synth.config_diamond4096(nrp=3)
     with pytest.raises(ma.MarnoldiError) as ei:
         ctx.build_tb(bad)
