@@ -208,7 +208,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": s.name, "atoms": s.n_atoms, "columns": s.M, "p": s.p, "q": s.q,
                    "kT": s.kT, "mu": "bisected at half filling", "precision": args.precision,
-                   "build_s": round(build_s, 3), "hipgraph": not args.no_graph,
+                   "build_s": round(build_s, 3),
+                   "launch": ("eager, eigensolver pipelined beside the basis kernel"
+                              if s.M >= 4 * 2048 else
+                              "eager" if args.no_graph else "hipGraph replay"),
                    "basis_kernel": args.basis_kernel,
                    "tuning": None if tuning is None else {
                        "slots_per_cu": tuning["slots_per_cu"], "schedule": tuning["schedule"],
@@ -220,12 +223,13 @@ def main():
 
 
 def measured_traffic(workload_name, precision):
-    """HBM bytes per launch of the column kernel from the committed counter
-    summary of this workload and precision (FETCH_SIZE + WRITE_SIZE, scaled
-    by the same counters on a plain copy of known size), or None when there is
-    none or the kernel source has changed since the counters were taken."""
+    """HBM bytes per step of the basis kernel (summed over its launches in a
+    step) from the committed counter summary of this workload and precision
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a plain copy
+    of known size), or None when there is none or the kernel source has
+    changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_solve_{workload_name}_{precision}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"k_basis_{workload_name}_{precision}_traffic.md")
     src = os.path.join(ROOT, "paper_1202_0098_amd", "csrc", "ma_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -240,13 +244,13 @@ def measured_traffic(workload_name, precision):
     if fields.get("kernel source sha256") != digest:
         return None
     try:
-        return float(fields["HBM bytes per launch"])
+        return float(fields["HBM bytes per step"])
     except (KeyError, ValueError):
         return None
 
 
 def kernel_model(s, st, reg_atoms, loc_blocks, precision):
-    """Algorithmic bytes and flops of one column-kernel launch.
+    """Algorithmic bytes and flops of the basis kernel over one step.
 
     Per column j with region dimension n = o * (atoms of the region), local
     operator blocks nb (o x o each), nu_eff = L accepted basis vectors and c

@@ -135,6 +135,10 @@ typedef struct {
     int32_t chunk_columns;  /* columns per chunk of the processing order (0 = as many
                                as a 4 GiB chunk buffer holds); a solve of several
                                chunks launches eagerly instead of replaying graphs */
+    int32_t pipeline;       /* >= 2 (default 4): a solve of at least 2048 * pipeline
+                               columns is cut into at least `pipeline` chunks, and the
+                               eigensolver of chunk k runs on a second stream beside
+                               the basis kernel of chunk k + 1 (0 or 1: off) */
 } ma_opts;
 
 /* Schedules of the persistent column kernel.  LPT: one queue, columns with

@@ -57,7 +57,7 @@ class _Opts(ctypes.Structure):
                 ("n_target", ctypes.c_double), ("start", ctypes.c_int32),
                 ("slots_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("basis_kernel", ctypes.c_int32),
-                ("chunk_columns", ctypes.c_int32)]
+                ("chunk_columns", ctypes.c_int32), ("pipeline", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):

@@ -83,6 +83,7 @@ struct ma_ctx {
     int device = 0;
     hipStream_t stream = nullptr;     // the caller's stream
     hipStream_t own = nullptr;        // used instead when the caller's is the null stream
+    hipStream_t aux = nullptr;        // eigensolver of chunk k beside the basis kernel of chunk k+1
     hipEvent_t evu = nullptr;         // orders `own` after the caller's null stream
     // the stream the solve path enqueues on (the null stream cannot be captured)
     hipStream_t work_stream() const { return stream ? stream : own; }
@@ -129,7 +130,7 @@ struct ma_ctx {
     DevBuf cols, order, qbounds, gstart, ws, eps, wts, amp, amp_off, mid, stats, ctl, lohi, partial,
         Ecol, Ncol, sums;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evk0 = nullptr, evk1 = nullptr, eve1 = nullptr;
-    std::vector<hipEvent_t> chunk_ev;  // per-chunk timing of eager multi-chunk solves
+    std::vector<hipEvent_t> chunk_ev;  // per-chunk timing and ordering of multi-chunk solves
     uint64_t generation = 0;          // bumped by every ma_build_system
 
     // captured launch sequence and the configuration it was captured for
@@ -427,6 +428,7 @@ MA_API void ma_default_opts(ma_opts *o)
     o->use_graph = 1;
     o->basis_kernel = MA_BASIS_AUTO;
     o->chunk_columns = 0;
+    o->pipeline = 4;
 }
 
 MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
@@ -446,7 +448,8 @@ MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
         hipEventCreate(&c->evk0) != hipSuccess || hipEventCreate(&c->evk1) != hipSuccess ||
         hipEventCreate(&c->eve1) != hipSuccess ||
         hipEventCreateWithFlags(&c->evu, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return MA_EDEVICE;
     }
@@ -468,6 +471,7 @@ MA_API ma_status ma_destroy(ma_ctx *ctx)
     ctx->drop_graph();
     if (ctx->evu) (void)hipEventDestroy(ctx->evu);
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
     return MA_OK;
 }
@@ -797,6 +801,7 @@ struct Plan {
     bool bisect = false;
     int kind = ma::kBasisWorkspace;   // basis kernel
     int nchunks = 0, max_cn = 0;      // chunks of the processing order
+    bool pipelined = false;           // eigensolver of chunk k on the aux stream
     std::vector<int32_t> ch_c0, ch_cn, ch_items;   // per chunk: first column position,
                                                    // columns, work items
     std::vector<int32_t> hcols;
@@ -810,6 +815,8 @@ struct Plan {
         Jk.c0 = ch_c0[k];
         Jk.cn = ch_cn[k];
         Jk.qbounds = qb_dev + (int64_t)k * (J.nqueues + 1);
+        // pipelined: chunks alternate between two halves of the chunk buffer
+        if (pipelined && (k & 1)) Jk.mid = J.mid + (int64_t)max_cn * J.mid_stride;
         return Jk;
     }
 };
@@ -882,6 +889,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_GROUP)
         return ctx->fail(MA_EINVAL, "unknown basis kernel %d", opts.basis_kernel);
     if (opts.chunk_columns < 0) return ctx->fail(MA_EINVAL, "chunk_columns must be >= 0");
+    if (opts.pipeline < 0) return ctx->fail(MA_EINVAL, "pipeline must be >= 0");
     const bool fits = ma::basis_small_fits(ctx->nmax, P.nu, q, ctx->o);
     const bool gfits = ma::basis_group_fits(ctx->nmax, P.nu, ctx->o);
     if (opts.basis_kernel == MA_BASIS_ONCHIP && !fits)
@@ -956,7 +964,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     // chunks: whole work items, at most the chunk budget of columns each
     J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
     const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
-    const int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
+    int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
+    // pipelining: at least opts.pipeline chunks for solves large enough
+    if (opts.pipeline >= 2 && ncols >= (int64_t)opts.pipeline * 2048)
+        budget = std::min<int64_t>(budget, (ncols + opts.pipeline - 1) / opts.pipeline);
     std::vector<int32_t> ch_item0;   // first work item of each chunk
     {
         int64_t cols_in = 0;
@@ -970,6 +981,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         ch_item0.push_back(nitems);
     }
     P.nchunks = (int)ch_item0.size() - 1;
+    P.pipelined = opts.pipeline >= 2 && P.nchunks >= 2;
 
     // processing order of the work items, per chunk and queue
     std::vector<int32_t> witem(nitems);
@@ -1034,7 +1046,8 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * qb.size()), "queues");
     if (P.kind != ma::kBasisOnchip)
         HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
-    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.max_cn), "chunk buffer");
+    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.max_cn *
+                                 (P.pipelined ? 2 : 1)), "chunk buffer");
     HIPCHK(ctx, ctx->gstart.reserve(sizeof(int32_t) * (nitems + 1)), "work items");
     HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
     HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
@@ -1104,13 +1117,13 @@ hipError_t enqueue_basis(ma_ctx *ctx, const Plan &P, int k)
     return ma::launch_basis(P.S, Jk, P.kind, (int)std::min<int64_t>(P.slots, P.ch_items[k]), st);
 }
 
-hipError_t enqueue_eig(ma_ctx *ctx, const Plan &P, int k)
+hipError_t enqueue_eig(ma_ctx *ctx, const Plan &P, int k, hipStream_t st)
 {
-    return ma::launch_eig(P.S, P.chunk_job(k), ctx->work_stream());
+    return ma::launch_eig(P.S, P.chunk_job(k), st);
 }
 
 hipError_t enqueue_basis0(ma_ctx *ctx, const Plan &P) { return enqueue_basis(ctx, P, 0); }
-hipError_t enqueue_eig0(ma_ctx *ctx, const Plan &P) { return enqueue_eig(ctx, P, 0); }
+hipError_t enqueue_eig0(ma_ctx *ctx, const Plan &P) { return enqueue_eig(ctx, P, 0, ctx->work_stream()); }
 
 hipError_t net_refresh_bf16(ma_ctx *ctx, hipStream_t st);
 
@@ -1222,18 +1235,29 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         HIPCHK(ctx, hipEventRecord(ctx->eve1, st), "event");
         HIPCHK(ctx, hipGraphLaunch(ctx->gexec2, st), "graph launch");
     } else {
-        while ((int)ctx->chunk_ev.size() < 3 * P.nchunks) {
+        // eager: per chunk, events around the basis kernel (stream st) and the
+        // eigensolver (st, or the aux stream when pipelined: chunk k's
+        // eigensolver runs beside chunk k+1's basis kernel; chunk k+2 reuses
+        // chunk k's half of the chunk buffer only after that eigensolver)
+        while ((int)ctx->chunk_ev.size() < 6 * P.nchunks) {
             hipEvent_t ev;
             HIPCHK(ctx, hipEventCreate(&ev), "event");
             ctx->chunk_ev.push_back(ev);
         }
+        hipStream_t es = P.pipelined ? ctx->aux : st;
         for (int k = 0; k < P.nchunks; ++k) {
-            HIPCHK(ctx, hipEventRecord(ctx->chunk_ev[3 * k], st), "event");
+            hipEvent_t *ev = &ctx->chunk_ev[6 * k];
+            if (P.pipelined && k >= 2) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (k - 2) + 5], 0), "wait");
+            HIPCHK(ctx, hipEventRecord(ev[0], st), "event");
             HIPCHK(ctx, enqueue_basis(ctx, P, k), "basis kernel");
-            HIPCHK(ctx, hipEventRecord(ctx->chunk_ev[3 * k + 1], st), "event");
-            HIPCHK(ctx, enqueue_eig(ctx, P, k), "eigensolver kernel");
-            HIPCHK(ctx, hipEventRecord(ctx->chunk_ev[3 * k + 2], st), "event");
+            HIPCHK(ctx, hipEventRecord(ev[1], st), "event");
+            if (P.pipelined) HIPCHK(ctx, hipStreamWaitEvent(es, ev[1], 0), "wait");
+            HIPCHK(ctx, hipEventRecord(ev[2], es), "event");
+            HIPCHK(ctx, enqueue_eig(ctx, P, k, es), "eigensolver kernel");
+            HIPCHK(ctx, hipEventRecord(ev[3], es), "event");
+            HIPCHK(ctx, hipEventRecord(ev[5], es), "event");
         }
+        if (P.pipelined) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (P.nchunks - 1) + 5], 0), "wait");
         HIPCHK(ctx, enqueue_post(ctx, P), "launch");
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
@@ -1252,9 +1276,10 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         eig_ms = ms;
     } else {
         for (int k = 0; k < P.nchunks; ++k) {
-            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->chunk_ev[3 * k], ctx->chunk_ev[3 * k + 1]), "elapsed");
+            const hipEvent_t *ev = &ctx->chunk_ev[6 * k];
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]), "elapsed");
             basis_ms += ms;
-            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->chunk_ev[3 * k + 1], ctx->chunk_ev[3 * k + 2]), "elapsed");
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ev[2], ev[3]), "elapsed");
             eig_ms += ms;
         }
     }

@@ -99,7 +99,8 @@ def load(ctx: Context, path: str):
 
 def cg_stats(ctx: Context, tb, start: str, cg_tol=1e-8, precision="fp64", reps=3, mu=None):
     """Solve all columns of `tb` (already built) with the given start: CG
-    iterations (mean, p95), fallbacks, columns/s (best of reps, graph replay)."""
+    iterations (mean, p95), FP64 residual checks, fallbacks, columns/s (best
+    of reps, graph replay)."""
     import torch
     stats = torch.zeros(tb.M * STATS, dtype=torch.int32, device="cuda")
     o = tb.n_orb
@@ -120,17 +121,24 @@ def cg_stats(ctx: Context, tb, start: str, cg_tol=1e-8, precision="fp64", reps=3
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--train-seeds", default="2101-2112")
-    ap.add_argument("--eval-seeds", default="3001-3005")
+    ap.add_argument("--model", default="sp3", choices=["sp3", "spd"],
+                    help="sp3: train on diamond cells, evaluate on disordered cells; spd: train "
+                         "on small fcc spd cells, evaluate on a larger fcc spd cell")
+    ap.add_argument("--train-seeds", default="")
+    ap.add_argument("--eval-seeds", default="")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--cg-tol", type=float, default=1e-8)
     ap.add_argument("--precision", default="mixed_f64acc")
     ap.add_argument("--eval-atoms", type=int, default=8000)
+    ap.add_argument("--eval-cells", default="16,16,16")
     ap.add_argument("--save", default="")
     ap.add_argument("--json", default="")
     args = ap.parse_args(argv)
+    spd = args.model == "spd"
+    train_seeds = args.train_seeds or ("5101-5112" if spd else "2101-2112")
+    eval_seeds = args.eval_seeds or ("5000-5000" if spd else "3001-3005")
 
     def rng(s):
         a, b = (int(v) for v in s.split("-"))
@@ -142,12 +150,14 @@ def main(argv=None):
     ctx = Context(0)
     t0 = time.perf_counter()
     Xs, Ts = [], []
-    for seed in [1001]:
-        X, T = collect_pairs(ctx, synth.config_diamond64(seed))
-        Xs.append(X)
-        Ts.append(T)
-    for seed in rng(args.train_seeds):
-        X, T = collect_pairs(ctx, synth.config_diamond4096(seed))
+    if spd:
+        train_systems = [lambda sd=sd: synth.config_fcc_spd(sd, cells=(8, 8, 8))
+                         for sd in rng(train_seeds)]
+    else:
+        train_systems = [lambda: synth.config_diamond64(1001)] + \
+                        [lambda sd=sd: synth.config_diamond4096(sd) for sd in rng(train_seeds)]
+    for make in train_systems:
+        X, T = collect_pairs(ctx, make())
         Xs.append(X)
         Ts.append(T)
     import torch
@@ -160,26 +170,30 @@ def main(argv=None):
     train_s = time.perf_counter() - t0
     log(f"trained {args.epochs} epochs in {train_s:.1f}s, final loss {hist[-1]:.3e}")
     if args.save:
-        save(ctx, args.save, dict(train_seeds=args.train_seeds, epochs=args.epochs, loss=hist[-1]))
+        save(ctx, args.save, dict(model=args.model, train_seeds=train_seeds, epochs=args.epochs,
+                                  loss=hist[-1]))
     results = []
-    for seed in rng(args.eval_seeds):
-        tb = synth.config_disordered8000(seed, n_atoms=args.eval_atoms)
+    cells = tuple(int(v) for v in args.eval_cells.split(","))
+    for seed in rng(eval_seeds):
+        tb = (synth.config_fcc_spd(seed, cells=cells) if spd
+              else synth.config_disordered8000(seed, n_atoms=args.eval_atoms))
         ctx.build_tb(tb)
         ref = cg_stats(ctx, tb, "zero", 1e-12, "fp64", reps=1)
         z = cg_stats(ctx, tb, "zero", args.cg_tol, args.precision, mu=ref["mu"])
         l = cg_stats(ctx, tb, "learned", args.cg_tol, args.precision, mu=ref["mu"])
         ez = float(np.abs(z["rho"] - ref["rho"]).max())
         el = float(np.abs(l["rho"] - ref["rho"]).max())
-        row = dict(seed=seed, zero={k: v for k, v in z.items() if k != "rho"},
+        row = dict(seed=seed, system=tb.name, zero={k: v for k, v in z.items() if k != "rho"},
                    learned={k: v for k, v in l.items() if k != "rho"},
                    rho_err_zero=ez, rho_err_learned=el)
-        log(f"seed {seed}: CG iterations {z['cg_mean']:.2f} -> {l['cg_mean']:.2f} "
-            f"(p95 {z['cg_p95']:.0f} -> {l['cg_p95']:.0f}), fallback {l['fallback']:.3f}, "
+        log(f"{tb.name} seed {seed}: CG iterations {z['cg_mean']:.2f} -> {l['cg_mean']:.2f} "
+            f"(p95 {z['cg_p95']:.0f} -> {l['cg_p95']:.0f}), FP64 residual checks "
+            f"{z['judge_mean']:.2f} -> {l['judge_mean']:.2f}, fallback {l['fallback']:.3f}, "
             f"columns/s {z['cols_per_s']:.4g} -> {l['cols_per_s']:.4g}, "
             f"max|rho - rho(FP64, tol 1e-12)| zero {ez:.2e} learned {el:.2e}")
         results.append(row)
-    out = dict(train_pairs=int(X.shape[0]), train_s=train_s, loss_history=hist, eval=results,
-               cg_tol=args.cg_tol, precision=args.precision)
+    out = dict(model=args.model, train_pairs=int(X.shape[0]), train_s=train_s, loss_history=hist,
+               eval=results, cg_tol=args.cg_tol, precision=args.precision)
     if args.json:
         with open(args.json, "w") as f:
             json.dump(out, f, indent=1)

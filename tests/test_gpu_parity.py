@@ -242,6 +242,23 @@ def test_chunked_solve_matches_single_chunk(ctx, torch_cuda):
         assert np.array_equal(a[5], b[5])
 
 
+def test_pipelined_chunks_match_sequential(ctx, torch_cuda):
+    """The eigensolver of chunk k on a second stream beside the basis kernel
+    of chunk k + 1 (double-buffered chunk buffer) gives the sequential result
+    bit for bit."""
+    s = synth.config_diamond4096()
+    ctx.build_tb(s)
+    for kernel in ["workspace", "group"]:
+        _say(f"diamond4096 all columns, pipelined vs sequential chunks ({kernel} basis)")
+        a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel,
+                       pipeline=4)
+        b = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel,
+                       pipeline=0, chunk_columns=4096)
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert a[0].energy == b[0].energy and a[0].mu == b[0].mu
+        assert np.array_equal(a[5], b[5])
+
+
 @pytest.mark.parametrize("other", ["onchip", "group"])
 def test_basis_kernels_agree(ctx, torch_cuda, other):
     """The basis kernels (same method, different storage, grouping and
