@@ -10,20 +10,24 @@
 // H_A, S_A are the principal submatrices of H, S on the region of atom(j)
 // (real-space projection, Sec. 3), read through a per-region local block
 // index.  Thread t owns local rows t, t + NT, ...; the vector an SpMV reads
-// is staged in LDS.  Two variants:
+// is staged in LDS.  Three variants:
 //   k_basis_s  regions of at most 512 orbitals, nu <= 32: U lives in LDS,
 //              S U and the block-2 chain in registers (row-owned), and the
 //              Galerkin pair is accumulated as each vector is accepted, so the
 //              basis never leaves the compute unit;
 //   k_basis_g  any region: U, S U, H U and the chain live in a per-workgroup
-//              slice of a global workspace and the pair is formed on the FP64
-//              matrix cores.
-// Both write the pair and the basis rows the outputs need into a chunk buffer.
+//              slice of a global workspace, the second Gram-Schmidt pass of
+//              each vector is delayed into the next step (one dot sweep and
+//              one update sweep per vector) and the pair is formed on the
+//              FP64 matrix cores;
+//   k_basis_m  the columns of one atom in lockstep, every SpMV an SpMM.
+// All write the pair and the basis rows the outputs need into a chunk buffer.
 //
-// Eigensolver kernel (one wavefront per column): Cholesky of S~, cyclic
-// Jacobi of L^-1 H~ L^-T, the Ritz vectors at the rows of the outputs, Ritz
-// values and weights, and either the amplitudes v_ia v_ja (chemical potential
-// still to be found) or the Fermi-weighted rho, pi, E_j, N_j (Eqs. 13-14, 17).
+// Eigensolver kernel (one wavefront per column): Cholesky of S~, Householder
+// tridiagonalisation and implicit QL of L^-1 H~ L^-T, the Ritz vectors at
+// the rows of the outputs, Ritz values and weights, and either the
+// amplitudes v_ia v_ja (chemical potential still to be found) or the
+// Fermi-weighted rho, pi, E_j, N_j (Eqs. 13-14, 17).
 //
 // The remaining kernels bisect the chemical potential on the electron count
 // (Sec. 2, summation over j), weight the stored amplitudes with the Fermi
@@ -504,62 +508,203 @@ __device__ __forceinline__ void drain_queues_raw(const DevJob &J, int *s_idx, F 
 // ------------------------------------------------------------------------
 // large-region basis kernel: basis in the global workspace
 // ------------------------------------------------------------------------
-// out[m] = V[m] . x for m < L (x in LDS).  Each wavefront takes four
-// consecutive m at a time, keeping four independent load streams in flight.
-__device__ __forceinline__ void multidot(const double *__restrict__ V, int64_t ld, int L,
-                                         const double *x, int n, double *out)
+// Thread t owns local rows t, t + NTG, ...  The basis U, S U, H U and the
+// block-2 chain T live in a per-workgroup slice of the global workspace
+// (vector m at offset m * ld).  Each basis vector costs one fused dot sweep
+// and one fused update sweep over the stored vectors: the S-orthogonalisation
+// is classical Gram-Schmidt applied twice, with the second pass of each
+// vector delayed into the step that projects the next candidate (the delayed
+// reorthogonalisation of Bielich, Langou, Thomas, Swirydowicz, Yamazaki and
+// Boman, Parallel Computing 112 (2022)).  Step s therefore
+//   SpMV   S and H of the vector finalised in step s-1 (stored as S U, H U),
+//          S of the pending vector (once projected), H of the next chain
+//          source;
+//   dots   a = (S U)^T pending, b = (S U)^T candidate, and for the chain
+//          a_T = T^T pending chain vector, b_T = T^T (H of it);
+//   update u = (pending - U a) / beta with beta^2 = pending^T S pending - |a|^2,
+//          candidate - U b - u f becomes the next pending vector, where
+//          f = u^T S candidate = (pending^T S candidate - a.b) / beta;
+//          the chain likewise in the Euclidean inner product.
+// The block-1 candidate is H applied to the pending vector rather than to
+// the finished u: the two differ by H U a, which lies in the span already
+// built (Krylov property of block 1) and is removed by the projections; the
+// block-2 candidate is the pending chain vector, which differs from the
+// finished t by a vector in the span of earlier chain vectors.  Breakdown
+// (Eqs. 6-8 with the relative threshold tau) is judged on beta against the
+// candidate's norm rebuilt from both passes' coefficients, as with two
+// consecutive passes.
+
+// Sum of 2 x 4 dot products per task: task g < nv covers V rows 4g..4g+3
+// against x1, x2 (o1[m] = V[m].x1, o2[m] = V[m].x2), the remaining tasks W
+// rows against y1, y2 (p1, p2).  Each wavefront takes whole tasks, so every
+// basis vector is read once.
+__device__ __forceinline__ void dot_sweep(const double *__restrict__ V, int LV, const double *x1,
+                                          const double *x2, double *o1, double *o2,
+                                          const double *__restrict__ W, int LW, const double *y1,
+                                          const double *y2, double *p1, double *p2, int64_t ld,
+                                          int n)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int m0 = 4 * w; m0 < L; m0 += 4 * NWG) {
+    const int nv = (LV + 3) >> 2, nw = (LW + 3) >> 2;
+    for (int task = w; task < nv + nw; task += NWG) {
+        const bool first = task < nv;
+        const int m0 = 4 * (first ? task : task - nv);
+        const int L = first ? LV : LW;
         const int nm = min(4, L - m0);
-        const double *v0 = V + m0 * ld;
-        const double *v1 = V + (m0 + (nm > 1 ? 1 : 0)) * ld;
-        const double *v2 = V + (m0 + (nm > 2 ? 2 : 0)) * ld;
-        const double *v3 = V + (m0 + (nm > 3 ? 3 : 0)) * ld;
+        const double *B = first ? V : W;
+        const double *X1 = first ? x1 : y1;
+        const double *X2 = first ? x2 : y2;
+        const double *v0 = B + m0 * ld;
+        const double *v1 = B + (m0 + (nm > 1 ? 1 : 0)) * ld;
+        const double *v2 = B + (m0 + (nm > 2 ? 2 : 0)) * ld;
+        const double *v3 = B + (m0 + (nm > 3 ? 3 : 0)) * ld;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int i = lane; i < n; i += 64) {
-            const double xi = x[i];
-            a0 += v0[i] * xi;
-            a1 += v1[i] * xi;
-            a2 += v2[i] * xi;
-            a3 += v3[i] * xi;
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+        // two rows per lane and iteration: eight loads in flight
+        for (int i = lane; i < n; i += 128) {
+            const int i2 = i + 64;
+            const bool ok2 = i2 < n;
+            const int j2 = ok2 ? i2 : i;
+            const double e0 = v0[i], e1 = v1[i], e2 = v2[i], e3 = v3[i];
+            const double g0 = v0[j2], g1 = v1[j2], g2 = v2[j2], g3 = v3[j2];
+            const double xi = X1[i], zi = X2[i];
+            const double xj = ok2 ? X1[j2] : 0.0, zj = ok2 ? X2[j2] : 0.0;
+            a0 += e0 * xi;
+            a1 += e1 * xi;
+            a2 += e2 * xi;
+            a3 += e3 * xi;
+            b0 += e0 * zi;
+            b1 += e1 * zi;
+            b2 += e2 * zi;
+            b3 += e3 * zi;
+            a0 += g0 * xj;
+            a1 += g1 * xj;
+            a2 += g2 * xj;
+            a3 += g3 * xj;
+            b0 += g0 * zj;
+            b1 += g1 * zj;
+            b2 += g2 * zj;
+            b3 += g3 * zj;
         }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
-        a3 = wave_sum(a3);
-        if (lane == 0) {
-            out[m0] = a0;
-            if (nm > 1) out[m0 + 1] = a1;
-            if (nm > 2) out[m0 + 2] = a2;
-            if (nm > 3) out[m0 + 3] = a3;
+        double v[8] = {a0, a1, a2, a3, b0, b1, b2, b3};
+        wave_transpose_reduce<8>(v);
+        if (tr_writer<8>(lane)) {
+            const int k = tr_index<8>(lane);
+            const int m = m0 + (k & 3);
+            double *dst = (k < 4) ? (first ? o1 : p1) : (first ? o2 : p2);
+            if ((k & 3) < nm) dst[m] = v[0];
         }
     }
 }
 
-// l -= sum_m V[m] c[m] on the thread's rows.
+// s1[rr] = sum_m V[m][i] c1[m] and s2[rr] = sum_m V[m][i] c2[m] over m < cnt
+// on the thread's rows i = tid + rr * NTG (rows at or past n read row 0; the
+// caller discards them).  The loads of four vectors are issued before their
+// products, so 4 R loads are in flight.
 template <int R>
-__device__ __forceinline__ void sub_comb(double (&l)[R], const double *__restrict__ V, int64_t ld,
-                                         int L, const double *c, int n)
+__device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t ld, int cnt,
+                                           const double *c1, const double *c2, int n,
+                                           double (&s1)[R], double (&s2)[R])
 {
+    int off[R];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
         const int i = threadIdx.x + rr * NTG;
-        if (i < n) {
-            double acc = 0.0;
-#pragma unroll 8
-            for (int m = 0; m < L; ++m) acc += V[m * ld + i] * c[m];
-            l[rr] -= acc;
+        off[rr] = i < n ? i : 0;
+        s1[rr] = 0.0;
+        s2[rr] = 0.0;
+    }
+    int m = 0;
+    for (; m + 4 <= cnt; m += 4) {
+        double v[4][R];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) v[j][rr] = V[(m + j) * ld + off[rr]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double a = c1[m + j], b = c2[m + j];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                s1[rr] += v[j][rr] * a;
+                s2[rr] += v[j][rr] * b;
+            }
         }
+    }
+    for (; m < cnt; ++m) {
+        const double a = c1[m], b = c2[m];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const double v = V[m * ld + off[rr]];
+            s1[rr] += v * a;
+            s2[rr] += v * b;
+        }
+    }
+}
+
+// SpMV of three staged vectors on the thread's own rows:
+// ha = H xa, sa = S xa, sb = S xb, hd = H xd.
+template <int O, int R, typename TM, typename TX>
+__device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int o_rt,
+                                           const TM *__restrict__ Hv, const TM *__restrict__ Sv,
+                                           const TX *xa, const TX *xb, const TX *xd,
+                                           double (&ha)[R], double (&sa)[R], double (&sb)[R],
+                                           double (&hd)[R])
+{
+    const int o = O ? O : o_rt;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        const int i = threadIdx.x + rr * NTG;
+        TX h1 = 0, s1 = 0, s2 = 0, h3 = 0;
+        if (i < g.n) {
+            const int a = i / o;
+            const int ri = i - a * o;
+            const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
+#pragma unroll 4
+            for (int64_t kb = k0; kb < k1; ++kb) {
+                const int2 e = S.lblk[kb];
+                const int64_t base = (int64_t)e.y * (o * o) + ri * o;
+                const int xo = e.x * o;
+                if constexpr (O > 0) {
+#pragma unroll
+                    for (int cc = 0; cc < O; ++cc) {
+                        const TX hm = (TX)Hv[base + cc], sm = (TX)Sv[base + cc];
+                        const TX va = xa[xo + cc];
+                        h1 += hm * va;
+                        s1 += sm * va;
+                        s2 += sm * xb[xo + cc];
+                        h3 += hm * xd[xo + cc];
+                    }
+                } else {
+                    for (int cc = 0; cc < o; ++cc) {
+                        const TX hm = (TX)Hv[base + cc], sm = (TX)Sv[base + cc];
+                        const TX va = xa[xo + cc];
+                        h1 += hm * va;
+                        s1 += sm * va;
+                        s2 += sm * xb[xo + cc];
+                        h3 += hm * xd[xo + cc];
+                    }
+                }
+            }
+        }
+        ha[rr] = (double)h1;
+        sa[rr] = (double)s1;
+        sb[rr] = (double)s2;
+        hd[rr] = (double)h3;
     }
 }
 
 struct SmemG {
-    double *xa, *xb;     // nmax each: SpMV inputs / dot operands
-    double *cf;          // 4 * kMaxNu: coefficients
-    double *red;         // NWG
-    float *redf;         // NWG
+    double *da, *dp, *dz, *dh;   // nmax each: SpMV input a, pending u, chain vector, H image
+    void *fx;                    // PREC 1: the three SpMV inputs in FP32 (3 nmax floats)
+    double *cf;                  // coefficients, 6 * (kMaxNu + 1)
+    double *part;                // 4 * NWG wavefront partial sums
+    double *red;                 // NWG
+    float *redf;                 // NWG
 };
+
+// candidate sources of a step
+enum { kCandNone = 0, kCandBlock1 = 1, kCandChain = 2 };
 
 template <int O, int R, int PREC>
 __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &sm, int c, int s,
@@ -568,105 +713,219 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
     using TM = typename std::conditional<PREC != 0, float, double>::type;
     using TX = typename std::conditional<PREC == 1, float, double>::type;
     const int o = O ? O : S.o;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t ld = S.nmax;
     const int nu = J.nu;
     const Col g = make_col(S, J, c, o);
     const int n = g.n;
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
-    TX *xaX = reinterpret_cast<TX *>(sm.xa);
-    TX *xbX = reinterpret_cast<TX *>(sm.xb);
+    // SpMV inputs: a = finished vector, b = pending vector, d = H source
+    TX *xa, *xb, *xz;
+    if constexpr (PREC == 1) {
+        xa = reinterpret_cast<TX *>(sm.fx);
+        xb = xa + ld;
+        xz = xb + ld;
+    } else {
+        xa = reinterpret_cast<TX *>(sm.da);
+        xb = reinterpret_cast<TX *>(sm.dp);
+        xz = reinterpret_cast<TX *>(sm.dz);
+    }
 
     double x[R];
     int iters, nres, status, start;
-    inner_cg<O, R, NTG, PREC>(S, J, g, c, sm.xa, sm.xb, sm.red, sm.redf, x, iters, nres, status,
+    inner_cg<O, R, NTG, PREC>(S, J, g, c, sm.da, sm.dp, sm.red, sm.redf, x, iters, nres, status,
                               start);
 
     int L = 0;
     double *mid = J.mid + (int64_t)s * J.mid_stride;
     if (status == 0) {
-        // ---------------- basis of K_p(H;e_j) + K_q(H;s_j) ----------------
-        double l[R], w[R], hv[R], zv[R], t[R];
-        double *c1 = sm.cf, *c2 = sm.cf + kMaxNu;
-
-        // One candidate (Eqs. 6-8): two classical Gram-Schmidt passes with
-        // coefficients u_m^T S l, S-normalisation, breakdown test, and
-        // acceptance u = l/beta, S u, H u.  With `chain`, also zv = H t.
-        auto append = [&](bool chain) __attribute__((always_inline)) -> bool {
-            for (int pass = 0; pass < 2; ++pass) {
-                double *cc = pass ? c2 : c1;
-                store_rows<R, NTG, double>(sm.xa, l, n);
-                __syncthreads();
-                multidot(SU, ld, L, sm.xa, n, cc);
-                __syncthreads();
-                sub_comb<R>(l, U, ld, L, cc, n);
+        constexpr int CS = kMaxNu + 1;
+        double *ca = sm.cf, *cbuf0 = ca + CS, *cbuf1 = cbuf0 + CS;
+        double *cat = cbuf1 + CS, *ctb0 = cat + CS, *ctb1 = ctb0 + CS;
+        // State between steps lives in LDS (rows owned by their thread):
+        // xa the finished vector whose S and H images are not yet stored,
+        // dp the pending vector (projected once, first-pass coefficients in
+        // cp), dz the pending chain vector (projected once against T,
+        // coefficients in ctp); with PREC 1, xb and xz hold FP32 copies of
+        // dp and dz for the SpMV.
+        bool has_fin = false, has_pend = J.p > 0;
+        bool b1_live = true, chain_live = J.q > 0;
+        int nb1 = J.p > 0 ? 1 : 0, k = 0, ping = 0;
+        double cp_scale = 1.0, ctp_scale = 1.0;
+        __syncthreads();   // the CG's last reads of da, dp are done
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int i = tid + rr * NTG;
+            if (i < n) {
+                const double e = (i == g.jl) ? 1.0 : 0.0;   // block 1 starts at e_j
+                xa[i] = (TX)0.0;
+                sm.dp[i] = e;
+                sm.dz[i] = x[rr];                           // block 2 starts at s_j
+                if constexpr (PREC == 1) {
+                    xb[i] = (TX)e;
+                    xz[i] = (TX)x[rr];
+                }
             }
-            store_rows<R, NTG, TX>(xaX, l, n);
-            if (chain) store_rows<R, NTG, TX>(xbX, t, n);
-            __syncthreads();
-            if (chain)
-                spmv_rows<O, R, NTG, TM, TX, true, true, true>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
-            else
-                spmv_rows<O, R, NTG, TM, TX, true, true, false>(S, g, o, Hv, Sv, xaX, xbX, hv, w, zv);
-            const double bb = block_sum<NWG>(dot_rows<R, NTG>(l, w, n), sm.red);
-            double b0 = bb;
-            for (int m = 0; m < L; ++m) b0 += (c1[m] + c2[m]) * (c1[m] + c2[m]);
-            if (!(bb > 0.0) || !(b0 > 0.0) || sqrt(bb) <= J.tau * sqrt(b0)) return false;
-            const double inv = 1.0 / sqrt(bb);
+        }
+        for (;;) {
+            const int kind = (b1_live && nb1 < J.p) ? kCandBlock1
+                             : chain_live ? kCandChain : kCandNone;
+            if (!has_fin && !has_pend && kind == kCandNone) break;
+            const bool need_z = kind == kCandChain && k + 1 < J.q;   // next raw chain vector
+            const TX *xd = kind == kCandChain ? xz : xb;
+            double *cb = ping ? cbuf1 : cbuf0, *cp = ping ? cbuf0 : cbuf1;
+            double *ctb = ping ? ctb1 : ctb0, *ctp = ping ? ctb0 : ctb1;
+
+            // ---- SpMV ----
+            __syncthreads();   // staged vectors visible
+            double hf[R], sf[R], sp[R], hz[R];
+            spmv3_rows<O, R, TM, TX>(S, g, o, Hv, Sv, xa, xb, xd, hf, sf, sp, hz);
+            if (has_fin) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int i = tid + rr * NTG;
+                    if (i < n) {
+                        SU[(L - 1) * ld + i] = sf[rr];
+                        K[(L - 1) * ld + i] = hf[rr];
+                    }
+                }
+            }
+            if (kind == kCandNone && !has_pend) break;   // tail: images of the last vector stored
+            // row-local parts of pending^T S pending, pending^T S candidate,
+            // chain^T chain, chain^T (H chain)
+            double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int i = tid + rr * NTG;
                 if (i < n) {
-                    U[L * ld + i] = l[rr] * inv;
-                    SU[L * ld + i] = w[rr] * inv;
-                    K[L * ld + i] = hv[rr] * inv;
+                    const double up = sm.dp[i], zt = sm.dz[i];
+                    const double cand = kind == kCandChain ? zt : hz[rr];
+                    sm.dh[i] = hz[rr];
+                    q0 += up * sp[rr];
+                    q1 += sp[rr] * cand;
+                    q2 += zt * zt;
+                    q3 += zt * hz[rr];
                 }
-                l[rr] = hv[rr] * inv;   // next block-1 seed: H u_L
             }
-            ++L;
-            return true;
-        };
+            {
+                double v[4] = {q0, q1, q2, q3};
+                wave_transpose_reduce<4>(v);
+                if (tr_writer<4>(lane)) sm.part[wv * 4 + tr_index<4>(lane)] = v[0];
+            }
+            __syncthreads();   // LDS inputs, partials and the S U, H U rows visible
 
-        // block 1: seeds e_j, H u_1, H u_2, ...
+            // ---- dots ----
+            const int Lb = kind != kCandNone ? L : 0;   // candidate dots
+            const int La = has_pend ? L : 0;            // reorthogonalisation dots
+            const int kt = kind == kCandChain ? k : 0;
+            dot_sweep(SU, max(La, Lb), sm.dp, kind == kCandChain ? sm.dz : sm.dh, ca, cb, T, kt,
+                      sm.dz, sm.dh, cat, ctb, ld, n);
+            __syncthreads();
+
+            // ---- decisions (every thread, same values) ----
+            double nu_p = 0.0, e_p = 0.0, nu_t = 0.0, e_t = 0.0;
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) l[rr] = (tid + rr * NTG) == g.jl ? 1.0 : 0.0;
-        for (int step = 0; step < J.p; ++step)
-            if (!append(false)) break;
+            for (int w = 0; w < NWG; ++w) {
+                nu_p += sm.part[w * 4 + 0];
+                e_p += sm.part[w * 4 + 1];
+                nu_t += sm.part[w * 4 + 2];
+                e_t += sm.part[w * 4 + 3];
+            }
+            // Candidates are rescaled as they are projected (block 1: H u =
+            // H pending / beta; chain: H t = H chain / eta), so the stored
+            // first-pass coefficients refer to the unscaled vectors and are
+            // multiplied by the scale when the rebuilt norm is formed.
+            bool acc_u = false;
+            double beta = 1.0, f = 0.0;
+            if (has_pend) {
+                double asq = 0.0, tot = 0.0, ab = 0.0;
+                for (int m = 0; m < L; ++m) {
+                    const double cm = cp_scale * cp[m] + ca[m];
+                    asq += ca[m] * ca[m];
+                    tot += cm * cm;
+                    if (kind != kCandNone) ab += ca[m] * cb[m];
+                }
+                const double bb = nu_p - asq, b0 = bb + tot;
+                acc_u = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
+                if (acc_u) {
+                    beta = sqrt(bb);
+                    f = (e_p - ab) / beta;
+                }
+            }
+            bool acc_t = false;
+            double eta = 1.0, ft = 0.0;
+            if (kind == kCandChain) {
+                double asq = 0.0, tot = 0.0, ab = 0.0;
+                for (int m = 0; m < k; ++m) {
+                    const double cm = ctp_scale * ctp[m] + cat[m];
+                    asq += cat[m] * cat[m];
+                    tot += cm * cm;
+                    ab += cat[m] * ctb[m];
+                }
+                const double ee = nu_t - asq, e0 = ee + tot;
+                acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
+                if (acc_t) {
+                    eta = sqrt(ee);
+                    ft = (e_t - ab) / eta;
+                }
+            }
+            // a block-1 candidate is H of the pending vector: void if that broke down
+            const bool new_pend = (kind == kCandBlock1 && acc_u) || (kind == kCandChain && acc_t);
+            const bool new_chain = need_z && acc_t;
+            const double inv_b = 1.0 / beta, inv_e = 1.0 / eta;
+            const double sc = kind == kCandBlock1 ? inv_b : 1.0;
 
-        // block 2: chain t_1 = s_j / |s_j|, t_{k+1} = H t_k orthonormalised
-        if (J.q > 0) {
-            const double ns = sqrt(block_sum<NWG>(dot_rows<R, NTG>(x, x, n), sm.red));
+            // ---- update sweep: finish u and t, project the candidates once ----
+            double sa[R], sb[R], ta[R], tb[R];
+            comb2_rows<R>(U, ld, (acc_u || new_pend) ? L : 0, ca, cb, n, sa, sb);
+            comb2_rows<R>(T, ld, acc_t ? k : 0, cat, ctb, n, ta, tb);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int i = tid + rr * NTG;
-                t[rr] = x[rr] / ns;
-                if (i < n) T[i] = t[rr];
-            }
-            for (int k = 0; k < J.q; ++k) {
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) l[rr] = t[rr];
-                const bool last = (k + 1 == J.q);
-                append(!last);
-                if (last) break;
-                // Euclidean Gram-Schmidt of H t_k against t_1..t_k, twice
-                const double eta0 = sqrt(block_sum<NWG>(dot_rows<R, NTG>(zv, zv, n), sm.red));
-                for (int pass = 0; pass < 2; ++pass) {
-                    store_rows<R, NTG, double>(sm.xb, zv, n);
-                    __syncthreads();
-                    multidot(T, ld, k + 1, sm.xb, n, c1);
-                    __syncthreads();
-                    sub_comb<R>(zv, T, ld, k + 1, c1, n);
-                }
-                const double eta = sqrt(block_sum<NWG>(dot_rows<R, NTG>(zv, zv, n), sm.red));
-                if (!(eta > J.tau * eta0)) break;
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr) {
-                    const int i = tid + rr * NTG;
-                    t[rr] = zv[rr] / eta;
-                    if (i < n) T[(k + 1) * ld + i] = t[rr];
+                if (i < n) {
+                    const double up = sm.dp[i], zt = sm.dz[i], hv = sm.dh[i];
+                    const double u = (up - sa[rr]) * inv_b;
+                    const double cand = kind == kCandChain ? zt : hv;
+                    const double nl = (cand - sb[rr] - (acc_u ? f * u : 0.0)) * sc;
+                    const double t = (zt - ta[rr]) * inv_e;
+                    const double nz = (hv - tb[rr] - ft * t) * inv_e;
+                    if (acc_t) T[k * ld + i] = t;
+                    if (acc_u) {
+                        U[L * ld + i] = u;
+                        xa[i] = (TX)u;
+                    }
+                    const double pn = new_pend ? nl : 0.0;
+                    sm.dp[i] = pn;
+                    if constexpr (PREC == 1) xb[i] = (TX)pn;
+                    if (new_chain) {
+                        sm.dz[i] = nz;
+                        if constexpr (PREC == 1) xz[i] = (TX)nz;
+                    }
                 }
             }
+            if (tid == 0) {
+                if (acc_u) cb[L] = f;    // coefficient of the new pending vector on u_L
+                if (acc_t) ctb[k] = ft;
+            }
+            if (kind == kCandBlock1) {
+                if (acc_u) ++nb1;
+                else b1_live = false;
+            }
+            if (kind == kCandChain) {
+                if (acc_t) {
+                    ++k;
+                    chain_live = k < J.q;
+                } else {
+                    chain_live = false;
+                }
+            }
+            if (acc_u) ++L;
+            cp_scale = sc;
+            ctp_scale = inv_e;
+            has_fin = acc_u;
+            has_pend = new_pend;
+            ping ^= 1;
         }
         __syncthreads();   // basis writes visible to the whole workgroup
 
@@ -679,9 +938,8 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
         // eigensolver symmetrises.
         double *Xh = mid, *Xs = mid + (int64_t)nu * nu;
         {
-            const int w = tid >> 6, lane = tid & 63;
             const int nt = (L + 15) >> 4;
-            for (int tile = w; tile < nt * nt; tile += NWG) {
+            for (int tile = wv; tile < nt * nt; tile += NWG) {
                 const int mt = tile / nt, ntc = tile - mt * nt;
                 const int m = mt * 16 + (lane & 15), nn = ntc * 16 + (lane & 15);
                 const int kk = lane >> 4;
@@ -729,24 +987,40 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
     __syncthreads();
 }
 
+// LDS of the workspace kernel, in doubles: four vectors, the FP32 SpMV inputs
+// of PREC 1 (1.5 vectors) and the coefficients
+__host__ __device__ constexpr int64_t global_smem_doubles(int64_t nmax)
+{
+    return 4 * nmax + (3 * nmax + 1) / 2 + 6 * (kMaxNu + 1) + 4 * NWG;
+}
+
+// waves per SIMD the register allocation aims at: 3 for up to two rows per
+// thread, else 2
+template <int R>
+__host__ __device__ constexpr int global_waves() { return R <= 2 ? 3 : 2; }
+
 template <int O, int R, int PREC>
-__global__ void __launch_bounds__(NTG) k_basis_g(DevSystem S, DevJob J)
+__global__ void __launch_bounds__(NTG, global_waves<R>()) k_basis_g(DevSystem S, DevJob J)
 {
     extern __shared__ double smem[];
     __shared__ double red[NWG];
     __shared__ float redf[NWG];
     __shared__ int s_idx;
+    const int64_t nm = S.nmax;
     SmemG sm;
-    sm.xa = smem;
-    sm.xb = smem + S.nmax;
-    sm.cf = smem + 2 * S.nmax;
+    sm.da = smem;
+    sm.dp = smem + nm;
+    sm.dz = smem + 2 * nm;
+    sm.dh = smem + 3 * nm;
+    sm.fx = smem + 4 * nm;
+    sm.cf = smem + 4 * nm + (3 * nm + 1) / 2;
+    sm.part = sm.cf + 6 * (kMaxNu + 1);
     sm.red = red;
     sm.redf = redf;
-    const int64_t ld = S.nmax;
     double *U = J.ws + (int64_t)blockIdx.x * J.ws_stride;
-    double *SU = U + J.nu * ld;
-    double *K = SU + J.nu * ld;
-    double *T = K + J.nu * ld;
+    double *SU = U + J.nu * nm;
+    double *K = SU + J.nu * nm;
+    double *T = K + J.nu * nm;
     drain_queues(J, &s_idx, [&](int c, int s) __attribute__((always_inline)) {
         basis_global<O, R, PREC>(S, J, sm, c, s, U, SU, K, T);
     });
@@ -2461,7 +2735,7 @@ size_t basis_smem_bytes(int nmax, int nu, int kind, int o)
         const int b = basis_group_width(o);
         return sizeof(double) * (2 * (size_t)b * nmax + 2 * (size_t)b * kMaxNu + (512 / 64) * 16);
     }
-    return sizeof(double) * (2 * (size_t)nmax + 4 * kMaxNu);
+    return sizeof(double) * (size_t)global_smem_doubles(nmax);
 }
 
 hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st)
