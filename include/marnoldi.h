@@ -122,9 +122,10 @@ typedef struct {
     int32_t use_graph;      /* 1: capture the launch sequence in a hipGraph and replay it
                                while the configuration and buffers are unchanged */
     int32_t basis_kernel;   /* MA_BASIS_AUTO: the autotuned kernel for (p, q, precision)
-                               if ma_autotune ran, else MA_BASIS_GROUP where it applies,
-                               else MA_BASIS_WORKSPACE.  MA_BASIS_WORKSPACE: one column
-                               per workgroup, basis in a device workspace.
+                               if ma_autotune ran, else MA_BASIS_WORKSPACE.
+                               MA_BASIS_WORKSPACE: one column per workgroup, basis in a
+                               device workspace, one dot sweep and one update sweep per
+                               basis vector.
                                MA_BASIS_ONCHIP: one column per workgroup, basis in LDS
                                and registers (regions of at most 512 orbitals,
                                p + q <= 32, q <= 16; q <= 8 when p + q <= 16).

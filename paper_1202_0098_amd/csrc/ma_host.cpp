@@ -104,7 +104,8 @@ struct ma_ctx {
     // system sizes
     int o = 0, n_atoms = 0;
     int64_t nblk = 0, M = 0;
-    int nmax = 0, maxpat = 0;
+    int nmax = 0, maxpat = 0, max_nat = 0;
+    int64_t max_lnnz = 0;
     std::vector<int32_t> reg_len_of_atom;   // host: region atoms per atom (for ordering)
     std::vector<int64_t> lblk_of_atom;      // host: local operator blocks per atom
     std::vector<int32_t> pat_blocks;        // host: blocks in each atom's block-row
@@ -197,6 +198,9 @@ struct ma_ctx {
         S.jloc = jloc.as<int32_t>();
         S.blk_loc = blk_loc.as<int32_t>();
         S.out_loc = out_loc.as<int32_t>();
+        S.max_nat = max_nat;
+        S.max_lnnz = (int)max_lnnz;
+        S.lidx = ma::global_lidx_fits(nmax, max_nat, (int)max_lnnz) ? 1 : 0;
         return S;
     }
 };
@@ -634,8 +638,9 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     if (bad_region >= 0)
         return ctx->fail(MA_EINVAL, "region of atom %lld does not contain its block-row pattern",
                          (long long)bad_region.load());
-    int nmax = 0, maxpat = 0;
+    int nmax = 0, maxpat = 0, max_nat = 0;
     for (int r = 0; r < nreg; ++r) nmax = std::max(nmax, h_reg_len[r] * o);
+    for (int r = 0; r < nreg; ++r) max_nat = std::max(max_nat, h_reg_len[r]);
     for (int a = 0; a < n; ++a) maxpat = std::max(maxpat, (int)(bp[a + 1] - bp[a]) * o);
     if (nmax > 8 * ma::kThreads)
         return ctx->fail(MA_EINVAL, "region dimension %d exceeds the supported %d", nmax,
@@ -748,6 +753,9 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     ctx->M = (int64_t)n * o;
     ctx->nmax = nmax;
     ctx->maxpat = maxpat;
+    ctx->max_nat = max_nat;
+    ctx->max_lnnz = 0;
+    for (int r = 0; r < nreg; ++r) ctx->max_lnnz = std::max<int64_t>(ctx->max_lnnz, cnt[r + 1]);
     ctx->reg_len_of_atom.resize(n);
     ctx->lblk_of_atom.resize(n);
     ctx->pat_blocks.resize(n);
@@ -899,11 +907,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         return ctx->fail(MA_EINVAL, "the atom-group basis kernel needs 4 or 9 orbitals per atom "
                          "and regions it can stage (o = %d, %d orbitals)", ctx->o, ctx->nmax);
     // automatic choice: the autotuned kernel if there is one, else the
-    // atom-group kernel where it applies, else the workspace kernel
+    // workspace kernel (the fastest untuned choice on every shape measured)
     int want_kernel = opts.basis_kernel;
     if (want_kernel == MA_BASIS_AUTO)
-        want_kernel = tn && tn->kernel != MA_BASIS_AUTO ? tn->kernel
-                      : gfits ? MA_BASIS_GROUP : MA_BASIS_WORKSPACE;
+        want_kernel = tn && tn->kernel != MA_BASIS_AUTO ? tn->kernel : MA_BASIS_WORKSPACE;
     if ((want_kernel == MA_BASIS_ONCHIP && !fits) || (want_kernel == MA_BASIS_GROUP && !gfits))
         want_kernel = MA_BASIS_WORKSPACE;
     P.kind = want_kernel == MA_BASIS_ONCHIP ? ma::kBasisOnchip
@@ -965,14 +972,31 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
     const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
     int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
-    // pipelining: at least opts.pipeline chunks for solves large enough
-    if (opts.pipeline >= 2 && ncols >= (int64_t)opts.pipeline * 2048)
-        budget = std::min<int64_t>(budget, (ncols + opts.pipeline - 1) / opts.pipeline);
+    // pipelining: for solves large enough, opts.pipeline + 2 chunks whose
+    // sizes fall geometrically (ratio 0.7), so the eigensolver of each chunk
+    // fits beside the basis kernel of the next and the last one, which
+    // nothing overlaps, is short; equal chunks where the chunk buffer caps
+    // the first
+    std::vector<int64_t> target;   // column target per chunk
+    if (opts.pipeline >= 2 && ncols >= (int64_t)opts.pipeline * 2048) {
+        const int nch = opts.pipeline + 2;
+        const double r = 0.7;
+        double norm = 0.0;
+        for (int k = 0; k < nch; ++k) norm += std::pow(r, k);
+        for (int k = 0; k < nch; ++k)
+            target.push_back(std::max<int64_t>(1, std::llround((double)ncols * std::pow(r, k) / norm)));
+        if (target[0] > budget) {
+            target.clear();
+            budget = std::min<int64_t>(budget, (ncols + opts.pipeline - 1) / opts.pipeline);
+        }
+    }
     std::vector<int32_t> ch_item0;   // first work item of each chunk
     {
         int64_t cols_in = 0;
         for (int w = 0; w < nitems; ++w) {
-            if (w == 0 || cols_in + item_len(w) > budget) {
+            const size_t k = ch_item0.size() - 1;   // current chunk (w > 0)
+            const int64_t lim = (w > 0 && k < target.size()) ? target[k] : budget;
+            if (w == 0 || cols_in + item_len(w) > lim) {
                 ch_item0.push_back(w);
                 cols_in = 0;
             }
@@ -1062,7 +1086,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     }
     HIPCHK(ctx, ctx->ctl.reserve(sizeof(int) * 16), "ctl");
     HIPCHK(ctx, ctx->lohi.reserve(sizeof(double) * 2), "lohi");
-    HIPCHK(ctx, ctx->partial.reserve(sizeof(double) * ma::kCountBlocks * ma::kBisectTrials), "partial");
+    HIPCHK(ctx, ctx->partial.reserve(sizeof(double) * (ma::kCountBlocks * ma::kBisectTrials + 1)), "partial");
     HIPCHK(ctx, ctx->Ecol.reserve(sizeof(double) * ncols), "Ecol");
     HIPCHK(ctx, ctx->Ncol.reserve(sizeof(double) * ncols), "Ncol");
     HIPCHK(ctx, ctx->sums.reserve(sizeof(double) * 2), "sums");

@@ -43,6 +43,10 @@ struct DevSystem {
                                // inside the region of its row atom
     const int32_t *out_loc;    // n_atoms * kNbOut: local position (in the atom's own
                                // region) of its kNbOut nearest atoms, -1 if outside
+    int max_nat;               // largest region (atoms)
+    int max_lnnz;              // largest region operator (local blocks)
+    int lidx;                  // 1: the workspace kernel stages a region's local block
+                               // index in LDS for its SpMVs
 };
 
 // One solve.  Columns are processed in chunks of the processing order: the
@@ -111,6 +115,8 @@ bool basis_small_fits(int nmax, int nu, int q, int o);
 bool basis_group_fits(int nmax, int nu, int o);
 int basis_group_width(int o);   // columns of one atom solved together
 size_t basis_smem_bytes(int nmax, int nu, int kind, int o);
+// whether the workspace kernel keeps a region's local block index in LDS
+bool global_lidx_fits(int nmax, int max_nat, int max_lnnz);
 int basis_rows_per_thread(int nmax);
 hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st);
 hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots, hipStream_t st);

@@ -181,6 +181,9 @@ struct Col {
     const int64_t *rp;   // local block-row pointers (n_at + 1)
     int jl;              // local index of j
     int A, r;            // atom and orbital of j
+    bool lidx;           // the block index below is staged in LDS
+    const int *srp;      // LDS: block-row pointers relative to rp[0]
+    const int2 *sblk;    // LDS: the region's local blocks
 };
 
 __device__ __forceinline__ Col make_col(const DevSystem &S, const DevJob &J, int c, int o)
@@ -194,7 +197,26 @@ __device__ __forceinline__ Col make_col(const DevSystem &S, const DevJob &J, int
     g.n = g.n_at * o;
     g.rp = S.lrp + S.lrp_off[rid];
     g.jl = S.jloc[g.A] * o + g.r;
+    g.lidx = false;
+    g.srp = nullptr;
+    g.sblk = nullptr;
     return g;
+}
+
+// Copy the column's region block index into LDS (the whole workgroup), so
+// every SpMV of the column reads it from there: one global round trip per
+// SpMV (the operator values) instead of three dependent ones.
+template <int NT>
+__device__ __forceinline__ void stage_col_index(const DevSystem &S, Col &g, int *srp, int2 *sblk)
+{
+    const int64_t b0 = g.rp[0];
+    const int nnz = (int)(g.rp[g.n_at] - b0);
+    for (int a = threadIdx.x; a <= g.n_at; a += NT) srp[a] = (int)(g.rp[a] - b0);
+    for (int k = threadIdx.x; k < nnz; k += NT) sblk[k] = S.lblk[b0 + k];
+    __syncthreads();
+    g.lidx = true;
+    g.srp = srp;
+    g.sblk = sblk;
 }
 
 // SpMV on the thread's own rows: hy = H x, sy = S x (x in LDS), zy = H xb.
@@ -213,12 +235,7 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
         if (i < g.n) {
             const int a = i / o;
             const int ri = i - a * o;
-            const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
-            // several blocks in flight: the index and value loads of a block
-            // do not depend on the previous block
-#pragma unroll 4
-            for (int64_t kb = k0; kb < k1; ++kb) {
-                const int2 e = S.lblk[kb];
+            auto blk = [&](const int2 e) __attribute__((always_inline)) {
                 const int64_t base = (int64_t)e.y * (o * o) + ri * o;
                 const int xo = e.x * o;
                 if constexpr (O > 0) {
@@ -237,6 +254,17 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
                         if (DO_Z) z += (TX)Hv[base + cc] * xb[xo + cc];
                     }
                 }
+            };
+            if (g.lidx) {
+                const int k0 = g.srp[a], k1 = g.srp[a + 1];
+#pragma unroll 8
+                for (int kb = k0; kb < k1; ++kb) blk(g.sblk[kb]);
+            } else {
+                // several blocks in flight: the index and value loads of a
+                // block do not depend on the previous block
+                const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
+#pragma unroll 4
+                for (int64_t kb = k0; kb < k1; ++kb) blk(S.lblk[kb]);
             }
         }
         hy[rr] = (double)h;
@@ -652,6 +680,8 @@ __device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int
                                            double (&hd)[R])
 {
     const int o = O ? O : o_rt;
+    constexpr int OB = O > 0 ? O : 1;   // the batched path below is taken for O > 0 only
+    constexpr int NB = O > 4 ? 2 : sizeof(TM) == 8 ? 3 : 4;   // blocks per batch
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
         const int i = threadIdx.x + rr * NTG;
@@ -659,10 +689,7 @@ __device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int
         if (i < g.n) {
             const int a = i / o;
             const int ri = i - a * o;
-            const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
-#pragma unroll 4
-            for (int64_t kb = k0; kb < k1; ++kb) {
-                const int2 e = S.lblk[kb];
+            auto blk = [&](const int2 e) __attribute__((always_inline)) {
                 const int64_t base = (int64_t)e.y * (o * o) + ri * o;
                 const int xo = e.x * o;
                 if constexpr (O > 0) {
@@ -685,6 +712,47 @@ __device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int
                         h3 += hm * xd[xo + cc];
                     }
                 }
+            };
+            if (g.lidx) {
+                // batches of NB blocks: their value loads are issued before
+                // any product (blocks past the row's end read its first
+                // block and add nothing)
+                const int k0 = g.srp[a], k1 = g.srp[a + 1];
+                if constexpr (O == 0) {
+                    for (int kb = k0; kb < k1; ++kb) blk(g.sblk[kb]);
+                } else for (int kb = k0; kb < k1; kb += NB) {
+                    int2 e[NB];
+                    TM hm[NB][OB], sm[NB][OB];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        e[j] = g.sblk[kb + j < k1 ? kb + j : k0];
+                        const int64_t base = (int64_t)e[j].y * (o * o) + ri * o;
+#pragma unroll
+                        for (int cc = 0; cc < OB; ++cc) {
+                            hm[j][cc] = Hv[base + cc];
+                            sm[j][cc] = Sv[base + cc];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        const bool ok = kb + j < k1;
+                        const int xo = e[j].x * o;
+#pragma unroll
+                        for (int cc = 0; cc < OB; ++cc) {
+                            const TX hv = ok ? (TX)hm[j][cc] : (TX)0;
+                            const TX sv = ok ? (TX)sm[j][cc] : (TX)0;
+                            const TX va = xa[xo + cc];
+                            h1 += hv * va;
+                            s1 += sv * va;
+                            s2 += sv * xb[xo + cc];
+                            h3 += hv * xd[xo + cc];
+                        }
+                    }
+                }
+            } else {
+                const int64_t k0 = g.rp[a], k1 = g.rp[a + 1];
+#pragma unroll 4
+                for (int64_t kb = k0; kb < k1; ++kb) blk(S.lblk[kb]);
             }
         }
         ha[rr] = (double)h1;
@@ -701,6 +769,8 @@ struct SmemG {
     double *part;                // 4 * NWG wavefront partial sums
     double *red;                 // NWG
     float *redf;                 // NWG
+    int *srp;                    // region block index (when staged): max_nat + 1 row pointers
+    int2 *sblk;                  // and max_lnnz blocks
 };
 
 // candidate sources of a step
@@ -716,7 +786,8 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t ld = S.nmax;
     const int nu = J.nu;
-    const Col g = make_col(S, J, c, o);
+    Col g = make_col(S, J, c, o);
+    if (S.lidx) stage_col_index<NTG>(S, g, sm.srp, sm.sblk);
     const int n = g.n;
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
@@ -1015,6 +1086,8 @@ __global__ void __launch_bounds__(NTG, global_waves<R>()) k_basis_g(DevSystem S,
     sm.fx = smem + 4 * nm;
     sm.cf = smem + 4 * nm + (3 * nm + 1) / 2;
     sm.part = sm.cf + 6 * (kMaxNu + 1);
+    sm.srp = reinterpret_cast<int *>(sm.part + 4 * NWG);
+    sm.sblk = reinterpret_cast<int2 *>(sm.srp + ((S.max_nat + 2) & ~1));
     sm.red = red;
     sm.redf = redf;
     double *U = J.ws + (int64_t)blockIdx.x * J.ws_stride;
@@ -2065,7 +2138,8 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
     double *A = smem, *B = smem + nu * nu, *Z = smem + 2 * nu * nu;   // Z column-major
     double *ev = smem + 3 * nu * nu, *vj = ev + kMaxNu, *svj = vj + kMaxNu, *fw = svj + kMaxNu;
     double *hh = fw + kMaxNu, *ee = hh + kMaxNu, *qv = ee + kMaxNu, *rd = qv + kMaxNu;
-    int *rank = reinterpret_cast<int *>(rd + kMaxNu);
+    double *upj = rd + kMaxNu;   // 2 kMaxNu
+    int *rank = reinterpret_cast<int *>(upj + 2 * kMaxNu);
     int *inv = rank + kMaxNu;
     __shared__ double hv[kMaxNu];   // current Householder vector (separate objects: the
     __shared__ double hq[kMaxNu];   // compiler may keep their loads ahead of A's stores)
@@ -2078,10 +2152,16 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
         int32_t *st = J.stats + (int64_t)c * kStats;
         int L = st[3] == 0 ? st[0] : 0;
         int status = 0;
+#pragma unroll 4
         for (int e = lane; e < L * L; e += 64) {
             const int i = e / L, k = e - i * L;
             A[e] = 0.5 * (mid[i * nu + k] + mid[k * nu + i]);
             B[e] = 0.5 * (mid[nu * nu + i * nu + k] + mid[nu * nu + k * nu + i]);
+        }
+        // basis rows at j: u_m[j] and (S u_m)[j]
+        for (int m = lane; m < L; m += 64) {
+            upj[m] = Up[m];
+            upj[kMaxNu + m] = Up[nu + m];
         }
         __syncthreads();
 
@@ -2218,9 +2298,14 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
         for (int l = 0; l < L && status == 0; ++l) {
             int sweeps = 0;
             for (;;) {
-                int m = l;
-                for (; m < L - 1; ++m)
-                    if (fabs(ee[m]) <= DBL_EPSILON * (fabs(ev[m]) + fabs(ev[m + 1]))) break;
+                // m: the first k >= l with ee[k] negligible (L - 1 if none),
+                // one lane per k
+                bool small = lane == L - 1;
+                if (lane >= l && lane < L - 1)
+                    small = fabs(ee[lane]) <= DBL_EPSILON * (fabs(ev[lane]) + fabs(ev[lane + 1]));
+                const unsigned long long msk =
+                    __ballot(small) & ~((l > 0 ? (1ull << l) : 1ull) - 1ull);
+                const int m = __ffsll((long long)msk) - 1;
                 if (m == l) break;
                 if (++sweeps > 64) {
                     status = -5;
@@ -2323,8 +2408,8 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
             #pragma unroll 4
             for (int m = 0; m < L; ++m) {
                 const double cma = C[m * L + a];
-                v1 += Up[m] * cma;
-                v2 += Up[nu + m] * cma;
+                v1 += upj[m] * cma;
+                v2 += upj[kMaxNu + m] * cma;
             }
             vj[a] = v1;
             svj[a] = v2;
@@ -2353,13 +2438,22 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
             TA *amp = reinterpret_cast<TA *>(J.amp) + J.amp_off[c];
             const int nrt = (npat + 15) >> 4, nct = (nu + 15) >> 4;
             const int kq = lane >> 4, l16 = lane & 15;
-            for (int tile = 0; tile < nrt * nct; ++tile) {
-                const int mt = tile / nct, ct = tile - mt * nct;
-                const int arow = mt * 16 + l16, bcol = ct * 16 + l16;
+            for (int mt = 0; mt < nrt; ++mt) {
+                const int arow = mt * 16 + l16;
+                // this lane's basis-row operands for the first 32 k, loaded together
+                double avs[8];
+#pragma unroll
+                for (int st4 = 0; st4 < 8; ++st4) {
+                    const int kk = 4 * st4 + kq;
+                    avs[st4] = (arow < npat && kk < L) ? Up[(2 + arow) * nu + kk] : 0.0;
+                }
+              for (int ct = 0; ct < nct; ++ct) {
+                const int bcol = ct * 16 + l16;
                 dbl4 acc = {0.0, 0.0, 0.0, 0.0};
                 for (int k0 = 0; k0 < L; k0 += 4) {
                     const int kk = k0 + kq;
-                    const double av = (arow < npat && kk < L) ? Up[(2 + arow) * nu + kk] : 0.0;
+                    const double av = k0 < 32 ? avs[(k0 >> 2) & 7]
+                                      : (arow < npat && kk < L) ? Up[(2 + arow) * nu + kk] : 0.0;
                     const double bv = (bcol < L && kk < L) ? C[kk * L + bcol] : 0.0;
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
                 }
@@ -2371,6 +2465,7 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
                         else amp[tr * nu + bcol] = (TA)0.0;
                     }
                 }
+              }
             }
         } else {
             __syncthreads();
@@ -2451,26 +2546,47 @@ __global__ void __launch_bounds__(256) k_minmax(const double *eps, const int32_t
     }
 }
 
-__global__ void k_minmax_final(const double *part, int nblocks, double kT, double *lohi)
+__global__ void __launch_bounds__(64) k_minmax_final(const double *part, int nblocks, double kT,
+                                                     double *lohi, unsigned *done)
 {
-    if (threadIdx.x != 0) return;
     double lo = INFINITY, hi = -INFINITY;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = threadIdx.x; b < nblocks; b += 64) {
         lo = fmin(lo, part[2 * b]);
         hi = fmax(hi, part[2 * b + 1]);
     }
-    lohi[0] = lo - 50.0 * kT;
-    lohi[1] = hi + 50.0 * kT;
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if (threadIdx.x == 0) {
+        lohi[0] = lo - 50.0 * kT;
+        lohi[1] = hi + 50.0 * kT;
+        *done = 0u;   // the K-section passes' completion counter
+    }
+}
+
+// completion counter of the K-section passes: the word after the partial sums
+__host__ __device__ inline unsigned *count_done(double *partial)
+{
+    return reinterpret_cast<unsigned *>(partial + kCountBlocks * kBisectTrials);
 }
 
 // Electron count sum_j sum_a f((eps_a - mu_t)/kT) w_a for the kBisectTrials
 // trial potentials mu_t equally spaced inside (lo, hi); one partial per block.
+// One K-section pass: every block evaluates the electron count at KT_
+// equally spaced trial potentials over its share of the Ritz pairs and
+// writes its partial sums; the last block to finish (a device-scope counter)
+// sums the partials of all blocks in a fixed order and narrows the bracket
+// to the first trial whose count reaches the target, then clears the
+// counter for the next pass.
 __global__ void __launch_bounds__(256) k_count(const double *eps, const double *wts,
                                                const int32_t *stats, int ncols, int nu,
-                                               double kT, const double *lohi, double *partial)
+                                               double kT, double n_target, double *lohi,
+                                               double *partial, unsigned *done)
 {
     constexpr int KT_ = kBisectTrials;
     __shared__ double sred[4][KT_];
+    __shared__ int last;
     const double lo = lohi[0], hi = lohi[1];
     double acc[KT_];
 #pragma unroll
@@ -2496,28 +2612,37 @@ __global__ void __launch_bounds__(256) k_count(const double *eps, const double *
     __syncthreads();
     for (int t = threadIdx.x; t < KT_; t += blockDim.x)
         partial[blockIdx.x * KT_ + t] = ((sred[0][t] + sred[1][t]) + sred[2][t]) + sred[3][t];
-}
-
-// New bracket: the first trial whose count reaches the target closes it.
-__global__ void k_bracket(const double *partial, int nblocks, double n_target, double *lohi)
-{
-    constexpr int KT_ = kBisectTrials;
-    __shared__ double cnt[KT_];
-    for (int t = threadIdx.x; t < KT_; t += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partial[b * KT_ + t];
-        cnt[t] = s;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // fixed order: thread b adds blocks b, b + 256, ...; then wavefronts, then waves 0..3
+#pragma unroll
+    for (int t = 0; t < KT_; ++t) acc[t] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+#pragma unroll
+        for (int t = 0; t < KT_; ++t) acc[t] += __builtin_nontemporal_load(partial + b * KT_ + t);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KT_; ++t) {
+        const double v = wave_sum(acc[t]);
+        if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6][t] = v;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double lo = lohi[0], hi = lohi[1];
         int first = KT_;
         for (int t = 0; t < KT_; ++t)
-            if (cnt[t] >= n_target) { first = t; break; }
+            if (((sred[0][t] + sred[1][t]) + sred[2][t]) + sred[3][t] >= n_target) {
+                first = t;
+                break;
+            }
         const double nlo = first == 0 ? lo : lo + (hi - lo) * (double)first / (double)(KT_ + 1);
         const double nhi = first == KT_ ? hi : lo + (hi - lo) * (double)(first + 1) / (double)(KT_ + 1);
         lohi[0] = nlo;
         lohi[1] = nhi;
+        *done = 0u;
     }
 }
 
@@ -2725,6 +2850,18 @@ int basis_rows_per_thread(int nmax)
     return 8;
 }
 
+// LDS of a staged region block index
+size_t lidx_bytes(int max_nat, int max_lnnz)
+{
+    return sizeof(int) * (size_t)((max_nat + 2) & ~1) + sizeof(int2) * (size_t)max_lnnz;
+}
+
+bool global_lidx_fits(int nmax, int max_nat, int max_lnnz)
+{
+    return sizeof(double) * (size_t)global_smem_doubles(nmax) + lidx_bytes(max_nat, max_lnnz) <=
+           80 * 1024;
+}
+
 size_t basis_smem_bytes(int nmax, int nu, int kind, int o)
 {
     if (kind == kBasisOnchip) {
@@ -2757,7 +2894,8 @@ hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots
         return launch_with_smem(k, slots, 512, smem, st, S, J);
     }
     basis_fn k = (basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision);
-    return launch_with_smem(k, slots, NTG, smem, st, S, J);
+    const size_t sx = S.lidx ? lidx_bytes(S.max_nat, S.max_lnnz) : 0;
+    return launch_with_smem(k, slots, NTG, smem + sx, st, S, J);
 }
 
 hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *bpc)
@@ -2770,13 +2908,14 @@ hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *b
     }
     if (kind == kBasisGroup)
         return occupancy_of((basis_fn)group_kernel(S.o, S.nmax, J.precision), 512, smem, bpc);
+    const size_t sx = S.lidx ? lidx_bytes(S.max_nat, S.max_lnnz) : 0;
     return occupancy_of((basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision),
-                        NTG, smem, bpc);
+                        NTG, smem + sx, bpc);
 }
 
 hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
 {
-    const size_t smem = sizeof(double) * (3 * (size_t)J.nu * J.nu + 8 * kMaxNu) +
+    const size_t smem = sizeof(double) * (3 * (size_t)J.nu * J.nu + 10 * kMaxNu) +
                         sizeof(int) * 2 * kMaxNu;
     const int grid = J.cn < (1 << 20) ? J.cn : (1 << 20);
     if (grid < 1) return hipSuccess;
@@ -2788,7 +2927,8 @@ hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int
                          double *lohi, double *partial, hipStream_t st)
 {
     hipLaunchKernelGGL(k_minmax, dim3(kCountBlocks), dim3(256), 0, st, eps, stats, ncols, nu, partial);
-    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, st, partial, kCountBlocks, kT, lohi);
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, st, partial, kCountBlocks, kT, lohi,
+                       count_done(partial));
     return hipGetLastError();
 }
 
@@ -2796,12 +2936,9 @@ hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *st
                          int nu, double kT, double n_target, double *lohi, double *partial,
                          hipStream_t st)
 {
-    for (int pass = 0; pass < kBisectPasses; ++pass) {
+    for (int pass = 0; pass < kBisectPasses; ++pass)
         hipLaunchKernelGGL(k_count, dim3(kCountBlocks), dim3(256), 0, st, eps, wts, stats, ncols,
-                           nu, kT, lohi, partial);
-        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(64), 0, st, partial, kCountBlocks, n_target,
-                           lohi);
-    }
+                           nu, kT, n_target, lohi, partial, count_done(partial));
     return hipGetLastError();
 }
 
