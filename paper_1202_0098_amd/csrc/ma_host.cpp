@@ -916,6 +916,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     P.kind = want_kernel == MA_BASIS_ONCHIP ? ma::kBasisOnchip
              : want_kernel == MA_BASIS_GROUP ? ma::kBasisGroup : ma::kBasisWorkspace;
     const int o = ctx->o;
+    J.lidx = P.kind == ma::kBasisWorkspace ? S.lidx
+             : P.kind == ma::kBasisOnchip
+                 ? (ma::onchip_lidx_fits(ctx->nmax, P.nu, ctx->max_nat, (int)ctx->max_lnnz) ? 1 : 0)
+                 : 0;
     J.ws_stride = P.kind == ma::kBasisOnchip ? 0
                   : (int64_t)(P.kind == ma::kBasisGroup ? ma::basis_group_width(o) : 1) *
                         (3 * P.nu + q) * ctx->nmax;

@@ -45,8 +45,8 @@ struct DevSystem {
                                // region) of its kNbOut nearest atoms, -1 if outside
     int max_nat;               // largest region (atoms)
     int max_lnnz;              // largest region operator (local blocks)
-    int lidx;                  // 1: the workspace kernel stages a region's local block
-                               // index in LDS for its SpMVs
+    int lidx;                  // 1: the workspace kernel can stage a region's local
+                               // block index in LDS beside its other buffers
 };
 
 // One solve.  Columns are processed in chunks of the processing order: the
@@ -68,6 +68,8 @@ struct DevJob {
     int *fail;                 // [0] = first failing c (INT_MAX none)
     const int32_t *gstart;     // atom-group kernel: columns of group g are order positions
                                // gstart[g] .. gstart[g+1]
+    int lidx;                  // 1: the basis kernel stages each region's local block
+                               // index in LDS
     double *ws;                // basis workspace of the large-region kernel, slots * ws_stride
     int64_t ws_stride;
     // chunk: order positions c0 .. c0 + cn; slot s = position - c0
@@ -115,8 +117,10 @@ bool basis_small_fits(int nmax, int nu, int q, int o);
 bool basis_group_fits(int nmax, int nu, int o);
 int basis_group_width(int o);   // columns of one atom solved together
 size_t basis_smem_bytes(int nmax, int nu, int kind, int o);
-// whether the workspace kernel keeps a region's local block index in LDS
+// whether the workspace (resp. on-chip) kernel keeps a region's local block
+// index in LDS
 bool global_lidx_fits(int nmax, int max_nat, int max_lnnz);
+bool onchip_lidx_fits(int nmax, int nu, int max_nat, int max_lnnz);
 int basis_rows_per_thread(int nmax);
 hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st);
 hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots, hipStream_t st);

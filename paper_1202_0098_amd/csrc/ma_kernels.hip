@@ -672,7 +672,7 @@ __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t
 
 // SpMV of three staged vectors on the thread's own rows:
 // ha = H xa, sa = S xa, sb = S xb, hd = H xd.
-template <int O, int R, typename TM, typename TX>
+template <int O, int R, int NT, typename TM, typename TX>
 __device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int o_rt,
                                            const TM *__restrict__ Hv, const TM *__restrict__ Sv,
                                            const TX *xa, const TX *xb, const TX *xd,
@@ -684,7 +684,7 @@ __device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int
     constexpr int NB = O > 4 ? 2 : sizeof(TM) == 8 ? 3 : 4;   // blocks per batch
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-        const int i = threadIdx.x + rr * NTG;
+        const int i = threadIdx.x + rr * NT;
         TX h1 = 0, s1 = 0, s2 = 0, h3 = 0;
         if (i < g.n) {
             const int a = i / o;
@@ -787,7 +787,7 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
     const int64_t ld = S.nmax;
     const int nu = J.nu;
     Col g = make_col(S, J, c, o);
-    if (S.lidx) stage_col_index<NTG>(S, g, sm.srp, sm.sblk);
+    if (J.lidx) stage_col_index<NTG>(S, g, sm.srp, sm.sblk);
     const int n = g.n;
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
@@ -851,7 +851,7 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
             // ---- SpMV ----
             __syncthreads();   // staged vectors visible
             double hf[R], sf[R], sp[R], hz[R];
-            spmv3_rows<O, R, TM, TX>(S, g, o, Hv, Sv, xa, xb, xd, hf, sf, sp, hz);
+            spmv3_rows<O, R, NTG, TM, TX>(S, g, o, Hv, Sv, xa, xb, xd, hf, sf, sp, hz);
             if (has_fin) {
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) {
@@ -1927,31 +1927,37 @@ __global__ void __launch_bounds__(NT) k_basis_m(DevSystem S, DevJob J)
 // small-region basis kernel: basis on chip
 // ------------------------------------------------------------------------
 // Thread t owns local row t (n <= NT).  U[m] lives in LDS (row stride
-// nmax), S u_m and the chain vectors t_k in the thread's registers.  The
-// Gram-Schmidt dots are per-row partial products reduced with the transposed
-// wavefront reduction; the Galerkin pair is accumulated as each vector is
-// accepted: X[m][L] = u_m^T H u_L (upper triangle, mirrored),
-// S~[m][L] = u_m^T (S u_L) and S~[L][m] = u_L^T (S u_m).
+// nmax), S u_m and the chain vectors t_k in the thread's registers, so every
+// access to the basis is to the thread's own row.  The S-orthogonalisation is
+// the delayed two-pass classical Gram-Schmidt of the workspace kernel (one
+// reduction per basis vector); the Galerkin pair is accumulated as each
+// vector's S and H images become available: X[m][L] = u_m^T H u_L (upper
+// triangle, mirrored), S~[m][L] = u_m^T (S u_L) and S~[L][m] = u_L^T (S u_m).
+// Each step reduces one set of per-row partial products over the workgroup
+// (transposed wavefront reductions, then the wavefront totals in LDS).
 template <int O, int NT, int NU, int PREC>
 __device__ void basis_small(const DevSystem &S, const DevJob &J, double *Ub, double *xa,
-                            double *xb, double *scratch, double *cf, double *red, float *redf,
-                            int c, int s)
+                            double *xb, double *xz, double *scratch, double *rs, double *cf,
+                            int *srp, int2 *sblk, double *red, float *redf, int c, int s)
 {
     using TM = typename std::conditional<PREC != 0, float, double>::type;
     using TX = typename std::conditional<PREC == 1, float, double>::type;
     constexpr int NWV = NT / 64;
     constexpr int NQ = NU / 2;
+    constexpr int G = 7;   // reduction groups of NU values, see below
     const int o = O ? O : S.o;
     const int tid = threadIdx.x;
     const int ldu = S.nmax;
     const int nu = J.nu;
-    const Col g = make_col(S, J, c, o);
+    Col g = make_col(S, J, c, o);
+    if (J.lidx) stage_col_index<NT>(S, g, srp, sblk);
     const int n = g.n;
     const bool own = tid < n;
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
     TX *xaX = reinterpret_cast<TX *>(xa);
     TX *xbX = reinterpret_cast<TX *>(xb);
+    TX *xzX = reinterpret_cast<TX *>(xz);
 
     double x[1];
     int iters, nres, status, start;
@@ -1967,100 +1973,189 @@ __device__ void basis_small(const DevSystem &S, const DevJob &J, double *Ub, dou
     for (int m = 0; m < NQ; ++m) Tc[m] = 0.0;
     int L = 0;
     if (status == 0) {
-        double l = (tid == g.jl) ? 1.0 : 0.0;
-        double zv = 0.0, t = 0.0;
-        double *c1 = cf, *c2 = cf + NU, *pr = cf + 2 * NU;
+        double *cbuf0 = cf, *cbuf1 = cf + (NU + 1), *ctb0 = cf + 2 * (NU + 1), *ctb1 = ctb0 + (NQ + 1);
+        // own-row state: uf finished vector (images pending), p pending
+        // vector, zt pending chain vector
+        double uf = 0.0, p = (tid == g.jl) ? 1.0 : 0.0, zt = own ? x[0] : 0.0;
+        bool has_fin = false, has_pend = J.p > 0;
+        bool b1_live = true, chain_live = J.q > 0;
+        int nb1 = J.p > 0 ? 1 : 0, k = 0, ping = 0;
+        double cp_scale = 1.0, ctp_scale = 1.0;
+        __syncthreads();   // the CG's last reads of xa, xb are done
+        if (own) {
+            xaX[tid] = (TX)0.0;
+            xbX[tid] = (TX)p;
+            xzX[tid] = (TX)zt;
+        }
+        for (;;) {
+            const int kind = (b1_live && nb1 < J.p) ? kCandBlock1
+                             : chain_live ? kCandChain : kCandNone;
+            if (!has_fin && !has_pend && kind == kCandNone) break;
+            const bool need_z = kind == kCandChain && k + 1 < J.q;
+            const TX *xd = kind == kCandChain ? xzX : xbX;
+            double *cp = ping ? cbuf0 : cbuf1, *cbn = ping ? cbuf1 : cbuf0;
+            double *ctp = ping ? ctb0 : ctb1, *ctn = ping ? ctb1 : ctb0;
 
-        auto append = [&](bool chain) __attribute__((always_inline)) -> bool {
-            for (int pass = 0; pass < 2; ++pass) {
-                double *cc = pass ? c2 : c1;
-                block_reduce<NWV, NU, 1>([&](int, double (&v)[NU]) __attribute__((always_inline)) {
+            // ---- SpMV ----
+            __syncthreads();   // staged vectors visible
+            double hf1[1], sf1[1], sp1[1], hz1[1];
+            spmv3_rows<O, 1, NT, TM, TX>(S, g, o, Hv, Sv, xaX, xbX, xd, hf1, sf1, sp1, hz1);
+            const double hf = hf1[0], sf = sf1[0], sp = sp1[0], hz = hz1[0];
+            if (has_fin) {
 #pragma unroll
-                    for (int m = 0; m < NU; ++m) v[m] = (m < L && own) ? SU[m] * l : 0.0;
-                }, scratch, cc);
-                if (own) {
-                    double acc = 0.0;
-                    for (int m = 0; m < L; ++m) acc += Ub[m * ldu + tid] * cc[m];
-                    l -= acc;
-                }
+                for (int m = 0; m < NU; ++m) SU[m] = (m == L - 1) ? sf : SU[m];
             }
-            if (own) {
-                xaX[tid] = (TX)l;
-                if (chain) xbX[tid] = (TX)t;
-            }
-            __syncthreads();
-            double hv1[1], w1[1], z1[1];
-            if (chain)
-                spmv_rows<O, 1, NT, TM, TX, true, true, true>(S, g, o, Hv, Sv, xaX, xbX, hv1, w1, z1);
-            else
-                spmv_rows<O, 1, NT, TM, TX, true, true, false>(S, g, o, Hv, Sv, xaX, xbX, hv1, w1, z1);
-            if (chain) zv = z1[0];
-            const double bb = block_sum<NWV>(own ? l * w1[0] : 0.0, red);
-            double b0 = bb;
-            for (int m = 0; m < L; ++m) b0 += (c1[m] + c2[m]) * (c1[m] + c2[m]);
-            if (!(bb > 0.0) || !(b0 > 0.0) || sqrt(bb) <= J.tau * sqrt(b0)) return false;
-            const double inv = 1.0 / sqrt(bb);
-            const double u = l * inv, su = w1[0] * inv, kk = hv1[0] * inv;
-            if (own) Ub[L * ldu + tid] = u;
-#pragma unroll
-            for (int m = 0; m < NU; ++m) SU[m] = (m == L) ? su : SU[m];
-            // column L of the Galerkin pair
-            block_reduce<NWV, NU, 3>([&](int gi, double (&v)[NU]) __attribute__((always_inline)) {
+            const bool tail = kind == kCandNone && !has_pend;
+            const double cand = kind == kCandChain ? zt : hz;
+
+            // ---- one reduction: dots, Galerkin column L-1, scalars ----
+            // groups: 0 a = (S U)^T p, 1 b = (S U)^T candidate,
+            // 2 [T^T zt | T^T H zt], 3 U^T H u_{L-1}, 4 U^T S u_{L-1},
+            // 5 (S U)^T u_{L-1}, 6 scalars
+            block_reduce<NWV, NU, G>([&](int gi, double (&v)[NU]) __attribute__((always_inline)) {
 #pragma unroll
                 for (int m = 0; m < NU; ++m) {
-                    const bool ok = own && m <= L;
-                    if (gi == 2) {
-                        v[m] = ok ? SU[m] * u : 0.0;
-                    } else {
-                        const double um = ok ? Ub[m * ldu + tid] : 0.0;
-                        v[m] = um * (gi == 0 ? kk : su);
+                    double val = 0.0;
+                    if (own) {
+                        if (gi == 0) val = (m < L && !tail) ? SU[m] * p : 0.0;
+                        else if (gi == 1) val = (m < L && !tail) ? SU[m] * cand : 0.0;
+                        else if (gi == 2) {
+                            if (kind == kCandChain) {
+                                if (m < NQ) val = m < k ? Tc[m & (NQ - 1)] * zt : 0.0;
+                                else val = (m - NQ) < k ? Tc[(m - NQ) & (NQ - 1)] * hz : 0.0;
+                            }
+                        } else if (gi == 3 || gi == 4) {
+                            const double um = (has_fin && m < L) ? Ub[m * ldu + tid] : 0.0;
+                            val = um * (gi == 3 ? hf : sf);
+                        } else if (gi == 5) {
+                            val = (has_fin && m < L) ? uf * SU[m] : 0.0;
+                        } else {
+                            val = m == 0 ? p * sp : m == 1 ? sp * cand : m == 2 ? zt * zt
+                                  : m == 3 ? zt * hz : 0.0;
+                        }
+                    }
+                    v[m] = val;
+                }
+            }, scratch, rs);
+            const double *ca = rs, *cb = rs + NU, *cat = rs + 2 * NU, *ctb = rs + 2 * NU + NQ;
+            if (has_fin) {
+                // Galerkin column L-1
+                for (int m = tid; m < L; m += NT) {
+                    const double h = rs[3 * NU + m];
+                    Xh[m * nu + (L - 1)] = h;
+                    Xh[(L - 1) * nu + m] = h;
+                    Xs[m * nu + (L - 1)] = rs[4 * NU + m];
+                    if (m < L - 1) Xs[(L - 1) * nu + m] = rs[5 * NU + m];
+                }
+            }
+            if (tail) break;
+            const double nu_p = rs[6 * NU + 0], e_p = rs[6 * NU + 1];
+            const double nu_t = rs[6 * NU + 2], e_t = rs[6 * NU + 3];
+
+            // ---- decisions (every thread, same values) ----
+            bool acc_u = false;
+            double beta = 1.0, f = 0.0;
+            if (has_pend) {
+                double asq = 0.0, tot = 0.0, ab = 0.0;
+                for (int m = 0; m < L; ++m) {
+                    const double cm = cp_scale * cp[m] + ca[m];
+                    asq += ca[m] * ca[m];
+                    tot += cm * cm;
+                    if (kind != kCandNone) ab += ca[m] * cb[m];
+                }
+                const double bb = nu_p - asq, b0 = bb + tot;
+                acc_u = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
+                if (acc_u) {
+                    beta = sqrt(bb);
+                    f = (e_p - ab) / beta;
+                }
+            }
+            bool acc_t = false;
+            double eta = 1.0, ft = 0.0;
+            if (kind == kCandChain) {
+                double asq = 0.0, tot = 0.0, ab = 0.0;
+                for (int m = 0; m < k; ++m) {
+                    const double cm = ctp_scale * ctp[m] + cat[m];
+                    asq += cat[m] * cat[m];
+                    tot += cm * cm;
+                    ab += cat[m] * ctb[m];
+                }
+                const double ee = nu_t - asq, e0 = ee + tot;
+                acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
+                if (acc_t) {
+                    eta = sqrt(ee);
+                    ft = (e_t - ab) / eta;
+                }
+            }
+            const bool new_pend = (kind == kCandBlock1 && acc_u) || (kind == kCandChain && acc_t);
+            const bool new_chain = need_z && acc_t;
+            const double inv_b = 1.0 / beta, inv_e = 1.0 / eta;
+            const double sc = kind == kCandBlock1 ? inv_b : 1.0;
+            // first-pass coefficients of the new pending vectors, kept for the next step
+            for (int m = tid; m < L; m += NT) cbn[m] = cb[m];
+            for (int m = tid; m < k; m += NT) ctn[m] = ctb[m];
+            if (tid == 0) {
+                if (acc_u) cbn[L] = f;
+                if (acc_t) ctn[k] = ft;
+            }
+
+            // ---- update of the thread's row ----
+            if (own) {
+                double sa = 0.0, sb = 0.0;
+                if (acc_u || new_pend) {
+#pragma unroll 8
+                    for (int m = 0; m < L; ++m) {
+                        const double um = Ub[m * ldu + tid];
+                        sa += um * ca[m];
+                        sb += um * cb[m];
                     }
                 }
-            }, scratch, pr);
-            for (int m = tid; m <= L; m += NT) {
-                const double h = pr[m];
-                Xh[m * nu + L] = h;
-                Xh[L * nu + m] = h;
-                Xs[m * nu + L] = pr[NU + m];
-                if (m < L) Xs[L * nu + m] = pr[2 * NU + m];
-            }
-            l = kk;   // next block-1 seed: H u_L
-            ++L;
-            return true;
-        };
-
-        // block 1: seeds e_j, H u_1, H u_2, ...
-        for (int step = 0; step < J.p; ++step)
-            if (!append(false)) break;
-
-        // block 2: chain t_1 = s_j / |s_j|, t_{k+1} = H t_k orthonormalised
-        if (J.q > 0) {
-            const double ns = sqrt(block_sum<NWV>(own ? x[0] * x[0] : 0.0, red));
-            t = x[0] / ns;
-            Tc[0] = t;
-            for (int k = 0; k < J.q; ++k) {
-                l = t;
-                const bool last = (k + 1 == J.q);
-                append(!last);
-                if (last) break;
-                // Euclidean Gram-Schmidt of H t_k against t_1..t_k, twice
-                const double eta0 = sqrt(block_sum<NWV>(own ? zv * zv : 0.0, red));
-                for (int pass = 0; pass < 2; ++pass) {
-                    block_reduce<NWV, NQ, 1>([&](int, double (&v)[NQ]) __attribute__((always_inline)) {
+                double ta = 0.0, tb = 0.0;
 #pragma unroll
-                        for (int m = 0; m < NQ; ++m) v[m] = (m <= k && own) ? Tc[m] * zv : 0.0;
-                    }, scratch, c1);
-                    double acc = 0.0;
-#pragma unroll
-                    for (int m = 0; m < NQ; ++m) acc += (m <= k) ? Tc[m] * c1[m] : 0.0;
-                    zv -= acc;
+                for (int m = 0; m < NQ; ++m) {
+                    if (m < k) {
+                        ta += Tc[m] * cat[m];
+                        tb += Tc[m] * ctb[m];
+                    }
                 }
-                const double eta = sqrt(block_sum<NWV>(own ? zv * zv : 0.0, red));
-                if (!(eta > J.tau * eta0)) break;
-                t = zv / eta;
+                const double u = (p - sa) * inv_b;
+                const double nl = (cand - sb - (acc_u ? f * u : 0.0)) * sc;
+                const double t = (zt - ta) * inv_e;
+                const double nz = (hz - tb - ft * t) * inv_e;
+                if (acc_u) {
+                    Ub[L * ldu + tid] = u;
+                    xaX[tid] = (TX)u;
+                    uf = u;
+                }
+                if (acc_t) {
 #pragma unroll
-                for (int m = 0; m < NQ; ++m) Tc[m] = (m == k + 1) ? t : Tc[m];
+                    for (int m = 0; m < NQ; ++m) Tc[m] = (m == k) ? t : Tc[m];
+                }
+                p = new_pend ? nl : 0.0;
+                xbX[tid] = (TX)p;
+                if (new_chain) {
+                    zt = nz;
+                    xzX[tid] = (TX)zt;
+                }
             }
+            if (kind == kCandBlock1) {
+                if (acc_u) ++nb1;
+                else b1_live = false;
+            }
+            if (kind == kCandChain) {
+                if (acc_t) {
+                    ++k;
+                    chain_live = k < J.q;
+                } else {
+                    chain_live = false;
+                }
+            }
+            if (acc_u) ++L;
+            cp_scale = sc;
+            ctp_scale = inv_e;
+            has_fin = acc_u;
+            has_pend = new_pend;
+            ping ^= 1;
         }
         __syncthreads();   // U complete in LDS
 
@@ -2087,13 +2182,15 @@ __device__ void basis_small(const DevSystem &S, const DevJob &J, double *Ub, dou
         }
     }
     if (tid == 0) write_stats(J, c, L, iters, nres, status, start);
-    __syncthreads();   // U, xa, xb are reused by the next column
+    __syncthreads();   // U, the staged vectors and the index are reused by the next column
 }
 
+// LDS of the on-chip kernel in doubles, besides U (nu * nmax) and the index:
+// three staged vectors, the reduction scratch and results, coefficients
 template <int NT, int NU>
 __host__ __device__ constexpr int small_smem_doubles_fixed()
 {
-    return (NT / 64) * 3 * NU + 5 * NU;
+    return (NT / 64) * 7 * NU + 7 * NU + 2 * (NU + 1) + 2 * (NU / 2 + 1);
 }
 
 template <int O, int NT, int NU, int PREC>
@@ -2104,12 +2201,17 @@ __global__ void __launch_bounds__(NT) k_basis_s(DevSystem S, DevJob J)
     __shared__ float redf[NT / 64];
     __shared__ int s_idx;
     double *Ub = smem;
-    double *xa = Ub + (int64_t)NU * S.nmax;
+    double *xa = Ub + (int64_t)J.nu * S.nmax;
     double *xb = xa + S.nmax;
-    double *scratch = xb + S.nmax;
-    double *cf = scratch + (NT / 64) * 3 * NU;
+    double *xz = xb + S.nmax;
+    double *scratch = xz + S.nmax;
+    double *rs = scratch + (NT / 64) * 7 * NU;
+    double *cf = rs + 7 * NU;
+    int *srp = reinterpret_cast<int *>(cf + 2 * (NU + 1) + 2 * (NU / 2 + 1));
+    int2 *sblk = reinterpret_cast<int2 *>(srp + ((S.max_nat + 2) & ~1));
     drain_queues(J, &s_idx, [&](int c, int s) __attribute__((always_inline)) {
-        basis_small<O, NT, NU, PREC>(S, J, Ub, xa, xb, scratch, cf, red, redf, c, s);
+        basis_small<O, NT, NU, PREC>(S, J, Ub, xa, xb, xz, scratch, rs, cf, srp, sblk, red, redf,
+                                     c, s);
     });
 }
 
@@ -2856,6 +2958,11 @@ size_t lidx_bytes(int max_nat, int max_lnnz)
     return sizeof(int) * (size_t)((max_nat + 2) & ~1) + sizeof(int2) * (size_t)max_lnnz;
 }
 
+bool onchip_lidx_fits(int nmax, int nu, int max_nat, int max_lnnz)
+{
+    return basis_smem_bytes(nmax, nu, kBasisOnchip, 0) + lidx_bytes(max_nat, max_lnnz) <= 160 * 1024;
+}
+
 bool global_lidx_fits(int nmax, int max_nat, int max_lnnz)
 {
     return sizeof(double) * (size_t)global_smem_doubles(nmax) + lidx_bytes(max_nat, max_lnnz) <=
@@ -2866,7 +2973,11 @@ size_t basis_smem_bytes(int nmax, int nu, int kind, int o)
 {
     if (kind == kBasisOnchip) {
         const int nt = small_threads(nmax), nucap = small_nu_cap(nu);
-        return sizeof(double) * ((size_t)nucap * nmax + 2 * (size_t)nmax + (nt / 64) * 3 * nucap + 5 * nucap);
+        const int fixed = nt == 256 ? (nucap == 16 ? small_smem_doubles_fixed<256, 16>()
+                                                   : small_smem_doubles_fixed<256, 32>())
+                                    : (nucap == 16 ? small_smem_doubles_fixed<512, 16>()
+                                                   : small_smem_doubles_fixed<512, 32>());
+        return sizeof(double) * ((size_t)nu * nmax + 3 * (size_t)nmax + fixed);
     }
     if (kind == kBasisGroup) {
         const int b = basis_group_width(o);
@@ -2883,7 +2994,8 @@ hipError_t launch_reset(int *queue, int *fail, int reset_fail, hipStream_t st)
 
 hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots, hipStream_t st)
 {
-    const size_t smem = basis_smem_bytes(S.nmax, J.nu, kind, S.o);
+    const size_t smem = basis_smem_bytes(S.nmax, J.nu, kind, S.o) +
+                        (J.lidx ? lidx_bytes(S.max_nat, S.max_lnnz) : 0);
     if (kind == kBasisOnchip) {
         const int nt = small_threads(S.nmax);
         basis_fn k = (basis_fn)small_kernel(S.o, nt, small_nu_cap(J.nu), J.precision);
@@ -2894,13 +3006,13 @@ hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots
         return launch_with_smem(k, slots, 512, smem, st, S, J);
     }
     basis_fn k = (basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision);
-    const size_t sx = S.lidx ? lidx_bytes(S.max_nat, S.max_lnnz) : 0;
-    return launch_with_smem(k, slots, NTG, smem + sx, st, S, J);
+    return launch_with_smem(k, slots, NTG, smem, st, S, J);
 }
 
 hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *bpc)
 {
-    const size_t smem = basis_smem_bytes(S.nmax, J.nu, kind, S.o);
+    const size_t smem = basis_smem_bytes(S.nmax, J.nu, kind, S.o) +
+                        (J.lidx ? lidx_bytes(S.max_nat, S.max_lnnz) : 0);
     if (kind == kBasisOnchip) {
         const int nt = small_threads(S.nmax);
         return occupancy_of((basis_fn)small_kernel(S.o, nt, small_nu_cap(J.nu), J.precision), nt,
@@ -2908,9 +3020,8 @@ hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *b
     }
     if (kind == kBasisGroup)
         return occupancy_of((basis_fn)group_kernel(S.o, S.nmax, J.precision), 512, smem, bpc);
-    const size_t sx = S.lidx ? lidx_bytes(S.max_nat, S.max_lnnz) : 0;
     return occupancy_of((basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision),
-                        NTG, smem + sx, bpc);
+                        NTG, smem, bpc);
 }
 
 hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
