@@ -137,9 +137,11 @@ typedef struct {
                                as a 4 GiB chunk buffer holds); a solve of several
                                chunks launches eagerly instead of replaying graphs */
     int32_t pipeline;       /* >= 2 (default 4): a solve of at least 2048 * pipeline
-                               columns is cut into at least `pipeline` chunks, and the
-                               eigensolver of chunk k runs on a second stream beside
-                               the basis kernel of chunk k + 1 (0 or 1: off) */
+                               columns is cut into pipeline + 2 chunks of geometrically
+                               falling size (equal chunks where the 4 GiB chunk buffer
+                               caps the first), and the eigensolver of chunk k runs on
+                               a second stream beside the later basis kernels, with a
+                               ring of chunk buffers of at most 8 GiB (0 or 1: off) */
 } ma_opts;
 
 /* Schedules of the persistent column kernel.  LPT: one queue, columns with
@@ -180,11 +182,11 @@ typedef struct {
 typedef struct {
     int32_t slots_per_cu;       /* chosen */
     int32_t schedule;           /* chosen */
-    double best_ms;             /* basis-kernel time of the chosen configuration */
+    double best_ms;             /* whole-solve device time of the chosen configuration */
     int32_t n_tried;
     int32_t tried_slots[64];
     int32_t tried_schedule[64];
-    double tried_ms[64];        /* basis-kernel time of each candidate (best of reps) */
+    double tried_ms[64];        /* whole-solve device time of each candidate (best of reps) */
     int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE or MA_BASIS_GROUP */
     int32_t tried_kernel[64];
 } ma_tuning;

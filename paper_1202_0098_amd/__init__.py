@@ -274,8 +274,9 @@ class Context:
         return ra, lb
 
     def autotune(self, cols, p, q, mu, kT, opts=None, reps=2):
-        """Search slots per CU x schedule on the column kernel; the best
-        configuration is kept for (p, q, precision).  Returns a dict."""
+        """Search basis kernel x slots per CU x schedule on the whole solve's
+        device time; the best configuration is kept for (p, q, precision).
+        Returns a dict."""
         if cols is None:
             cptr, n = None, 0
         else:

@@ -810,6 +810,7 @@ struct Plan {
     int kind = ma::kBasisWorkspace;   // basis kernel
     int nchunks = 0, max_cn = 0;      // chunks of the processing order
     bool pipelined = false;           // eigensolver of chunk k on the aux stream
+    int nbuf = 1;                     // chunk buffers in the ring (pipelined: >= 2)
     std::vector<int32_t> ch_c0, ch_cn, ch_items;   // per chunk: first column position,
                                                    // columns, work items
     std::vector<int32_t> hcols;
@@ -823,15 +824,18 @@ struct Plan {
         Jk.c0 = ch_c0[k];
         Jk.cn = ch_cn[k];
         Jk.qbounds = qb_dev + (int64_t)k * (J.nqueues + 1);
-        // pipelined: chunks alternate between two halves of the chunk buffer
-        if (pipelined && (k & 1)) Jk.mid = J.mid + (int64_t)max_cn * J.mid_stride;
+        // pipelined: chunk k uses buffer k mod nbuf of the ring
+        if (nbuf > 1) Jk.mid = J.mid + (int64_t)(k % nbuf) * max_cn * J.mid_stride;
         return Jk;
     }
 };
 
 // Chunk buffer budget: the Galerkin pairs and basis rows of the columns of
-// one chunk (the rest of the solve's memory is proportional to the system).
+// one chunk (the rest of the solve's memory is proportional to the system);
+// a pipelined solve keeps a ring of such buffers within kRingBudget, so the
+// basis kernel of chunk k waits only for the eigensolver of chunk k - nbuf.
 constexpr size_t kMidBudget = (size_t)4 << 30;
+constexpr size_t kRingBudget = (size_t)8 << 30;
 
 ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, int32_t q,
                     double mu, double kT, const ma_opts *opts_in, double *rho, double *pi,
@@ -1051,6 +1055,12 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
             P.max_cn = std::max(P.max_cn, P.ch_cn[k]);
         }
     }
+    if (P.pipelined) {
+        const size_t buf = sizeof(double) * (size_t)J.mid_stride * std::max(1, P.max_cn);
+        P.nbuf = (int)std::max<size_t>(2, std::min<size_t>((size_t)P.nchunks, kRingBudget / buf));
+    } else {
+        P.nbuf = 1;
+    }
     int max_items = 0;
     for (int k = 0; k < P.nchunks; ++k) max_items = std::max(max_items, P.ch_items[k]);
     P.slots = (int)std::min<int64_t>((int64_t)bpc * ctx->cu_count, max_items);
@@ -1074,8 +1084,8 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * qb.size()), "queues");
     if (P.kind != ma::kBasisOnchip)
         HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
-    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.max_cn *
-                                 (P.pipelined ? 2 : 1)), "chunk buffer");
+    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.max_cn * P.nbuf),
+           "chunk buffer");
     HIPCHK(ctx, ctx->gstart.reserve(sizeof(int32_t) * (nitems + 1)), "work items");
     HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
     HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
@@ -1265,8 +1275,8 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
     } else {
         // eager: per chunk, events around the basis kernel (stream st) and the
         // eigensolver (st, or the aux stream when pipelined: chunk k's
-        // eigensolver runs beside chunk k+1's basis kernel; chunk k+2 reuses
-        // chunk k's half of the chunk buffer only after that eigensolver)
+        // eigensolver runs beside the later basis kernels; chunk k + nbuf
+        // reuses chunk k's buffer of the ring only after that eigensolver)
         while ((int)ctx->chunk_ev.size() < 6 * P.nchunks) {
             hipEvent_t ev;
             HIPCHK(ctx, hipEventCreate(&ev), "event");
@@ -1275,7 +1285,8 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         hipStream_t es = P.pipelined ? ctx->aux : st;
         for (int k = 0; k < P.nchunks; ++k) {
             hipEvent_t *ev = &ctx->chunk_ev[6 * k];
-            if (P.pipelined && k >= 2) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (k - 2) + 5], 0), "wait");
+            if (P.pipelined && k >= P.nbuf)
+                HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (k - P.nbuf) + 5], 0), "wait");
             HIPCHK(ctx, hipEventRecord(ev[0], st), "event");
             HIPCHK(ctx, enqueue_basis(ctx, P, k), "basis kernel");
             HIPCHK(ctx, hipEventRecord(ev[1], st), "event");
@@ -1400,7 +1411,10 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
                     ma_result res{};
                     s = run_plan(ctx, P, &res);
                     if (s != MA_OK) return s;
-                    best = std::min(best, res.kernel_ms);
+                    // the whole solve: with pipelining, a basis kernel that leaves
+                    // no room for the eigensolver beside it can be faster alone
+                    // and slower in the solve
+                    best = std::min(best, res.elapsed_ms);
                 }
                 const int t = out->n_tried++;
                 out->tried_slots[t] = bpc;

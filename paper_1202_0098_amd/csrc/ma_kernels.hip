@@ -588,31 +588,32 @@ __device__ __forceinline__ void dot_sweep(const double *__restrict__ V, int LV, 
         const double *v3 = B + (m0 + (nm > 3 ? 3 : 0)) * ld;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
-        // two rows per lane and iteration: eight loads in flight
-        for (int i = lane; i < n; i += 128) {
-            const int i2 = i + 64;
-            const bool ok2 = i2 < n;
-            const int j2 = ok2 ? i2 : i;
-            const double e0 = v0[i], e1 = v1[i], e2 = v2[i], e3 = v3[i];
-            const double g0 = v0[j2], g1 = v1[j2], g2 = v2[j2], g3 = v3[j2];
-            const double xi = X1[i], zi = X2[i];
-            const double xj = ok2 ? X1[j2] : 0.0, zj = ok2 ? X2[j2] : 0.0;
-            a0 += e0 * xi;
-            a1 += e1 * xi;
-            a2 += e2 * xi;
-            a3 += e3 * xi;
-            b0 += e0 * zi;
-            b1 += e1 * zi;
-            b2 += e2 * zi;
-            b3 += e3 * zi;
-            a0 += g0 * xj;
-            a1 += g1 * xj;
-            a2 += g2 * xj;
-            a3 += g3 * xj;
-            b0 += g0 * zj;
-            b1 += g1 * zj;
-            b2 += g2 * zj;
-            b3 += g3 * zj;
+        // four rows per lane and iteration: sixteen loads in flight
+        for (int i0 = lane; i0 < n; i0 += 256) {
+            double e[4][4], xv[4], zv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 64 * r;
+                const bool ok = i < n;
+                const int ii = ok ? i : i0;
+                e[r][0] = v0[ii];
+                e[r][1] = v1[ii];
+                e[r][2] = v2[ii];
+                e[r][3] = v3[ii];
+                xv[r] = ok ? X1[ii] : 0.0;
+                zv[r] = ok ? X2[ii] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a0 += e[r][0] * xv[r];
+                a1 += e[r][1] * xv[r];
+                a2 += e[r][2] * xv[r];
+                a3 += e[r][3] * xv[r];
+                b0 += e[r][0] * zv[r];
+                b1 += e[r][1] * zv[r];
+                b2 += e[r][2] * zv[r];
+                b3 += e[r][3] * zv[r];
+            }
         }
         double v[8] = {a0, a1, a2, a3, b0, b1, b2, b3};
         wave_transpose_reduce<8>(v);
@@ -627,8 +628,8 @@ __device__ __forceinline__ void dot_sweep(const double *__restrict__ V, int LV, 
 
 // s1[rr] = sum_m V[m][i] c1[m] and s2[rr] = sum_m V[m][i] c2[m] over m < cnt
 // on the thread's rows i = tid + rr * NTG (rows at or past n read row 0; the
-// caller discards them).  The loads of four vectors are issued before their
-// products, so 4 R loads are in flight.
+// caller discards them).  The loads of MB vectors are issued before their
+// products, so MB R loads are in flight.
 template <int R>
 __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t ld, int cnt,
                                            const double *c1, const double *c2, int n,
@@ -642,15 +643,16 @@ __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t
         s1[rr] = 0.0;
         s2[rr] = 0.0;
     }
+    constexpr int MB = 4;   // vectors per batch
     int m = 0;
-    for (; m + 4 <= cnt; m += 4) {
-        double v[4][R];
+    for (; m + MB <= cnt; m += MB) {
+        double v[MB][R];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < MB; ++j)
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) v[j][rr] = V[(m + j) * ld + off[rr]];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < MB; ++j) {
             const double a = c1[m + j], b = c2[m + j];
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
@@ -1019,14 +1021,22 @@ __device__ void basis_global(const DevSystem &S, const DevJob &J, const SmemG &s
                 const double *kn = K + (int64_t)(nok ? nn : 0) * ld;
                 const double *sn = SU + (int64_t)(nok ? nn : 0) * ld;
                 dbl4 ah = {0.0, 0.0, 0.0, 0.0}, as = {0.0, 0.0, 0.0, 0.0};
-                for (int i0 = 0; i0 < n; i0 += 4) {
-                    const int i = i0 + kk;
-                    const bool iok = i < n;
-                    const double a = (mok && iok) ? um[i] : 0.0;
-                    const double bh = (nok && iok) ? kn[i] : 0.0;
-                    const double bs = (nok && iok) ? sn[i] : 0.0;
-                    ah = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bh, ah, 0, 0, 0);
-                    as = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bs, as, 0, 0, 0);
+                // eight k-steps per batch: their 24 loads are issued together
+                for (int i0 = 0; i0 < n; i0 += 32) {
+                    double av[8], hv8[8], sv8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int i = i0 + 4 * u + kk;
+                        const bool iok = i < n;
+                        av[u] = (mok && iok) ? um[i] : 0.0;
+                        hv8[u] = (nok && iok) ? kn[i] : 0.0;
+                        sv8[u] = (nok && iok) ? sn[i] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        ah = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], hv8[u], ah, 0, 0, 0);
+                        as = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], sv8[u], as, 0, 0, 0);
+                    }
                 }
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
@@ -1065,13 +1075,13 @@ __host__ __device__ constexpr int64_t global_smem_doubles(int64_t nmax)
     return 4 * nmax + (3 * nmax + 1) / 2 + 6 * (kMaxNu + 1) + 4 * NWG;
 }
 
-// waves per SIMD the register allocation aims at: 3 for up to two rows per
-// thread, else 2
-template <int R>
-__host__ __device__ constexpr int global_waves() { return R <= 2 ? 3 : 2; }
+// waves per SIMD the register allocation aims at: 2 (with 3 the basis kernel
+// alone is faster, but it leaves no room for the eigensolver of the previous
+// chunk, and the pipelined solve is slower)
+constexpr int kGlobalWaves = 2;
 
 template <int O, int R, int PREC>
-__global__ void __launch_bounds__(NTG, global_waves<R>()) k_basis_g(DevSystem S, DevJob J)
+__global__ void __launch_bounds__(NTG, kGlobalWaves) k_basis_g(DevSystem S, DevJob J)
 {
     extern __shared__ double smem[];
     __shared__ double red[NWG];
