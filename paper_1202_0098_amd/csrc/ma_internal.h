@@ -12,7 +12,7 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kMaxNu = 64;
 constexpr int kBisectTrials = 15;        // trial potentials per bisection pass
 constexpr int kBisectPasses = 14;        // 16^14 = 7.2e16: any bracket narrows below 1e-15
-constexpr int kCountBlocks = 256;        // fixed grid of the electron-count kernel
+constexpr int kCountBlocks = 1024;       // fixed grid of the electron-count kernel
 constexpr int kNbDesc = 48;              // neighbours in a column descriptor
 constexpr int kNbOut = 12;               // atoms whose s_j coefficients the network predicts
 constexpr int kGeoFeat = 4 * kNbDesc;    // (d/5, dx/d, dy/d, dz/d) per neighbour

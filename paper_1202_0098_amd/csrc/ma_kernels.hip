@@ -2760,12 +2760,16 @@ __global__ void __launch_bounds__(256) k_count(const double *eps, const double *
 
 // rho, pi at the pattern slots of each column (Eqs. 13-14) and
 // E_j = sum_i rho_ij H_ji, N_j = sum_i rho_ij S_ji (Eq. 17), from the stored
-// amplitudes at the midpoint of the final bracket.
+// amplitudes at the midpoint of the final bracket.  With `stage`, a column's
+// amplitude block (pattern rows x nu, contiguous) is first copied into LDS
+// with coalesced loads, then each thread sums its row from there.
 template <typename TA>
 __global__ void __launch_bounds__(128) k_rho(DevSystem S, DevJob J, const double *mu_ptr,
                                              double kT, double *rho, double *pi, double *Ecol,
-                                             double *Ncol)
+                                             double *Ncol, int stage)
 {
+    extern __shared__ double rho_smem[];
+    TA *sa = reinterpret_cast<TA *>(rho_smem);
     __shared__ double f[kMaxNu], fe[kMaxNu];
     __shared__ double red[2][2];
     const double mu = 0.5 * (mu_ptr[0] + mu_ptr[1]);
@@ -2784,11 +2788,16 @@ __global__ void __launch_bounds__(128) k_rho(DevSystem S, DevJob J, const double
         const int64_t kb0 = S.blk_ptr[A];
         const int npat = (int)(S.blk_ptr[A + 1] - kb0) * o;
         const TA *amp = reinterpret_cast<const TA *>(J.amp) + J.amp_off[c];
+        if (stage) {
+            for (int e = threadIdx.x; e < npat * nu; e += blockDim.x) sa[e] = amp[e];
+            __syncthreads();
+        }
+        const TA *src = stage ? sa : amp;
         double ep = 0.0, np_ = 0.0;
         for (int t = threadIdx.x; t < npat; t += blockDim.x) {
             double sr = 0.0, sp = 0.0;
             for (int a = 0; a < L; ++a) {
-                const double am = (double)amp[t * nu + a];
+                const double am = (double)src[t * nu + a];
                 sr += f[a] * am;
                 sp += fe[a] * am;
             }
@@ -3044,11 +3053,20 @@ hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
     return launch_with_smem(k_eig<float>, grid, 64, smem, st, S, J);
 }
 
+// grid of the bracket and count kernels: about 2,048 Ritz pairs per
+// workgroup, between 64 and kCountBlocks workgroups
+int count_grid(int ncols, int nu)
+{
+    const int64_t g = ((int64_t)ncols * nu + 2047) / 2048;
+    return g < 64 ? 64 : g > kCountBlocks ? kCountBlocks : (int)g;
+}
+
 hipError_t launch_minmax(const double *eps, const int32_t *stats, int ncols, int nu, double kT,
                          double *lohi, double *partial, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_minmax, dim3(kCountBlocks), dim3(256), 0, st, eps, stats, ncols, nu, partial);
-    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, st, partial, kCountBlocks, kT, lohi,
+    const int grid = count_grid(ncols, nu);
+    hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(256), 0, st, eps, stats, ncols, nu, partial);
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(64), 0, st, partial, grid, kT, lohi,
                        count_done(partial));
     return hipGetLastError();
 }
@@ -3057,9 +3075,10 @@ hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *st
                          int nu, double kT, double n_target, double *lohi, double *partial,
                          hipStream_t st)
 {
+    const int grid = count_grid(ncols, nu);
     for (int pass = 0; pass < kBisectPasses; ++pass)
-        hipLaunchKernelGGL(k_count, dim3(kCountBlocks), dim3(256), 0, st, eps, wts, stats, ncols,
-                           nu, kT, n_target, lohi, partial, count_done(partial));
+        hipLaunchKernelGGL(k_count, dim3(grid), dim3(256), 0, st, eps, wts, stats, ncols, nu, kT,
+                           n_target, lohi, partial, count_done(partial));
     return hipGetLastError();
 }
 
@@ -3067,12 +3086,15 @@ hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr,
                       double *rho, double *pi, double *Ecol, double *Ncol, hipStream_t st)
 {
     const int grid = J.ncols < 65536 ? J.ncols : 65536;
+    const size_t blk = (size_t)S.maxpat * J.nu * (J.precision == 0 ? sizeof(double) : sizeof(float));
+    const int stage = blk <= 48 * 1024 ? 1 : 0;
+    const size_t smem = stage ? blk : 0;
     if (J.precision == 0)
-        hipLaunchKernelGGL(k_rho<double>, dim3(grid), dim3(128), 0, st, S, J, mu_ptr, kT, rho, pi,
-                           Ecol, Ncol);
+        hipLaunchKernelGGL(k_rho<double>, dim3(grid), dim3(128), smem, st, S, J, mu_ptr, kT, rho,
+                           pi, Ecol, Ncol, stage);
     else
-        hipLaunchKernelGGL(k_rho<float>, dim3(grid), dim3(128), 0, st, S, J, mu_ptr, kT, rho, pi,
-                           Ecol, Ncol);
+        hipLaunchKernelGGL(k_rho<float>, dim3(grid), dim3(128), smem, st, S, J, mu_ptr, kT, rho,
+                           pi, Ecol, Ncol, stage);
     return hipGetLastError();
 }
 
