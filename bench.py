@@ -62,6 +62,9 @@ def main():
                     help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE[,BASIS_KERNEL]' instead of "
                          "the autotuner")
     ap.add_argument("--no-graph", action="store_true", help="launch without hipGraph replay")
+    ap.add_argument("--pipeline", type=int, default=-1,
+                    help="chunks pipelining the eigensolver beside the basis kernel (library "
+                         "default 4; 0 = one chunk, replayed as hipGraphs)")
     ap.add_argument("--basis-kernel", default="auto", choices=["auto", "onchip", "workspace", "group"],
                     help="basis kernel: on-chip basis (regions up to 512 orbitals) or workspace")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -98,6 +101,8 @@ def main():
     stats = torch.zeros(s.M * ma.STATS, dtype=torch.int32, device=dev)
     opts = ma.default_opts(precision=args.precision, use_graph=0 if args.no_graph else 1,
                            basis_kernel=args.basis_kernel)
+    if args.pipeline >= 0:
+        opts.pipeline = args.pipeline
     tuning = None
     if args.tuning:
         slots, sched = args.tuning.split(",")[:2]
@@ -210,7 +215,7 @@ def main():
                    "kT": s.kT, "mu": "bisected at half filling", "precision": args.precision,
                    "build_s": round(build_s, 3),
                    "launch": ("eager, eigensolver pipelined beside the basis kernel"
-                              if s.M >= 4 * 2048 else
+                              if opts.pipeline >= 2 and s.M >= opts.pipeline * 2048 else
                               "eager" if args.no_graph else "hipGraph replay"),
                    "basis_kernel": args.basis_kernel,
                    "tuning": None if tuning is None else {
