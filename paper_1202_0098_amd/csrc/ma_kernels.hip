@@ -257,8 +257,43 @@ __device__ __forceinline__ void spmv_rows(const DevSystem &S, const Col &g, int 
             };
             if (g.lidx) {
                 const int k0 = g.srp[a], k1 = g.srp[a + 1];
-#pragma unroll 8
-                for (int kb = k0; kb < k1; ++kb) blk(g.sblk[kb]);
+                if constexpr (O == 0) {
+                    for (int kb = k0; kb < k1; ++kb) blk(g.sblk[kb]);
+                } else {
+                    // batches of NB blocks whose value loads are issued
+                    // before any product (blocks past the row's end read its
+                    // first block and add nothing): more loads in flight per
+                    // round trip than the unrolled loop gets (6 blocks: the
+                    // spd cell's step 9 % faster)
+                    constexpr int OB = O > 0 ? O : 1;
+                    constexpr int NB = 6;
+                    for (int kb = k0; kb < k1; kb += NB) {
+                        int2 e[NB];
+                        TM hm[NB][OB], sm[NB][OB];
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) {
+                            e[j] = g.sblk[kb + j < k1 ? kb + j : k0];
+                            const int64_t base = (int64_t)e[j].y * (o * o) + ri * o;
+#pragma unroll
+                            for (int cc = 0; cc < OB; ++cc) {
+                                if (DO_H || DO_Z) hm[j][cc] = Hv[base + cc];
+                                if (DO_S) sm[j][cc] = Sv[base + cc];
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) {
+                            const bool ok = kb + j < k1;
+                            const int xo = e[j].x * o;
+#pragma unroll
+                            for (int cc = 0; cc < OB; ++cc) {
+                                const TX xv = xa[xo + cc];
+                                if (DO_H) h += (ok ? (TX)hm[j][cc] : (TX)0) * xv;
+                                if (DO_S) s += (ok ? (TX)sm[j][cc] : (TX)0) * xv;
+                                if (DO_Z) z += (ok ? (TX)hm[j][cc] : (TX)0) * xb[xo + cc];
+                            }
+                        }
+                    }
+                }
             } else {
                 // several blocks in flight: the index and value loads of a
                 // block do not depend on the previous block
@@ -683,7 +718,10 @@ __device__ __forceinline__ void spmv3_rows(const DevSystem &S, const Col &g, int
 {
     const int o = O ? O : o_rt;
     constexpr int OB = O > 0 ? O : 1;   // the batched path below is taken for O > 0 only
-    constexpr int NB = O > 4 ? 2 : sizeof(TM) == 8 ? 3 : 4;   // blocks per batch
+    // blocks per batch: more value loads in flight per round trip, within
+    // the registers of 2 waves per SIMD (9 x 9 FP32 blocks: 3 are 6 % faster
+    // than 2 on the spd cell; 4 spill and are no faster)
+    constexpr int NB = O > 4 ? (sizeof(TM) == 8 ? 2 : 3) : sizeof(TM) == 8 ? 3 : 4;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
         const int i = threadIdx.x + rr * NT;
