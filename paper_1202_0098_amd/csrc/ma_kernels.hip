@@ -664,7 +664,9 @@ __device__ __forceinline__ void dot_sweep(const double *__restrict__ V, int LV, 
 // s1[rr] = sum_m V[m][i] c1[m] and s2[rr] = sum_m V[m][i] c2[m] over m < cnt
 // on the thread's rows i = tid + rr * NTG (rows at or past n read row 0; the
 // caller discards them).  The loads of MB vectors are issued before their
-// products, so MB R loads are in flight.
+// products, so MB R loads are in flight; the last batch is padded with
+// copies of its first vector at coefficient zero, so every batch is one round
+// trip (the sums are the same, term by term, as without the padding).
 template <int R>
 __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t ld, int cnt,
                                            const double *c1, const double *c2, int n,
@@ -679,30 +681,24 @@ __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t
         s2[rr] = 0.0;
     }
     constexpr int MB = 4;   // vectors per batch
-    int m = 0;
-    for (; m + MB <= cnt; m += MB) {
+    for (int m = 0; m < cnt; m += MB) {
         double v[MB][R];
 #pragma unroll
-        for (int j = 0; j < MB; ++j)
+        for (int j = 0; j < MB; ++j) {
+            const int mj = m + j < cnt ? m + j : m;
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) v[j][rr] = V[(m + j) * ld + off[rr]];
+            for (int rr = 0; rr < R; ++rr) v[j][rr] = V[mj * ld + off[rr]];
+        }
 #pragma unroll
         for (int j = 0; j < MB; ++j) {
-            const double a = c1[m + j], b = c2[m + j];
+            const bool ok = m + j < cnt;
+            const int mj = ok ? m + j : m;
+            const double a = ok ? c1[mj] : 0.0, b = ok ? c2[mj] : 0.0;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 s1[rr] += v[j][rr] * a;
                 s2[rr] += v[j][rr] * b;
             }
-        }
-    }
-    for (; m < cnt; ++m) {
-        const double a = c1[m], b = c2[m];
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            const double v = V[m * ld + off[rr]];
-            s1[rr] += v * a;
-            s2[rr] += v * b;
         }
     }
 }
