@@ -84,6 +84,7 @@ struct ma_ctx {
     hipStream_t stream = nullptr;     // the caller's stream
     hipStream_t own = nullptr;        // used instead when the caller's is the null stream
     hipStream_t aux = nullptr;        // eigensolver of chunk k beside the basis kernel of chunk k+1
+    hipStream_t aux2 = nullptr;       // eigensolver of the last chunk, beside the one before it
     hipEvent_t evu = nullptr;         // orders `own` after the caller's null stream
     // the stream the solve path enqueues on (the null stream cannot be captured)
     hipStream_t work_stream() const { return stream ? stream : own; }
@@ -453,7 +454,8 @@ MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
         hipEventCreate(&c->eve1) != hipSuccess ||
         hipEventCreateWithFlags(&c->evu, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return MA_EDEVICE;
     }
@@ -476,6 +478,7 @@ MA_API ma_status ma_destroy(ma_ctx *ctx)
     if (ctx->evu) (void)hipEventDestroy(ctx->evu);
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->aux2) (void)hipStreamDestroy(ctx->aux2);
     delete ctx;
     return MA_OK;
 }
@@ -1276,15 +1279,19 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         // eager: per chunk, events around the basis kernel (stream st) and the
         // eigensolver (st, or the aux stream when pipelined: chunk k's
         // eigensolver runs beside the later basis kernels; chunk k + nbuf
-        // reuses chunk k's buffer of the ring only after that eigensolver)
+        // reuses chunk k's buffer of the ring only after that eigensolver).
+        // The last chunk's eigensolver goes to a second stream, so that it
+        // starts when its basis kernel ends instead of queueing behind the
+        // previous chunk's: nothing else runs then, and the two eigensolvers
+        // write disjoint columns and ring slots.
         while ((int)ctx->chunk_ev.size() < 6 * P.nchunks) {
             hipEvent_t ev;
             HIPCHK(ctx, hipEventCreate(&ev), "event");
             ctx->chunk_ev.push_back(ev);
         }
-        hipStream_t es = P.pipelined ? ctx->aux : st;
         for (int k = 0; k < P.nchunks; ++k) {
             hipEvent_t *ev = &ctx->chunk_ev[6 * k];
+            const hipStream_t es = !P.pipelined ? st : (k > 0 && k == P.nchunks - 1) ? ctx->aux2 : ctx->aux;
             if (P.pipelined && k >= P.nbuf)
                 HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (k - P.nbuf) + 5], 0), "wait");
             HIPCHK(ctx, hipEventRecord(ev[0], st), "event");
@@ -1296,7 +1303,11 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
             HIPCHK(ctx, hipEventRecord(ev[3], es), "event");
             HIPCHK(ctx, hipEventRecord(ev[5], es), "event");
         }
-        if (P.pipelined) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (P.nchunks - 1) + 5], 0), "wait");
+        if (P.pipelined) {
+            HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (P.nchunks - 1) + 5], 0), "wait");
+            if (P.nchunks > 1)
+                HIPCHK(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[6 * (P.nchunks - 2) + 5], 0), "wait");
+        }
         HIPCHK(ctx, enqueue_post(ctx, P), "launch");
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
