@@ -984,14 +984,14 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
     int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
     // pipelining: for solves large enough, opts.pipeline + 2 chunks whose
-    // sizes fall geometrically (ratio 0.7), so the eigensolver of each chunk
-    // fits beside the basis kernel of the next and the last one, which
-    // nothing overlaps, is short; equal chunks where the chunk buffer caps
-    // the first
+    // sizes fall geometrically (ratio 0.75, the best of 0.6-0.8 measured), so
+    // the eigensolver of each chunk fits beside the basis kernel of the next
+    // and the last one, which nothing overlaps, is short; equal chunks where
+    // the chunk buffer caps the first
     std::vector<int64_t> target;   // column target per chunk
     if (opts.pipeline >= 2 && ncols >= (int64_t)opts.pipeline * 2048) {
         const int nch = opts.pipeline + 2;
-        const double r = 0.7;
+        const double r = 0.75;
         double norm = 0.0;
         for (int k = 0; k < nch; ++k) norm += std::pow(r, k);
         for (int k = 0; k < nch; ++k)
