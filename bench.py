@@ -55,8 +55,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="diamond4096")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_f64acc"])
+    ap.add_argument("--workload", default="fcc_spd",
+                    help="fcc_spd (default: the 262,144-atom spd cell), fcc_spd16384, "
+                         "diamond4096, disordered8000, diamond64")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "mixed_f64acc"],
+                    help="default: mixed_f64acc for the spd cells, fp64 otherwise")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="",
                     help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE[,BASIS_KERNEL]' instead of "
@@ -81,6 +84,8 @@ def main():
     import torch
     import paper_1202_0098_amd as ma
 
+    if args.precision is None:
+        args.precision = "mixed_f64acc" if args.workload.startswith("fcc_spd") else "fp64"
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     t_gen = time.perf_counter()
@@ -165,6 +170,8 @@ def main():
     reg_atoms, loc_blocks = ctx.region_sizes(s.n_atoms)
     counts = kernel_model(s, st, reg_atoms, loc_blocks, args.precision)
     achieved_gbs = counts["bytes"] / (k_ms * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
+    log(f"measured copy bandwidth {copy_gbs:.0f} GB/s")
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved_gbs, 2),
@@ -173,6 +180,9 @@ def main():
         "frac": round(achieved_gbs / PEAK_HBM_GBS, 5),
         "traffic": measured_traffic(s.name, args.precision),
         "algorithmic_bytes": round(counts["bytes"]),
+        "operator_applications_per_column": round(counts["n_app"], 3),
+        "measured_copy_peak": round(copy_gbs, 1),
+        "frac_of_measured_copy": round(achieved_gbs / copy_gbs, 5),
         "kernel": "basis kernel",
         "kernel_ms": round(k_ms, 4),
         "eig_kernel_ms": round(float(np.mean(eig_ms)), 4),
@@ -227,6 +237,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def device_source_digest():
+    """SHA-256 over the device sources of the library (sorted by name)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1202_0098_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith(".hip") or fn in ("ma_device.h", "ma_internal.h"):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload_name, precision):
     """HBM bytes per step of the basis kernel (summed over its launches in a
     step) from the committed counter summary of this workload and precision
@@ -235,7 +257,6 @@ def measured_traffic(workload_name, precision):
     changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_basis_{workload_name}_{precision}_traffic.md")
-    src = os.path.join(ROOT, "paper_1202_0098_amd", "csrc", "ma_kernels.hip")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -244,9 +265,7 @@ def measured_traffic(workload_name, precision):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    if fields.get("kernel source sha256") != digest:
+    if fields.get("kernel source sha256") != device_source_digest():
         return None
     try:
         return float(fields["HBM bytes per step"])
@@ -255,36 +274,53 @@ def measured_traffic(workload_name, precision):
 
 
 def kernel_model(s, st, reg_atoms, loc_blocks, precision):
-    """Algorithmic bytes and flops of the basis kernel over one step.
+    """Algorithmic bytes and flops of the basis kernel over one step
+    (operator-streaming model).
 
-    Per column j with region dimension n = o * (atoms of the region), local
-    operator blocks nb (o x o each), nu_eff = L accepted basis vectors and c
-    operator applications in the CG (iterations plus FP64 residual checks):
-      operator applications  a = c (S) + 2 L (H and S on each candidate)
-                             + q (H on the chain vectors of block 2)
-      operator bytes         a * nb * (o^2 v + 4) / o: each application
-                             streams the region operator once (v = 8 bytes per
-                             FP64 value, 4 per FP32 value, 4 bytes of block
-                             index), shared by the o columns of the atom
-      compulsory outputs     Ritz values and weights (16 nu bytes) and the
-                             amplitudes at the pattern rows (8 or 4 bytes per
-                             row and Ritz vector)
-      flops                  2 o^2 nb per application, plus ~6 n L^2 FP64 flops
-                             of Gram-Schmidt and projection
+    Per column j of atom A, with nb local operator blocks (o x o each, H and S
+    share the pattern), L accepted basis vectors and c CG iterations:
+      n_app  = 2 L + c (+1 when the learned start was used: its residual
+               check) operator applications -- H and S once per basis vector,
+               S once per CG iteration; the H product of the block-2 chain
+               rides in the same operator pass and streams nothing extra
+      bytes  = n_app nb (o^2 v + 4) / o + 16 |pattern(j)|: every application
+               streams the region operator once (v = 8 bytes per FP64 value,
+               4 per FP32 value, 4 bytes of block index), shared by the o
+               columns of the atom, and rho and pi are written once (FP64)
+      flops  = 2 o^2 nb per application and column, plus ~8 n L^2 FP64
+               flops of Gram-Schmidt and projection
     """
     o = s.n_orb
-    nu = s.p + s.q
     a = np.arange(s.M) // o
     L = st[:, 0].astype(float)
-    c = st[:, 1].astype(float) + st[:, 2].astype(float)
-    n = reg_atoms[a].astype(float) * o
+    c = st[:, 1].astype(float) + (st[:, 4] == 1).astype(float)
     nb = loc_blocks[a].astype(float)
     npat = np.diff(s.blk_ptr)[a].astype(float) * o
-    apps = c + 2 * L + s.q
-    flops = float(np.sum(2 * o * o * nb * apps + 6 * n * L * L))
+    n = reg_atoms[a].astype(float) * o
+    apps = 2 * L + c
     vbytes = 8 if precision == "fp64" else 4
-    bytes_ = float(np.sum(apps * nb * (o * o * vbytes + 4) / o + 16 * nu + npat * nu * vbytes))
-    return {"flops": flops, "bytes": bytes_}
+    bytes_ = float(np.sum(apps * nb * (o * o * vbytes + 4) / o + 16 * npat))
+    flops = float(np.sum(2 * o * o * nb * apps + 8 * n * L * L))
+    return {"flops": flops, "bytes": bytes_, "n_app": float(np.mean(apps))}
+
+
+def copy_bandwidth(torch, mib=2048, reps=10):
+    """Measured HBM bandwidth of a plain elementwise copy (read + write of
+    MIB MiB each), timed with events on the current stream: the achievable
+    second denominator beside the published peak."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
 if __name__ == "__main__":

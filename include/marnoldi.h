@@ -191,59 +191,107 @@ typedef struct {
     int32_t tried_kernel[64];
 } ma_tuning;
 
-/* Library version string. */
+/* Library version string (static storage). */
 MA_API const char *ma_version(void);
 
-/* Fill *o with the defaults listed above. */
+/* Fill *o with the defaults listed above (NULL: no-op). */
 MA_API void ma_default_opts(ma_opts *o);
 
 /* Create a context on HIP device `device` that enqueues on `stream` (a
  * hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the null
- * stream).  The context owns every device buffer it allocates. */
+ * stream).  The context owns every device buffer it allocates; *out is NULL
+ * on failure (MA_EDEVICE: no such device or a HIP call failed). */
 MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream);
 
-/* Free every resource of the context. */
+/* Free every resource of the context (MA_EINVAL for NULL). */
 MA_API ma_status ma_destroy(ma_ctx *ctx);
 
-/* Description of the last error on this context (never NULL). */
+/* Description of the last error on this context (never NULL; owned by the
+ * context, valid until its next call). */
 MA_API const char *ma_last_error(const ma_ctx *ctx);
 
-/* Validate the pencil, build the per-atom regions and their local block
- * operators, and upload everything (FP64 and FP32 copies) to the device.
- * Replaces any previous system of the context.  MA_EINVAL on a malformed
- * pattern, asymmetric or non-finite values, unsupported o, or a region that
- * misses part of its atom's pattern. */
+/* Load the pencil (H, S) of Sec. 2 -- H real symmetric, S symmetric positive
+ * definite, both sparse in the atom-block pattern -- and build the real-space
+ * region of every atom (Sec. 3, the projection of H and S onto a sphere or
+ * the N_RP nearest atoms around the atom of basis j) with its local block
+ * operators H_A, S_A (principal submatrices, addressed through a local block
+ * index: the values are not copied per region).  Host arrays are copied;
+ * FP64 and FP32 copies of H and S are uploaded.  Replaces any previous system
+ * of the context.  MA_EINVAL (nothing uploaded) on a malformed pattern,
+ * asymmetric or non-finite values, unsupported o, or a region that misses
+ * part of its atom's pattern. */
 MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_region *reg);
 
-/* Sizes of the built system: M, nblk, the largest region dimension and the
- * largest number of pattern rows of a column. */
+/* Sizes of the built system (Sec. 3 regions): M, nblk, the largest region
+ * dimension and the largest number of pattern rows of a column; any output
+ * pointer may be NULL.  MA_ESTATE before a successful build. */
 MA_API ma_status ma_system_info(const ma_ctx *ctx, int64_t *M, int64_t *nblk,
                                 int32_t *max_region_orbitals, int32_t *max_pattern_rows);
 
-/* Per-atom sizes of the built system (host arrays of n_atoms entries, either
- * may be NULL): the number of atoms in the atom's region and the number of
- * blocks of its local operator H_A (the same pattern serves S_A). */
+/* Per-atom sizes of the real-space regions (Sec. 3) of the built system
+ * (host arrays of n_atoms entries, either may be NULL): the number of atoms
+ * in the atom's region and the number of blocks of its local operator H_A
+ * (the same pattern serves S_A). */
 MA_API ma_status ma_region_sizes(const ma_ctx *ctx, int32_t *region_atoms,
                                  int64_t *local_blocks);
 
-/* Host-only query (no device is used): the region of `atom` that
- * ma_build_system would build for (sys, reg), ascending atom indices, written
- * to out[0..min(count, cap)).  Returns the region's atom count, or a negative
- * ma_status on invalid arguments.  Meant for inspecting and testing the
- * real-space projection. */
+/* Host-only query (no device is used): the region of `atom` (Sec. 3,
+ * real-space projection) that ma_build_system would build for (sys, reg),
+ * ascending atom indices, written to out[0..min(count, cap)) (host, caller
+ * owned).  Returns the region's atom count, or a negative ma_status on
+ * invalid arguments. */
 MA_API int64_t ma_region_atoms(const ma_system *sys, const ma_region *reg, int32_t atom,
                                int32_t *out, int64_t cap);
 
-/* Solve columns cols[0..ncols) (host array of global orbital indices; NULL =
- * all M columns, in order) with subspace dimensions p >= 1, q >= 0,
- * p + q <= MA_MAX_NU, temperature kT > 0 and chemical potential mu (NaN:
- * bisect so that sum_j N_j = opts->n_target over the solved columns).
- * opts NULL = defaults.  Breakdowns are not errors (see col_stats).  Returns
- * MA_ENOTPD / MA_ENOCONV if some column's CG failed (the first such column is
- * named by ma_last_error); outputs are then undefined for that column. */
+/* The per-column multiple Arnoldi solve (Sec. 2): for every column j of
+ * cols[0..ncols) (host array of global orbital indices; NULL = all M columns,
+ * in order) the inner CG for s_j = S_A^-1 e_j, the S-orthonormal basis of
+ * K_p(H; e_j) + K_q(H; s_j) (Eq. 4, built by Eqs. 6-9), the Galerkin pair and
+ * its eigenpairs (Eq. 10), and rho_ij, pi_ij (Eqs. 13-14) with E_j, N_j
+ * (Eq. 17 and Tr rho S), at temperature kT > 0 and chemical potential mu
+ * (NaN: bisect so that sum_j N_j = opts->n_target over the solved columns,
+ * Sec. 2, electron count summed over j).  p >= 1, q >= 0, p + q <=
+ * MA_MAX_NU; opts NULL = defaults.  Outputs go to the caller's device
+ * pointers in *out (any may be NULL) and the scalars of *out.  Breakdowns are
+ * not errors (see col_stats).  Returns MA_ENOTPD / MA_ENOCONV if some
+ * column's CG failed (the first such column is named by ma_last_error);
+ * outputs are then undefined for that column.  A bisected solve keeps its
+ * Ritz data and amplitudes for ma_find_mu until the next solve. */
 MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *cols,
                                   int32_t p, int32_t q, double mu, double kT,
                                   const ma_opts *opts, ma_result *out);
+
+/* Chemical potential again (Sec. 2: mu fixed by the electron count summed
+ * over the basis index j), on the Ritz values, weights and amplitudes of the
+ * last solve, which must have bisected mu (else MA_ESTATE): K-section on
+ * sum_j sum_a f((eps_a - mu)/kT) w_a = n_target (per spin), then rho and pi
+ * (Eqs. 13-14, into out->rho / out->pi, device, same layout as the solve,
+ * either may be NULL; only the solved columns' rows are written) and
+ * out->energy, out->n_elec (times `spin`), out->mu, out->elapsed_ms.  kT may
+ * differ from the solve's: the amplitudes do not depend on it.  No column is
+ * re-solved.  If the solve wrote its Ritz data to the caller's eps/wts
+ * buffers (or into a caller workspace), those must still hold them. */
+MA_API ma_status ma_find_mu(ma_ctx *ctx, double n_target, double kT, double spin,
+                            ma_result *out);
+
+/* Bytes of device workspace a solve with these arguments (the arguments of
+ * ma_solve_columns; only whether mu is NaN matters) needs when the caller
+ * provides it: the column lists, the basis workspace of the persistent
+ * workgroups, the chunk buffers, Ritz data, amplitudes (bisected solves),
+ * statistics and the reduction scratch.  0 on invalid arguments
+ * (ma_last_error says why).  An upper bound: buffers the caller passes in
+ * ma_result (eps, wts, col_stats) are counted as if the library held them. */
+MA_API size_t ma_workspace_size(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
+                                int32_t q, double mu, const ma_opts *opts);
+
+/* Use [device_ptr, device_ptr + bytes) (caller owned, 256-byte aligned,
+ * device memory of the context's device) for the per-solve buffers of the
+ * following solves and autotuning instead of the library's own allocations;
+ * NULL, 0 goes back to them.  A solve that needs more than `bytes` fails with
+ * MA_EINVAL naming the size it needs.  The workspace must stay valid while a
+ * solve runs and, for ma_find_mu, until the next solve.  The system (H, S,
+ * regions) stays in the library's own memory. */
+MA_API ma_status ma_set_workspace(ma_ctx *ctx, void *device_ptr, size_t bytes);
 
 /* ------------------------------------------------------------------------
  * Learned CG start (callers that want fewer CG iterations).  A 3-layer
@@ -262,35 +310,46 @@ typedef struct {
     int64_t n_params;   /* W1 (n_in x n_hidden), b1, W2 (n_hidden^2), b2, W3 (n_hidden x n_out), b3 */
 } ma_mlp_shape;
 
-/* Shape of the start network for the built system. */
+/* Shape of the start network for the built system (MA_ESTATE before a
+ * build).  The network is not part of the paper's method: it only supplies
+ * the start vector of the inner CG of Sec. 2, whose result it does not
+ * change beyond the CG tolerance. */
 MA_API ma_status ma_mlp_shape_of(const ma_ctx *ctx, ma_mlp_shape *out);
 
 /* Random initial weights (He-scaled normal, zero biases, seeded) and zeroed
- * Adam state; the network becomes the context's start model. */
+ * Adam state; the network becomes the context's start model (the CG start
+ * of Sec. 2).  MA_ESTATE before a build. */
 MA_API ma_status ma_mlp_init(ma_ctx *ctx, uint64_t seed);
 
-/* Copy the parameters (host, FP32, the packed order of ma_mlp_shape) in/out. */
+/* Copy the start network's parameters (host, FP32, caller owned, the packed
+ * order of ma_mlp_shape) in/out; MA_EINVAL if count != n_params. */
 MA_API ma_status ma_mlp_set_params(ma_ctx *ctx, const float *params, int64_t count);
 MA_API ma_status ma_mlp_get_params(const ma_ctx *ctx, float *params, int64_t count);
 
-/* Descriptors of cols[0..ncols) (host list) into feat (device, ncols * n_in). */
+/* Descriptors of cols[0..ncols) (host list) into feat (device, caller owned,
+ * ncols * n_in FP32): the local geometry around atom(j) that the start
+ * network reads (needs positions in ma_system). */
 MA_API ma_status ma_column_features(ma_ctx *ctx, int64_t ncols, const int32_t *cols, float *feat);
 
-/* y = net(x) for n rows (device arrays, n * n_in -> n * n_out); bf16 = 1 uses
- * the inference kernel, 0 the FP32 training path. */
+/* y = net(x) for n rows (device arrays, caller owned, n * n_in -> n * n_out,
+ * FP32); bf16 = 1 uses the inference kernel (BF16 matrix cores, FP32
+ * accumulation), 0 the FP32 training path. */
 MA_API ma_status ma_mlp_forward(ma_ctx *ctx, const float *x, int64_t n, float *y, int32_t bf16);
 
-/* Mean squared error over n rows (rows idx[i] of x and t if idx != NULL) and
- * its gradient (host, n_params floats, may be NULL). */
+/* Mean squared error of the start network over n rows (rows idx[i] of x and
+ * t, device, if idx != NULL, else rows 0..n-1) and its gradient (host,
+ * n_params floats, may be NULL).  Indices are checked on the host. */
 MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
                                   int64_t n, double *loss, float *grad);
 
-/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error of the
- * n rows idx[i] (device int32, NULL = rows 0..n-1) of x and t (device). */
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) of the start network on the
+ * mean squared error of the n rows idx[i] (device int32, NULL = rows
+ * 0..n-1) of x and t (device); the loss before the step in *loss. */
 MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
                                    int64_t n, float lr, double *loss);
 
-/* Autotuner: time the basis kernel on cols[0..ncols) (NULL = all) for every
+/* Autotuner of the launch (not part of the paper's method, which runs the
+ * columns of Sec. 2 independently): time the solve on cols[0..ncols) (NULL = all) for every
  * candidate -- basis kernel (each one that can hold the shape) x
  * slots per CU from 1 to that kernel's occupancy limit x every schedule --
  * `reps` times each at chemical potential mu (finite), and keep the fastest
@@ -301,7 +360,7 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
                              int32_t q, double mu, double kT, const ma_opts *opts, int32_t reps,
                              ma_tuning *out);
 
-/* Store a previously found tuning for (p, q, precision) (e.g. from a cache);
+/* Store a previously found launch tuning for (p, q, precision) (e.g. from a cache);
  * basis_kernel is MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE or MA_BASIS_GROUP
  * (MA_BASIS_AUTO keeps the automatic choice). */
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,

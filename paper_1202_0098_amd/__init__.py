@@ -29,7 +29,8 @@ API_FUNCTIONS = ("ma_version", "ma_default_opts", "ma_create", "ma_destroy", "ma
                  "ma_build_system", "ma_system_info", "ma_region_sizes", "ma_region_atoms",
                  "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
                  "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
-                 "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step")
+                 "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step", "ma_find_mu",
+                 "ma_workspace_size", "ma_set_workspace")
 
 
 class MarnoldiError(RuntimeError):
@@ -134,13 +135,20 @@ def load_library():
     lib.ma_mlp_forward.argtypes = [P, P, i64, P, i32]
     lib.ma_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, P]
     lib.ma_mlp_train_step.argtypes = [P, P, P, P, i64, ctypes.c_float, P]
+    lib.ma_find_mu.argtypes = [P, f64, f64, f64, ctypes.POINTER(_Result)]
+    lib.ma_find_mu.restype = ctypes.c_int
+    lib.ma_workspace_size.argtypes = [P, i64, P, i32, i32, f64, ctypes.POINTER(_Opts)]
+    lib.ma_workspace_size.restype = ctypes.c_size_t
+    lib.ma_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+    lib.ma_set_workspace.restype = ctypes.c_int
     for name in ("ma_mlp_shape_of", "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params",
                  "ma_column_features", "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("ma_create", "ma_destroy", "ma_build_system", "ma_system_info",
                  "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
                  "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
-                 "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step"):
+                 "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step", "ma_find_mu",
+                 "ma_set_workspace"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -351,7 +359,40 @@ class Context:
         o = opts if opts is not None else default_opts()
         res = _Result(_ptr(rho), _ptr(pi), _ptr(eps), _ptr(wts), _ptr(col_stats), 0.0, 0.0, 0.0,
                       0.0, 0.0, _ptr(sj_near), 0.0)
-        self._check(self._lib.ma_solve_columns(self._h, n, cptr, int(p), int(q), float(mu),
-                                               float(kT), ctypes.byref(o), ctypes.byref(res)))
+        self._check(self._lib.ma_solve_columns(self._h, n, cptr, int(p), int(q), float(mu), float(kT), ctypes.byref(o),
+                       ctypes.byref(res)))
         return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, res.kernel_ms,
                            res.eig_ms)
+
+    def find_mu(self, n_target, kT, spin=2.0, rho=None, pi=None) -> SolveResult:
+        """Bisect mu again on the last bisected solve's Ritz data and rewrite
+        rho/pi (optional torch device tensors) without re-solving."""
+        res = _Result(_ptr(rho), _ptr(pi), None, None, None, 0.0, 0.0, 0.0, 0.0, 0.0, None, 0.0)
+        self._check(self._lib.ma_find_mu(self._h, float(n_target), float(kT), float(spin),
+                                         ctypes.byref(res)))
+        return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, 0.0, 0.0)
+
+    def workspace_size(self, cols, p, q, mu=math.nan, opts=None) -> int:
+        """Bytes of caller workspace a solve with these arguments needs."""
+        if cols is None:
+            cptr, n = None, 0
+        else:
+            cols = np.ascontiguousarray(cols, np.int32)
+            cptr, n = _ptr(cols), len(cols)
+        o = opts if opts is not None else default_opts()
+        nbytes = self._lib.ma_workspace_size(self._h, n, cptr, int(p), int(q), float(mu),
+                                             ctypes.byref(o))
+        if nbytes == 0:
+            raise MarnoldiError(MA_EINVAL, self._lib.ma_last_error(self._h).decode())
+        return int(nbytes)
+
+    def set_workspace(self, buf=None):
+        """Use a caller-owned device buffer (a torch tensor, 256-byte aligned)
+        for the per-solve buffers; None goes back to the library's own."""
+        if buf is None:
+            self._check(self._lib.ma_set_workspace(self._h, None, 0))
+            self._keep = None
+        else:
+            self._check(self._lib.ma_set_workspace(self._h, buf.data_ptr(),
+                                                   buf.numel() * buf.element_size()))
+            self._keep = buf

@@ -142,6 +142,19 @@ struct ma_ctx {
     hipGraphExec_t gexec0 = nullptr;  // descriptors and start network (learned start)
     std::vector<unsigned char> gkey;
 
+    // caller-owned workspace (ma_set_workspace): the per-solve buffers are
+    // carved from it instead of the library's own allocations
+    char *user_ws = nullptr;
+    size_t user_ws_bytes = 0;
+
+    // The last solve that bisected the chemical potential: its Ritz data and
+    // amplitudes stay where that solve wrote them, for ma_find_mu, until the
+    // next solve, build or workspace change.
+    bool last_valid = false;
+    ma::DevSystem lastS{};
+    ma::DevJob lastJ{};
+    double *last_lohi = nullptr, *last_partial = nullptr, *last_sums = nullptr;
+
     // autotuned (slots per CU, schedule) per (p, q, precision)
     struct Tune { int p, q, prec, slots, sched, kernel; };
     std::vector<Tune> tunes;
@@ -502,6 +515,7 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     if (!ctx) return MA_EINVAL;
     if (!sys || !reg) return ctx->fail(MA_EINVAL, "null system or region");
     ctx->built = false;
+    ctx->last_valid = false;
     ctx->drop_graph();
     ctx->generation++;
     const int n = sys->n_atoms, o = sys->n_orb;
@@ -821,6 +835,13 @@ struct Plan {
     ma::DevJob J;                // J.c0, J.cn, J.qbounds describe chunk 0
     const int32_t *qb_dev = nullptr;
     double *rho = nullptr, *pi = nullptr;
+    // per-solve device buffers (the library's own, or carved from a caller
+    // workspace or the allocation-free scratch)
+    float *feat = nullptr, *x0 = nullptr;
+    int *ctl = nullptr;
+    double *lohi = nullptr, *partial = nullptr, *sums = nullptr;
+    size_t bytes = 0;              // bytes the buffers take (sizing)
+    bool timed_chunks = true;      // per-chunk timing events (multi-chunk solves)
     ma::DevJob chunk_job(int k) const
     {
         ma::DevJob Jk = J;
@@ -840,11 +861,34 @@ struct Plan {
 constexpr size_t kMidBudget = (size_t)4 << 30;
 constexpr size_t kRingBudget = (size_t)8 << 30;
 
+// Where the per-solve buffers of a plan come from: the library's own
+// allocations (grown as needed), or consecutive 256-byte aligned pieces of a
+// caller-provided region (a caller workspace, or the allocation-free
+// scratch); with `size_only` nothing is placed and only the bytes are counted.
+struct BufSource {
+    char *base = nullptr;      // null: the library's own allocations
+    size_t cap = 0;
+    size_t off = 0;
+    bool size_only = false;
+    bool limited = false;      // the region is small: cap the chunk buffer and
+                               // the persistent workgroups to fit
+    bool region() const { return base != nullptr || size_only; }
+    void *take(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        void *ptr = size_only ? nullptr : base + off;
+        off += n;
+        return ptr;
+    }
+};
+
 ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, int32_t q,
                     double mu, double kT, const ma_opts *opts_in, double *rho, double *pi,
                     double *eps, double *wts, int32_t *col_stats, float *sj_near,
-                    int slots_override, int sched_override, Plan &P)
+                    int slots_override, int sched_override, Plan &P, BufSource *src = nullptr)
 {
+    BufSource own;
+    if (!src) src = &own;
     if (!ctx->built) return ctx->fail(MA_ESTATE, "ma_build_system has not succeeded");
     ma_default_opts(&P.opts);
     if (opts_in) P.opts = *opts_in;
@@ -981,7 +1025,8 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
 
     // chunks: whole work items, at most the chunk budget of columns each
     J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
-    const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(kMidBudget / (sizeof(double) * J.mid_stride)));
+    const size_t mid_budget = src->limited ? src->cap / 4 : kMidBudget;
+    const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(mid_budget / (sizeof(double) * J.mid_stride)));
     int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
     // pipelining: for solves large enough, opts.pipeline + 2 chunks whose
     // sizes fall geometrically (ratio 0.75, the best of 0.6-0.8 measured), so
@@ -1082,67 +1127,144 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     const size_t amp_bytes = (opts.precision == MA_PREC_FP64 ? sizeof(double) : sizeof(float)) *
                              std::max<size_t>(1, amp_elems);
 
-    HIPCHK(ctx, ctx->cols.reserve(sizeof(int32_t) * ncols), "cols");
-    HIPCHK(ctx, ctx->order.reserve(sizeof(int32_t) * ncols), "order");
-    HIPCHK(ctx, ctx->qbounds.reserve(sizeof(int32_t) * qb.size()), "queues");
-    if (P.kind != ma::kBasisOnchip)
-        HIPCHK(ctx, ctx->ws.reserve(sizeof(double) * (size_t)J.ws_stride * P.slots), "workspace");
-    HIPCHK(ctx, ctx->mid.reserve(sizeof(double) * (size_t)J.mid_stride * P.max_cn * P.nbuf),
-           "chunk buffer");
-    HIPCHK(ctx, ctx->gstart.reserve(sizeof(int32_t) * (nitems + 1)), "work items");
-    HIPCHK(ctx, ctx->eps.reserve(sizeof(double) * (size_t)ncols * P.nu), "eps");
-    HIPCHK(ctx, ctx->wts.reserve(sizeof(double) * (size_t)ncols * P.nu), "wts");
-    if (P.bisect) {
-        HIPCHK(ctx, ctx->amp.reserve(amp_bytes), "amplitudes");
-        HIPCHK(ctx, ctx->amp_off.reserve(sizeof(int64_t) * (ncols + 1)), "amplitude offsets");
+    // per-solve buffers: the library's own, or pieces of the caller's region
+    const bool learned = opts.start == MA_START_LEARNED;
+    const size_t n_cols = sizeof(int32_t) * ncols, n_order = sizeof(int32_t) * ncols,
+                 n_qb = sizeof(int32_t) * qb.size(), n_gstart = sizeof(int32_t) * (nitems + 1),
+                 n_eps = eps ? 0 : sizeof(double) * (size_t)ncols * P.nu,
+                 n_wts = wts ? 0 : sizeof(double) * (size_t)ncols * P.nu,
+                 n_amp = P.bisect ? amp_bytes : 0,
+                 n_aoff = P.bisect ? sizeof(int64_t) * (ncols + 1) : 0,
+                 n_stats = col_stats ? 0 : sizeof(int32_t) * (size_t)ncols * ma::kStats,
+                 n_feat = learned ? sizeof(float) * (size_t)ncols * ctx->net.nf : 0,
+                 n_x0 = learned ? sizeof(float) * (size_t)ncols * ctx->net.no : 0,
+                 n_ctl = sizeof(int) * 16, n_lohi = sizeof(double) * 2,
+                 n_partial = sizeof(double) * (ma::kCountBlocks * ma::kBisectTrials + 1),
+                 n_E = sizeof(double) * ncols, n_sums = sizeof(double) * 2,
+                 n_mid = sizeof(double) * (size_t)J.mid_stride * P.max_cn * P.nbuf,
+                 slot_bytes = P.kind == ma::kBasisOnchip ? 0 : sizeof(double) * (size_t)J.ws_stride;
+    void *b_cols, *b_order, *b_qb, *b_gstart, *b_ws = nullptr, *b_mid, *b_eps = nullptr,
+         *b_wts = nullptr, *b_amp = nullptr, *b_aoff = nullptr, *b_stats = nullptr,
+         *b_feat = nullptr, *b_x0 = nullptr, *b_ctl, *b_lohi, *b_partial, *b_E, *b_N, *b_sums;
+    if (src->region()) {
+        b_cols = src->take(n_cols);
+        b_order = src->take(n_order);
+        b_qb = src->take(n_qb);
+        b_gstart = src->take(n_gstart);
+        b_mid = src->take(n_mid);
+        if (n_eps) b_eps = src->take(n_eps);
+        if (n_wts) b_wts = src->take(n_wts);
+        if (n_amp) b_amp = src->take(n_amp);
+        if (n_aoff) b_aoff = src->take(n_aoff);
+        if (n_stats) b_stats = src->take(n_stats);
+        if (n_feat) b_feat = src->take(n_feat);
+        if (n_x0) b_x0 = src->take(n_x0);
+        b_ctl = src->take(n_ctl);
+        b_lohi = src->take(n_lohi);
+        b_partial = src->take(n_partial);
+        b_E = src->take(n_E);
+        b_N = src->take(n_E);
+        b_sums = src->take(n_sums);
+        if (slot_bytes) {
+            if (src->limited) {
+                // as many persistent workgroups as the rest of the region holds
+                const size_t used = (src->off + 255) & ~(size_t)255;
+                const int64_t fit = used < src->cap ? (int64_t)((src->cap - used) / slot_bytes) : 0;
+                if (fit < 1)
+                    return ctx->fail(MA_EINVAL, "the solve needs more than the %zu-byte scratch "
+                                     "(%zu bytes before the first basis workspace of %zu bytes)",
+                                     src->cap, used, slot_bytes);
+                P.slots = (int)std::min<int64_t>(P.slots, fit);
+            }
+            b_ws = src->take(slot_bytes * P.slots);
+        }
+        P.bytes = (src->off + 255) & ~(size_t)255;
+        if (src->size_only) return MA_OK;
+        if (src->off > src->cap)
+            return ctx->fail(MA_EINVAL, "the solve needs %zu bytes of workspace, %zu given",
+                             src->off, src->cap);
+    } else {
+        HIPCHK(ctx, ctx->cols.reserve(n_cols), "cols");
+        HIPCHK(ctx, ctx->order.reserve(n_order), "order");
+        HIPCHK(ctx, ctx->qbounds.reserve(n_qb), "queues");
+        HIPCHK(ctx, ctx->gstart.reserve(n_gstart), "work items");
+        if (slot_bytes) HIPCHK(ctx, ctx->ws.reserve(slot_bytes * P.slots), "workspace");
+        HIPCHK(ctx, ctx->mid.reserve(n_mid), "chunk buffer");
+        if (n_eps) HIPCHK(ctx, ctx->eps.reserve(n_eps), "eps");
+        if (n_wts) HIPCHK(ctx, ctx->wts.reserve(n_wts), "wts");
+        if (n_amp) HIPCHK(ctx, ctx->amp.reserve(n_amp), "amplitudes");
+        if (n_aoff) HIPCHK(ctx, ctx->amp_off.reserve(n_aoff), "amplitude offsets");
+        if (n_stats) HIPCHK(ctx, ctx->stats.reserve(n_stats), "stats");
+        if (n_feat) HIPCHK(ctx, ctx->feat.reserve(n_feat), "descriptors");
+        if (n_x0) HIPCHK(ctx, ctx->x0.reserve(n_x0), "start vectors");
+        HIPCHK(ctx, ctx->ctl.reserve(n_ctl), "ctl");
+        HIPCHK(ctx, ctx->lohi.reserve(n_lohi), "lohi");
+        HIPCHK(ctx, ctx->partial.reserve(n_partial), "partial");
+        HIPCHK(ctx, ctx->Ecol.reserve(n_E), "Ecol");
+        HIPCHK(ctx, ctx->Ncol.reserve(n_E), "Ncol");
+        HIPCHK(ctx, ctx->sums.reserve(n_sums), "sums");
+        b_cols = ctx->cols.p;
+        b_order = ctx->order.p;
+        b_qb = ctx->qbounds.p;
+        b_gstart = ctx->gstart.p;
+        b_ws = slot_bytes ? ctx->ws.p : nullptr;
+        b_mid = ctx->mid.p;
+        b_eps = n_eps ? ctx->eps.p : nullptr;
+        b_wts = n_wts ? ctx->wts.p : nullptr;
+        b_amp = n_amp ? ctx->amp.p : nullptr;
+        b_aoff = n_aoff ? ctx->amp_off.p : nullptr;
+        b_stats = n_stats ? ctx->stats.p : nullptr;
+        b_feat = n_feat ? ctx->feat.p : nullptr;
+        b_x0 = n_x0 ? ctx->x0.p : nullptr;
+        b_ctl = ctx->ctl.p;
+        b_lohi = ctx->lohi.p;
+        b_partial = ctx->partial.p;
+        b_E = ctx->Ecol.p;
+        b_N = ctx->Ncol.p;
+        b_sums = ctx->sums.p;
     }
-    HIPCHK(ctx, ctx->stats.reserve(sizeof(int32_t) * (size_t)ncols * ma::kStats), "stats");
-    if (opts.start == MA_START_LEARNED) {
-        HIPCHK(ctx, ctx->feat.reserve(sizeof(float) * (size_t)ncols * ctx->net.nf), "descriptors");
-        HIPCHK(ctx, ctx->x0.reserve(sizeof(float) * (size_t)ncols * ctx->net.no), "start vectors");
-    }
-    HIPCHK(ctx, ctx->ctl.reserve(sizeof(int) * 16), "ctl");
-    HIPCHK(ctx, ctx->lohi.reserve(sizeof(double) * 2), "lohi");
-    HIPCHK(ctx, ctx->partial.reserve(sizeof(double) * (ma::kCountBlocks * ma::kBisectTrials + 1)), "partial");
-    HIPCHK(ctx, ctx->Ecol.reserve(sizeof(double) * ncols), "Ecol");
-    HIPCHK(ctx, ctx->Ncol.reserve(sizeof(double) * ncols), "Ncol");
-    HIPCHK(ctx, ctx->sums.reserve(sizeof(double) * 2), "sums");
     hipStream_t st = ctx->work_stream();
     HIPCHK(ctx, ctx->after_caller(), "stream order");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->cols.p, P.hcols.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "cols");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int32_t) * ncols, hipMemcpyHostToDevice, st), "order");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->qbounds.p, qb.data(), sizeof(int32_t) * qb.size(), hipMemcpyHostToDevice, st), "queues");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->gstart.p, gstart.data(), sizeof(int32_t) * gstart.size(), hipMemcpyHostToDevice, st), "work items");
+    HIPCHK(ctx, hipMemcpyAsync(b_cols, P.hcols.data(), n_cols, hipMemcpyHostToDevice, st), "cols");
+    HIPCHK(ctx, hipMemcpyAsync(b_order, order.data(), n_order, hipMemcpyHostToDevice, st), "order");
+    HIPCHK(ctx, hipMemcpyAsync(b_qb, qb.data(), n_qb, hipMemcpyHostToDevice, st), "queues");
+    HIPCHK(ctx, hipMemcpyAsync(b_gstart, gstart.data(), n_gstart, hipMemcpyHostToDevice, st), "work items");
     if (P.bisect)
-        HIPCHK(ctx, hipMemcpyAsync(ctx->amp_off.p, aoff.data(), sizeof(int64_t) * (ncols + 1), hipMemcpyHostToDevice, st), "amplitude offsets");
+        HIPCHK(ctx, hipMemcpyAsync(b_aoff, aoff.data(), n_aoff, hipMemcpyHostToDevice, st), "amplitude offsets");
     // the copies read pageable host vectors: finish them before those go away
     HIPCHK(ctx, hipStreamSynchronize(st), "upload");
 
-    J.cols = ctx->cols.as<int32_t>();
-    J.order = ctx->order.as<int32_t>();
-    P.qb_dev = ctx->qbounds.as<int32_t>();
+    J.cols = static_cast<int32_t *>(b_cols);
+    J.order = static_cast<int32_t *>(b_order);
+    P.qb_dev = static_cast<int32_t *>(b_qb);
     J.qbounds = P.qb_dev;
     J.c0 = P.ch_c0[0];
     J.cn = P.ch_cn[0];
-    J.gstart = ctx->gstart.as<int32_t>();
-    J.queue = ctx->ctl.as<int>();
-    J.fail = ctx->ctl.as<int>() + ma::kMaxQueues;
-    J.ws = P.kind == ma::kBasisOnchip ? nullptr : ctx->ws.as<double>();
-    J.mid = ctx->mid.as<double>();
-    J.eps = eps ? eps : ctx->eps.as<double>();
-    J.wts = wts ? wts : ctx->wts.as<double>();
-    J.amp = P.bisect ? ctx->amp.p : nullptr;
-    J.amp_off = P.bisect ? ctx->amp_off.as<int64_t>() : nullptr;
-    J.stats = col_stats ? col_stats : ctx->stats.as<int32_t>();
-    J.x0 = opts.start == MA_START_LEARNED ? ctx->x0.as<float>() : nullptr;
+    J.gstart = static_cast<int32_t *>(b_gstart);
+    P.ctl = static_cast<int *>(b_ctl);
+    J.queue = P.ctl;
+    J.fail = P.ctl + ma::kMaxQueues;
+    J.ws = P.kind == ma::kBasisOnchip ? nullptr : static_cast<double *>(b_ws);
+    J.mid = static_cast<double *>(b_mid);
+    J.eps = eps ? eps : static_cast<double *>(b_eps);
+    J.wts = wts ? wts : static_cast<double *>(b_wts);
+    J.amp = P.bisect ? b_amp : nullptr;
+    J.amp_off = P.bisect ? static_cast<int64_t *>(b_aoff) : nullptr;
+    J.stats = col_stats ? col_stats : static_cast<int32_t *>(b_stats);
+    P.feat = static_cast<float *>(b_feat);
+    P.x0 = static_cast<float *>(b_x0);
+    P.lohi = static_cast<double *>(b_lohi);
+    P.partial = static_cast<double *>(b_partial);
+    P.sums = static_cast<double *>(b_sums);
+    J.x0 = learned ? P.x0 : nullptr;
     J.sj_near = sj_near;
     J.direct = P.bisect ? 0 : 1;
     J.mu = P.bisect ? 0.0 : mu;
     J.kT = kT;
     J.rho = rho;
     J.pi = pi;
-    J.Ecol = ctx->Ecol.as<double>();
-    J.Ncol = ctx->Ncol.as<double>();
+    J.Ecol = static_cast<double *>(b_E);
+    J.Ncol = static_cast<double *>(b_N);
     return MA_OK;
 }
 
@@ -1173,14 +1295,14 @@ hipError_t enqueue_pre(ma_ctx *ctx, const Plan &P)
     hipStream_t st = ctx->work_stream();
     auto &N = ctx->net;
     hipError_t e = ma::launch_features(P.J.cols, P.J.ncols, ctx->o, ctx->geo.as<float>(),
-                                       ma::kGeoFeat, N.nf, ctx->feat.as<float>(), st);
+                                       ma::kGeoFeat, N.nf, P.feat, st);
     if (e != hipSuccess) return e;
     if ((e = net_refresh_bf16(ctx, st)) != hipSuccess) return e;
     const float *pr = N.params.as<float>();
-    return ma::launch_mlp_infer(ctx->feat.as<float>(), P.J.ncols, N.nf, N.nf_pad, N.nh, N.no,
+    return ma::launch_mlp_infer(P.feat, P.J.ncols, N.nf, N.nf_pad, N.nh, N.no,
                                 N.W1t.as<unsigned short>(), pr + N.ob1, N.W2t.as<unsigned short>(),
                                 pr + N.ob2, N.W3t.as<unsigned short>(), pr + N.ob3,
-                                ctx->x0.as<float>(), st);
+                                P.x0, st);
 }
 
 hipError_t enqueue_post(ma_ctx *ctx, const Plan &P)
@@ -1190,15 +1312,14 @@ hipError_t enqueue_post(ma_ctx *ctx, const Plan &P)
     const ma::DevJob &J = P.J;
     hipError_t e;
     if (P.bisect) {
-        if ((e = ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, P.kT, ctx->lohi.as<double>(),
-                                   ctx->partial.as<double>(), st)) != hipSuccess) return e;
+        if ((e = ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, P.kT, P.lohi, P.partial, st)) !=
+            hipSuccess) return e;
         if ((e = ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, J.nu, P.kT, P.n_target,
-                                   ctx->lohi.as<double>(), ctx->partial.as<double>(), st)) != hipSuccess) return e;
-        if ((e = ma::launch_rho(S, J, ctx->lohi.as<double>(), P.kT, P.rho, P.pi,
-                                ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), st)) != hipSuccess) return e;
+                                   P.lohi, P.partial, st)) != hipSuccess) return e;
+        if ((e = ma::launch_rho(S, J, P.lohi, P.kT, P.rho, P.pi, J.Ecol, J.Ncol, st)) != hipSuccess)
+            return e;
     }
-    return ma::launch_sum2(ctx->Ecol.as<double>(), ctx->Ncol.as<double>(), J.ncols,
-                           ctx->sums.as<double>(), st);
+    return ma::launch_sum2(J.Ecol, J.Ncol, J.ncols, P.sums, st);
 }
 
 hipError_t capture(ma_ctx *ctx, const Plan &P, hipError_t (*fn)(ma_ctx *, const Plan &),
@@ -1284,12 +1405,19 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         // starts when its basis kernel ends instead of queueing behind the
         // previous chunk's: nothing else runs then, and the two eigensolvers
         // write disjoint columns and ring slots.
-        while ((int)ctx->chunk_ev.size() < 6 * P.nchunks) {
+        if (!P.timed_chunks) {
+            // one stream, no per-chunk events (the allocation-free path)
+            for (int k = 0; k < P.nchunks; ++k) {
+                HIPCHK(ctx, enqueue_basis(ctx, P, k), "basis kernel");
+                HIPCHK(ctx, enqueue_eig(ctx, P, k, st), "eigensolver kernel");
+            }
+        }
+        while (P.timed_chunks && (int)ctx->chunk_ev.size() < 6 * P.nchunks) {
             hipEvent_t ev;
             HIPCHK(ctx, hipEventCreate(&ev), "event");
             ctx->chunk_ev.push_back(ev);
         }
-        for (int k = 0; k < P.nchunks; ++k) {
+        for (int k = 0; P.timed_chunks && k < P.nchunks; ++k) {
             hipEvent_t *ev = &ctx->chunk_ev[6 * k];
             const hipStream_t es = !P.pipelined ? st : (k > 0 && k == P.nchunks - 1) ? ctx->aux2 : ctx->aux;
             if (P.pipelined && k >= P.nbuf)
@@ -1313,9 +1441,9 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
     HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
     double sums[2] = {0, 0}, lohi[2] = {0, 0};
     int ctl[ma::kMaxQueues + 1];
-    HIPCHK(ctx, hipMemcpyAsync(sums, ctx->sums.p, sizeof sums, hipMemcpyDeviceToHost, st), "copy");
-    HIPCHK(ctx, hipMemcpyAsync(ctl, ctx->ctl.p, sizeof ctl, hipMemcpyDeviceToHost, st), "copy");
-    if (P.bisect) HIPCHK(ctx, hipMemcpyAsync(lohi, ctx->lohi.p, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipMemcpyAsync(sums, P.sums, sizeof sums, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipMemcpyAsync(ctl, P.ctl, sizeof ctl, hipMemcpyDeviceToHost, st), "copy");
+    if (P.bisect) HIPCHK(ctx, hipMemcpyAsync(lohi, P.lohi, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
     HIPCHK(ctx, hipStreamSynchronize(st), "solve");
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "elapsed");
     out->elapsed_ms = ms;
@@ -1325,7 +1453,7 @@ ma_status run_plan(ma_ctx *ctx, const Plan &P, ma_result *out)
         HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->evk1, ctx->eve1), "elapsed");
         eig_ms = ms;
     } else {
-        for (int k = 0; k < P.nchunks; ++k) {
+        for (int k = 0; P.timed_chunks && k < P.nchunks; ++k) {
             const hipEvent_t *ev = &ctx->chunk_ev[6 * k];
             HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]), "elapsed");
             basis_ms += ms;
@@ -1362,11 +1490,95 @@ MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *col
     if (!ctx) return MA_EINVAL;
     if (!out) return ctx->fail(MA_EINVAL, "null result");
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->last_valid = false;
     Plan P;
+    BufSource src;
+    if (ctx->user_ws) {
+        src.base = ctx->user_ws;
+        src.cap = ctx->user_ws_bytes;
+    }
     ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, opts_in, out->rho, out->pi, out->eps,
-                            out->wts, out->col_stats, out->sj_near, 0, -1, P);
+                            out->wts, out->col_stats, out->sj_near, 0, -1, P, &src);
     if (s != MA_OK) return s;
-    return run_plan(ctx, P, out);
+    s = run_plan(ctx, P, out);
+    if (s == MA_OK && P.bisect) {
+        ctx->last_valid = true;
+        ctx->lastS = P.S;
+        ctx->lastJ = P.J;
+        ctx->last_lohi = P.lohi;
+        ctx->last_partial = P.partial;
+        ctx->last_sums = P.sums;
+    }
+    return s;
+}
+
+MA_API ma_status ma_find_mu(ma_ctx *ctx, double n_target, double kT, double spin,
+                            ma_result *out)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!out) return ctx->fail(MA_EINVAL, "null result");
+    if (!ctx->last_valid)
+        return ctx->fail(MA_ESTATE, "no bisected solve to reuse (the last solve was given mu, "
+                         "failed, or was followed by a build or workspace change)");
+    if (!(kT > 0) || !std::isfinite(kT)) return ctx->fail(MA_EINVAL, "kT must be positive");
+    if (!std::isfinite(n_target)) return ctx->fail(MA_EINVAL, "n_target must be finite");
+    if (!std::isfinite(spin)) return ctx->fail(MA_EINVAL, "spin must be finite");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const ma::DevSystem &S = ctx->lastS;
+    const ma::DevJob &J = ctx->lastJ;
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, st), "event");
+    HIPCHK(ctx, ma::launch_minmax(J.eps, J.stats, J.ncols, J.nu, kT, ctx->last_lohi,
+                                  ctx->last_partial, st), "bracket");
+    HIPCHK(ctx, ma::launch_bisect(J.eps, J.wts, J.stats, J.ncols, J.nu, kT, n_target,
+                                  ctx->last_lohi, ctx->last_partial, st), "bisection");
+    HIPCHK(ctx, ma::launch_rho(S, J, ctx->last_lohi, kT, out->rho, out->pi, J.Ecol, J.Ncol, st),
+           "rho");
+    HIPCHK(ctx, ma::launch_sum2(J.Ecol, J.Ncol, J.ncols, ctx->last_sums, st), "sums");
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, st), "event");
+    double sums[2] = {0, 0}, lohi[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpyAsync(sums, ctx->last_sums, sizeof sums, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipMemcpyAsync(lohi, ctx->last_lohi, sizeof lohi, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(ctx, hipStreamSynchronize(st), "find_mu");
+    float ms = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "elapsed");
+    out->elapsed_ms = ms;
+    out->kernel_ms = 0.0;
+    out->eig_ms = 0.0;
+    out->energy = spin * sums[0];
+    out->n_elec = spin * sums[1];
+    out->mu = 0.5 * (lohi[0] + lohi[1]);
+    return MA_OK;
+}
+
+MA_API size_t ma_workspace_size(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
+                                int32_t q, double mu, const ma_opts *opts)
+{
+    if (!ctx) return 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return 0;
+    Plan P;
+    BufSource src;
+    src.size_only = true;
+    src.cap = SIZE_MAX;
+    if (make_plan(ctx, ncols, cols, p, q, mu, 1.0, opts, nullptr, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, 0, -1, P, &src) != MA_OK)
+        return 0;
+    return P.bytes;
+}
+
+MA_API ma_status ma_set_workspace(ma_ctx *ctx, void *device_ptr, size_t bytes)
+{
+    if (!ctx) return MA_EINVAL;
+    if ((device_ptr == nullptr) != (bytes == 0))
+        return ctx->fail(MA_EINVAL, "a workspace needs both a pointer and a size");
+    if (reinterpret_cast<uintptr_t>(device_ptr) % 256 != 0)
+        return ctx->fail(MA_EINVAL, "the workspace must be 256-byte aligned");
+    ctx->last_valid = false;
+    ctx->drop_graph();
+    ctx->user_ws = static_cast<char *>(device_ptr);
+    ctx->user_ws_bytes = bytes;
+    return MA_OK;
 }
 
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
@@ -1395,6 +1607,12 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     if (!out || reps < 1) return ctx->fail(MA_EINVAL, "null result or reps < 1");
     if (!std::isfinite(mu)) return ctx->fail(MA_EINVAL, "autotuning needs a finite mu");
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->last_valid = false;
+    BufSource src;
+    if (ctx->user_ws) {
+        src.base = ctx->user_ws;
+        src.cap = ctx->user_ws_bytes;
+    }
     ma_opts o;
     ma_default_opts(&o);
     if (opts_in) o = *opts_in;
@@ -1407,15 +1625,19 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
         o.basis_kernel = kern;
         // occupancy limit of this kernel and shape
         Plan P0;
+        BufSource sz;
+        sz.size_only = true;
+        sz.cap = SIZE_MAX;
         ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, 1 << 20, MA_SCHED_LPT, P0);
+                                nullptr, nullptr, nullptr, 1 << 20, MA_SCHED_LPT, P0, &sz);
         if (s != MA_OK) return s;
         const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
         for (int sched = 0; sched <= MA_SCHED_XCD_LPT; ++sched)
             for (int bpc = 1; bpc <= max_bpc && out->n_tried < 64; ++bpc) {
                 Plan P;
+                BufSource run = src;
                 s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
-                              nullptr, nullptr, bpc, sched, P);
+                              nullptr, nullptr, bpc, sched, P, &run);
                 if (s != MA_OK) return s;
                 double best = INFINITY;
                 for (int r = 0; r < reps; ++r) {

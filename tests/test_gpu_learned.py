@@ -142,6 +142,42 @@ def test_bf16_inference_close_to_fp32(env):
     assert rel < 3e-2
 
 
+def test_inference_matches_fp64_reference(env):
+    """Both inference paths against the FP64 reference network, element by
+    element.  BF16 rounds the weights and the layer inputs to 8 significant
+    bits (relative 2^-9 each); through three layers the error of output k is
+    bounded by a small multiple of that times the magnitude network
+    |x||W1| + |b1| -> |silu| -> ... evaluated with absolute values: 0.02 of
+    it is used.  The FP32 path is held to 1e-5 of the same magnitude."""
+    torch, ma, ctx, s = env
+    from oracle import mlp
+    sh = ctx.mlp_shape()
+    shape = (sh["n_in"], sh["n_hidden"], sh["n_out"])
+    cols = np.arange(0, s.M, 53, dtype=np.int32)
+    n = len(cols)
+    feat = torch.zeros(n * sh["n_in"], dtype=torch.float32, device="cuda")
+    ctx.column_features(cols, feat)
+    y16 = torch.zeros(n * sh["n_out"], dtype=torch.float32, device="cuda")
+    y32 = torch.zeros_like(y16)
+    ctx.mlp_forward(feat, n, y16, bf16=True)
+    ctx.mlp_forward(feat, n, y32, bf16=False)
+    x = feat.cpu().numpy().reshape(n, -1).astype(np.float64)
+    params = ctx.mlp_get_params().astype(np.float64)
+    ref = mlp.forward(params, x, shape)
+    ref = ref[0] if isinstance(ref, tuple) else ref
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(params, *shape)
+    m1 = np.abs(x) @ np.abs(W1) + np.abs(b1)
+    m2 = m1 @ np.abs(W2) + np.abs(b2)          # |silu(z)| <= |z|
+    scale = m2 @ np.abs(W3) + np.abs(b3)
+    a16 = y16.cpu().numpy().reshape(n, -1)
+    a32 = y32.cpu().numpy().reshape(n, -1)
+    r16 = float(np.max(np.abs(a16 - ref) / scale))
+    r32 = float(np.max(np.abs(a32 - ref) / scale))
+    _say(f"inference vs FP64 reference: bf16 {r16:.2e}, fp32 {r32:.2e} of the magnitude bound")
+    assert r16 <= 0.02
+    assert r32 <= 1e-5
+
+
 def test_learned_start_gives_same_result_and_fallback(env):
     torch, ma, ctx, s = env
     import oracle
