@@ -366,6 +366,29 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
                                int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of ma_solve_columns with every per-solve buffer (column lists, queues, the
+ * basis workspace of the persistent workgroups, the chunk buffer, Ritz data
+ * and amplitudes when not passed in *out, reduction scratch) carved from a
+ * static device scratch of 256 MiB that the library holds on each device it
+ * runs on until the process ends.  It calls no hipMalloc, hipFree or other
+ * allocating routine; the context's system (ma_build_system) must be built.
+ * The chunk buffer takes at most a quarter of the scratch (more chunks, one
+ * stream, no hipGraph) and the persistent workgroups are as many as the rest
+ * holds; a solve that does not fit (too many columns, too large a region or
+ * subspace) fails with MA_EINVAL before any launch.  Zero CG start only;
+ * sj_near must be NULL; kernel_ms and eig_ms are reported as 0.  Every call
+ * on a device shares that device's scratch, which keeps the last call's
+ * contents: calls that overlap on one device (several contexts or threads)
+ * race.  The Ritz data of a bisected call are not kept for ma_find_mu.
+ * Results equal those of ma_solve_columns to rounding.
+ * ------------------------------------------------------------------------ */
+MA_API ma_status ma_solve_columns_noalloc(ma_ctx *ctx, int64_t ncols, const int32_t *cols,
+                                          int32_t p, int32_t q, double mu, double kT,
+                                          const ma_opts *opts, ma_result *out);
+
 #ifdef __cplusplus
 }
 #endif

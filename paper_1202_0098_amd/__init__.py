@@ -30,7 +30,7 @@ API_FUNCTIONS = ("ma_version", "ma_default_opts", "ma_create", "ma_destroy", "ma
                  "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
                  "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
                  "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step", "ma_find_mu",
-                 "ma_workspace_size", "ma_set_workspace")
+                 "ma_workspace_size", "ma_set_workspace", "ma_solve_columns_noalloc")
 
 
 class MarnoldiError(RuntimeError):
@@ -141,6 +141,9 @@ def load_library():
     lib.ma_workspace_size.restype = ctypes.c_size_t
     lib.ma_set_workspace.argtypes = [P, P, ctypes.c_size_t]
     lib.ma_set_workspace.restype = ctypes.c_int
+    lib.ma_solve_columns_noalloc.argtypes = [P, i64, P, i32, i32, f64, f64,
+                                             ctypes.POINTER(_Opts), ctypes.POINTER(_Result)]
+    lib.ma_solve_columns_noalloc.restype = ctypes.c_int
     for name in ("ma_mlp_shape_of", "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params",
                  "ma_column_features", "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step"):
         getattr(lib, name).restype = ctypes.c_int
@@ -148,7 +151,7 @@ def load_library():
                  "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
                  "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
                  "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step", "ma_find_mu",
-                 "ma_set_workspace"):
+                 "ma_set_workspace", "ma_solve_columns_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -348,9 +351,11 @@ class Context:
         return loss.value
 
     def solve_columns(self, cols, p, q, mu=math.nan, kT=0.1, opts=None, rho=None, pi=None,
-                      eps=None, wts=None, col_stats=None, sj_near=None) -> SolveResult:
+                      eps=None, wts=None, col_stats=None, sj_near=None,
+                      noalloc=False) -> SolveResult:
         """Solve the listed columns (None = all).  rho/pi/eps/wts/col_stats are
-        optional torch device tensors (float64 / int32) written by the library."""
+        optional torch device tensors (float64 / int32) written by the library.
+        noalloc=True calls the allocation-free entry point."""
         if cols is None:
             cptr, n = None, 0
         else:
@@ -359,7 +364,8 @@ class Context:
         o = opts if opts is not None else default_opts()
         res = _Result(_ptr(rho), _ptr(pi), _ptr(eps), _ptr(wts), _ptr(col_stats), 0.0, 0.0, 0.0,
                       0.0, 0.0, _ptr(sj_near), 0.0)
-        self._check(self._lib.ma_solve_columns(self._h, n, cptr, int(p), int(q), float(mu), float(kT), ctypes.byref(o),
+        fn = self._lib.ma_solve_columns_noalloc if noalloc else self._lib.ma_solve_columns
+        self._check(fn(self._h, n, cptr, int(p), int(q), float(mu), float(kT), ctypes.byref(o),
                        ctypes.byref(res)))
         return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, res.kernel_ms,
                            res.eig_ms)

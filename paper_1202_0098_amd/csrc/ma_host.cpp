@@ -146,6 +146,9 @@ struct ma_ctx {
     // carved from it instead of the library's own allocations
     char *user_ws = nullptr;
     size_t user_ws_bytes = 0;
+    // allocation-free entry point: this device's static scratch
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
 
     // The last solve that bisected the chemical potential: its Ritz data and
     // amplitudes stay where that solve wrote them, for ma_find_mu, until the
@@ -468,7 +471,8 @@ MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
         hipEventCreateWithFlags(&c->evu, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking) != hipSuccess ||
+        ma::scratch_address(device, &c->scratch, &c->scratch_bytes) != hipSuccess) {
         delete c;
         return MA_EDEVICE;
     }
@@ -1579,6 +1583,38 @@ MA_API ma_status ma_set_workspace(ma_ctx *ctx, void *device_ptr, size_t bytes)
     ctx->user_ws = static_cast<char *>(device_ptr);
     ctx->user_ws_bytes = bytes;
     return MA_OK;
+}
+
+MA_API ma_status ma_solve_columns_noalloc(ma_ctx *ctx, int64_t ncols, const int32_t *cols,
+                                          int32_t p, int32_t q, double mu, double kT,
+                                          const ma_opts *opts_in, ma_result *out)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!out) return ctx->fail(MA_EINVAL, "null result");
+    if (!ctx->scratch) return ctx->fail(MA_ESTATE, "no scratch on this device");
+    ma_opts o;
+    ma_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    if (o.start != MA_START_ZERO)
+        return ctx->fail(MA_EINVAL, "the allocation-free solve supports the zero CG start only");
+    if (out->sj_near) return ctx->fail(MA_EINVAL, "the allocation-free solve does not write sj_near");
+    o.use_graph = 0;   // instantiating a graph allocates
+    o.pipeline = 0;    // one stream, chunks in sequence over one chunk buffer
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ctx->last_valid = false;
+    Plan P;
+    BufSource src;
+    src.base = static_cast<char *>(ctx->scratch);
+    src.cap = ctx->scratch_bytes;
+    src.limited = true;
+    ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, out->rho, out->pi, out->eps,
+                            out->wts, out->col_stats, nullptr, 0, -1, P, &src);
+    if (s != MA_OK) return s;
+    P.timed_chunks = false;
+    s = run_plan(ctx, P, out);
+    out->kernel_ms = 0.0;
+    out->eig_ms = 0.0;
+    return s;
 }
 
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,

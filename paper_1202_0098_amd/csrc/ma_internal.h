@@ -140,6 +140,12 @@ hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr,
                       double *rho, double *pi, double *Ecol, double *Ncol, hipStream_t st);
 hipError_t launch_sum2(const double *a, const double *b, int n, double *out, hipStream_t st);
 
+// Allocation-free solve: a static device scratch of kScratchBytes per device
+// (ma_noalloc.hip).  scratch_address returns this device's address of it; the
+// device must be current.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+hipError_t scratch_address(int device, void **ptr, size_t *bytes);
+
 // Start network (ma_mlp.hip).
 hipError_t launch_features(const int32_t *cols, int ncols, int o, const float *geo, int nf_geo,
                            int nf, float *feat, hipStream_t st);
