@@ -68,7 +68,8 @@ def main():
     ap.add_argument("--pipeline", type=int, default=-1,
                     help="chunks pipelining the eigensolver beside the basis kernel (library "
                          "default 4; 0 = one chunk, replayed as hipGraphs)")
-    ap.add_argument("--basis-kernel", default="auto", choices=["auto", "onchip", "workspace", "group"],
+    ap.add_argument("--basis-kernel", default="auto",
+                    choices=["auto", "onchip", "workspace", "group", "atom"],
                     help="basis kernel: on-chip basis (regions up to 512 orbitals) or workspace")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain device copy of MIB MiB five times "

@@ -70,8 +70,9 @@ typedef enum {
 
 enum { MA_REGION_ALL = 0, MA_REGION_RADIUS = 1, MA_REGION_NEAREST = 2 };
 enum { MA_PREC_FP64 = 0, MA_PREC_MIXED = 1, MA_PREC_MIXED_F64ACC = 2 };
-enum { MA_START_ZERO = 0, MA_START_LEARNED = 1 };
-enum { MA_BASIS_AUTO = 0, MA_BASIS_ONCHIP = 1, MA_BASIS_WORKSPACE = 2, MA_BASIS_GROUP = 3 };
+enum { MA_START_ZERO = 0, MA_START_LEARNED = 1, MA_START_PREVIOUS = 2 };
+enum { MA_BASIS_AUTO = 0, MA_BASIS_ONCHIP = 1, MA_BASIS_WORKSPACE = 2, MA_BASIS_GROUP = 3,
+       MA_BASIS_ATOM = 4 };
 
 /* The pencil and its geometry.  All pointers are host memory owned by the
  * caller; ma_build_system copies what it needs. */
@@ -106,14 +107,22 @@ typedef struct {
                                as MIXED, but the basis SpMVs read FP32 operator
                                values into FP64 vectors and accumulators. */
     double cg_tol;          /* stop when ||e_j - S_A s_j||_2 <= cg_tol (default 1e-12) */
-    double inner_tol;       /* mixed: relative residual of each FP32 CG pass (default 1e-6) */
+    double inner_tol;       /* mixed: relative residual of each FP32 CG pass (default 1e-6;
+                               a pass whose start residual is small stops once the
+                               residual is cg_tol / 10) */
     int32_t max_refine;     /* mixed: FP64 refinement rounds (default 8) */
     double breakdown_tau;   /* a basis candidate is dropped when its S-norm after
                                orthogonalisation is <= tau * its S-norm before (1e-10) */
     double spin;            /* spin degeneracy for energy and n_elec (default 2) */
     double n_target;        /* per-spin electron count sum_j N_j for the bisection
                                (used when mu is NaN; default: half of M) */
-    int32_t start;          /* MA_START_ZERO, or MA_START_LEARNED (needs a model) */
+    int32_t start;          /* MA_START_ZERO; MA_START_LEARNED (needs a model);
+                               MA_START_PREVIOUS: the s_j of the same column kept by an
+                               earlier solve with keep_sj (possibly of an earlier
+                               geometry of the same atoms, after ma_build_system),
+                               mapped onto the current region atom by atom (atoms that
+                               left the region are dropped, new ones start at zero);
+                               like the learned start, judged by the FP64 residual */
     int32_t slots_per_cu;   /* persistent workgroups per compute unit (0 = the
                                autotuned value for this (p, q, precision) if
                                ma_autotune ran, else the occupancy limit) */
@@ -131,8 +140,13 @@ typedef struct {
                                p + q <= 32, q <= 16; q <= 8 when p + q <= 16).
                                MA_BASIS_GROUP: the requested columns of one atom in
                                lockstep, one SpMM per step for all of them (o = 4 or
-                               9).  A forced kernel that cannot hold the shape is
-                               MA_EINVAL. */
+                               9).
+                               MA_BASIS_ATOM: the requested columns of one atom in
+                               lockstep, every operator pass one block SpMM over a
+                               staged set of their vectors, bases in a device
+                               workspace (o = 4 or 9; MA_PREC_FP64 and
+                               MA_PREC_MIXED_F64ACC).  A forced kernel that cannot
+                               hold the shape is MA_EINVAL. */
     int32_t chunk_columns;  /* columns per chunk of the processing order (0 = as many
                                as a 4 GiB chunk buffer holds); a solve of several
                                chunks launches eagerly instead of replaying graphs */
@@ -142,6 +156,10 @@ typedef struct {
                                caps the first), and the eigensolver of chunk k runs on
                                a second stream beside the later basis kernels, with a
                                ring of chunk buffers of at most 8 GiB (0 or 1: off) */
+    int32_t keep_sj;        /* 1: keep each solved column's s_j = S_A^-1 e_j (region
+                               vector, FP64, M * nmax doubles in all) for a later solve
+                               with MA_START_PREVIOUS; the kept set belongs to the
+                               geometry of the solve that wrote it (default 0) */
 } ma_opts;
 
 /* Schedules of the persistent column kernel.  LPT: one queue, columns with
@@ -163,7 +181,8 @@ typedef struct {
     int32_t *col_stats;     /* device, ncols*8: nu_eff, CG iterations, FP64
                                residual evaluations, status, start used (0 zero,
                                1 learned, 2 learned but rejected by the residual
-                               judge), 3 reserved */
+                               judge, 3 previous, 4 previous but rejected), 3
+                               reserved */
     double energy;          /* spin * sum_j E_j over the solved columns */
     double n_elec;          /* spin * sum_j N_j over the solved columns */
     double mu;              /* chemical potential used */
@@ -187,7 +206,7 @@ typedef struct {
     int32_t tried_slots[64];
     int32_t tried_schedule[64];
     double tried_ms[64];        /* whole-solve device time of each candidate (best of reps) */
-    int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE or MA_BASIS_GROUP */
+    int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP, _WORKSPACE, _GROUP or _ATOM */
     int32_t tried_kernel[64];
 } ma_tuning;
 
@@ -273,6 +292,40 @@ MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *col
  * buffers (or into a caller workspace), those must still hold them. */
 MA_API ma_status ma_find_mu(ma_ctx *ctx, double n_target, double kT, double spin,
                             ma_result *out);
+
+/* Atomic forces from the column outputs (Sec. 2: F_K as the sum over j of
+ * the partial sums F_K^(j), which involve rho_ij and pi_ij only at pattern
+ * elements):
+ *   F_K = -spin sum_j sum_i [rho_ij dH_ji/dR_K - pi_ij dS_ji/dR_K].
+ * dH, dS: device, nblk * 3 * o * o FP64 (block k, Cartesian direction d,
+ * then the o x o block row-major): the derivative of block k = (A, B) of H
+ * (resp. S) with respect to the position of its column atom B; its
+ * derivative with respect to R_A is taken as the negative (translation
+ * invariance), and the atom-diagonal blocks are not used.  rho, pi: device,
+ * nblk * o * o, the outputs of ma_solve_columns (every column whose pattern
+ * reaches an atom must have been solved for that atom's force).  forces:
+ * device, n_atoms * 3, written.  The overlap term enters with the sign of
+ * the derivative of the grand potential for S-normalised eigenvectors.
+ * All arrays are caller owned; MA_ESTATE before a build. */
+MA_API ma_status ma_forces(ma_ctx *ctx, const double *dH, const double *dS, const double *rho,
+                           const double *pi, double spin, double *forces);
+
+/* Density of states of the last solve's subspaces (the subspace Green's
+ * functions of Eqs. 11-12 traced with the overlap, Lorentzian broadening eta
+ * > 0): dos[k] = spin/pi sum_j sum_a w_a eta / ((E_k - eps_a)^2 + eta^2)
+ * with w_a = v_ja (S v_a)_j, over the columns of the last solve.  energies
+ * and dos: host, n_energies entries (caller owned).  MA_ESTATE if no solve
+ * has run since the last build (or the last one failed or was allocation-free). */
+MA_API ma_status ma_dos(ma_ctx *ctx, int64_t n_energies, const double *energies, double eta,
+                        double spin, double *dos);
+
+/* The subspace Green's function at complex energy z (Eq. 12) applied to e_j
+ * (Eq. 11), G_ij(z) = sum_a v_ia v_ja / (z - eps_a), at the pattern
+ * elements of every column of the last solve, which must have bisected mu
+ * (its amplitudes are reused; else MA_ESTATE).  g_re, g_im: device, nblk *
+ * o * o, the block-slot layout of rho (either may be NULL; only the solved
+ * columns' rows are written).  Im z must be nonzero. */
+MA_API ma_status ma_green(ma_ctx *ctx, double z_re, double z_im, double *g_re, double *g_im);
 
 /* Bytes of device workspace a solve with these arguments (the arguments of
  * ma_solve_columns; only whether mu is NaN matters) needs when the caller

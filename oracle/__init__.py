@@ -12,7 +12,10 @@ Split of the work:
   * this module (numpy): the real-space regions (Sec. 3), the Fermi-weighted
     density and energy-density matrices (Eqs. 13-14), the column energies
     (Eq. 17), the electron count Tr[rho S] and the bisection for the chemical
-    potential (Sec. 2, last paragraph before Eq. 19).
+    potential (Sec. 2, last paragraph before Eq. 19), the atomic forces from
+    the column outputs (Sec. 2, the force partial sums), and the subspace
+    Green's function at complex energies with the density of states
+    (Eqs. 11-12).
 
 Conventions shared with the library's interface (an interface, not code):
   * a column j is a global orbital index, atom(j) = j // o, orbital j % o;
@@ -305,3 +308,68 @@ def solve(sys, cols=None, mu=None, kT=None, spin=2.0, **kw):
     rho, pi, E, N = outputs(sys, raw, mu, kT)
     return dict(raw=raw, mu=mu, rho=rho, pi=pi, E=E, N=N,
                 energy=spin * float(np.sum(E)), n_elec=spin * float(np.sum(N)))
+
+
+# ---------------------------------------------------------------------------
+# atomic forces (Sec. 2: F_K as a sum of partial sums over the columns j)
+# ---------------------------------------------------------------------------
+
+def forces(sys, cols, rho, pi, dH, dS, spin=2.0):
+    """F_K = -spin sum_j sum_i [rho_ij dH_ji/dR_K - pi_ij dS_ji/dR_K].
+
+    rho, pi: per-column pattern slots as returned by :func:`outputs` (row c
+    belongs to column cols[c]); dH, dS: (nblk, 3, o, o), the derivative of
+    block k = (A, B) with respect to the position of its column atom B (its
+    derivative with respect to R_A is the negative).  H_ji with j = (A, r) and
+    i = (B, c) is element (r, c) of block (A, B), so column j contributes
+    -spin g to F_B and +spin g to F_A, where
+    g = sum_c [rho_ij dH_k[:, r, c] - pi_ij dS_k[:, r, c]].  The sign of the
+    overlap term is that of the derivative of the grand potential with
+    S-normalised eigenvectors (a reading: the paper prints both terms with
+    the same sign).  Returns (n_atoms, 3), summed over the listed columns.
+    """
+    o = sys.n_orb
+    F = np.zeros((sys.n_atoms, 3))
+    for c, j in enumerate(np.asarray(cols)):
+        A, r = divmod(int(j), o)
+        k0, k1 = int(sys.blk_ptr[A]), int(sys.blk_ptr[A + 1])
+        for kk in range(k1 - k0):
+            k = k0 + kk
+            B = int(sys.blk_col[k])
+            if B == A:
+                continue
+            rv = rho[c, kk * o:(kk + 1) * o]
+            pv = pi[c, kk * o:(kk + 1) * o]
+            g = dH[k][:, r, :] @ rv - dS[k][:, r, :] @ pv
+            F[B] -= spin * g
+            F[A] += spin * g
+    return F
+
+
+# ---------------------------------------------------------------------------
+# subspace Green's function at complex z and the density of states (Eqs. 11-12)
+# ---------------------------------------------------------------------------
+
+def green(sys, raw, z):
+    """G_ij(z) = sum_a v_ia v_ja / (z - eps_a) at the pattern slots of every
+    column (Eq. 12, the subspace Green's function applied to e_j, Eq. 11):
+    complex array (ncols, maxpat)."""
+    nu_eff = raw["nu_eff"]
+    eps = raw["eps"]
+    mask = np.arange(eps.shape[1])[None, :] < nu_eff[:, None]
+    w = np.where(mask, 1.0 / (z - np.where(mask, eps, 0.0)), 0.0)
+    return np.einsum("cta,ca->ct", raw["vpat"], w * raw["vj"])
+
+
+def dos(raw, energies, eta, spin=2.0):
+    """Density of states with Lorentzian broadening eta:
+    D(E) = -spin/pi Im sum_j sum_a w_a / (E + i eta - eps_a), w_a = v_ja (S v_a)_j,
+    the S-weighted trace of the subspace Green's functions (per column it
+    integrates to N_j at full occupation)."""
+    nu_eff = raw["nu_eff"]
+    eps = raw["eps"]
+    mask = np.arange(eps.shape[1])[None, :] < nu_eff[:, None]
+    e = eps[mask]
+    w = (raw["vj"] * raw["svj"])[mask]
+    E = np.asarray(energies, float)[:, None]
+    return spin / np.pi * np.sum(w[None, :] * eta / ((E - e[None, :]) ** 2 + eta * eta), axis=1)

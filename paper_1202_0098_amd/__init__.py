@@ -30,7 +30,8 @@ API_FUNCTIONS = ("ma_version", "ma_default_opts", "ma_create", "ma_destroy", "ma
                  "ma_solve_columns", "ma_autotune", "ma_set_tuning", "ma_mlp_shape_of",
                  "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params", "ma_column_features",
                  "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step", "ma_find_mu",
-                 "ma_workspace_size", "ma_set_workspace", "ma_solve_columns_noalloc")
+                 "ma_workspace_size", "ma_set_workspace", "ma_solve_columns_noalloc",
+                 "ma_forces", "ma_dos", "ma_green")
 
 
 class MarnoldiError(RuntimeError):
@@ -58,7 +59,8 @@ class _Opts(ctypes.Structure):
                 ("n_target", ctypes.c_double), ("start", ctypes.c_int32),
                 ("slots_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("basis_kernel", ctypes.c_int32),
-                ("chunk_columns", ctypes.c_int32), ("pipeline", ctypes.c_int32)]
+                ("chunk_columns", ctypes.c_int32), ("pipeline", ctypes.c_int32),
+                ("keep_sj", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -70,7 +72,7 @@ class _Tuning(ctypes.Structure):
 
 
 SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
-BASIS_KERNELS = {"auto": 0, "onchip": 1, "workspace": 2, "group": 3}
+BASIS_KERNELS = {"auto": 0, "onchip": 1, "workspace": 2, "group": 3, "atom": 4}
 
 
 class _Result(ctypes.Structure):
@@ -144,6 +146,12 @@ def load_library():
     lib.ma_solve_columns_noalloc.argtypes = [P, i64, P, i32, i32, f64, f64,
                                              ctypes.POINTER(_Opts), ctypes.POINTER(_Result)]
     lib.ma_solve_columns_noalloc.restype = ctypes.c_int
+    lib.ma_forces.argtypes = [P, P, P, P, P, f64, P]
+    lib.ma_forces.restype = ctypes.c_int
+    lib.ma_dos.argtypes = [P, i64, P, f64, f64, P]
+    lib.ma_dos.restype = ctypes.c_int
+    lib.ma_green.argtypes = [P, f64, f64, P, P]
+    lib.ma_green.restype = ctypes.c_int
     for name in ("ma_mlp_shape_of", "ma_mlp_init", "ma_mlp_set_params", "ma_mlp_get_params",
                  "ma_column_features", "ma_mlp_forward", "ma_mlp_loss_grad", "ma_mlp_train_step"):
         getattr(lib, name).restype = ctypes.c_int
@@ -170,7 +178,7 @@ def default_opts(**kw) -> _Opts:
         if k == "schedule" and isinstance(v, str):
             v = SCHEDULES[v]
         if k == "start" and isinstance(v, str):
-            v = {"zero": 0, "learned": 1}[v]
+            v = {"zero": 0, "learned": 1, "previous": 2}[v]
         if k == "basis_kernel" and isinstance(v, str):
             v = BASIS_KERNELS[v]
         setattr(o, k, v)
@@ -377,6 +385,24 @@ class Context:
         self._check(self._lib.ma_find_mu(self._h, float(n_target), float(kT), float(spin),
                                          ctypes.byref(res)))
         return SolveResult(res.energy, res.n_elec, res.mu, res.elapsed_ms, 0.0, 0.0)
+
+    def forces(self, dH, dS, rho, pi, forces, spin=2.0):
+        """Atomic forces (device tensors: dH, dS nblk*3*o*o, rho, pi nblk*o*o,
+        forces n_atoms*3)."""
+        self._check(self._lib.ma_forces(self._h, _ptr(dH), _ptr(dS), _ptr(rho), _ptr(pi),
+                                        float(spin), _ptr(forces)))
+
+    def dos(self, energies, eta, spin=2.0) -> np.ndarray:
+        """Density of states of the last solve at the given energies (host)."""
+        e = np.ascontiguousarray(energies, np.float64)
+        out = np.zeros_like(e)
+        self._check(self._lib.ma_dos(self._h, len(e), _ptr(e), float(eta), float(spin), _ptr(out)))
+        return out
+
+    def green(self, z, g_re=None, g_im=None):
+        """G_ij(z) at the pattern slots of the last (bisected) solve's columns."""
+        self._check(self._lib.ma_green(self._h, float(z.real), float(z.imag), _ptr(g_re),
+                                       _ptr(g_im)))
 
     def workspace_size(self, cols, p, q, mu=math.nan, opts=None) -> int:
         """Bytes of caller workspace a solve with these arguments needs."""

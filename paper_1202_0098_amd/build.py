@@ -14,8 +14,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmarnoldi.so")
-SOURCES = ["ma_basis_g9.hip", "ma_basis_g4.hip", "ma_basis_g0.hip", "ma_basis_s.hip",
-           "ma_basis_m.hip", "ma_kernels.hip", "ma_mlp.hip", "ma_noalloc.hip", "ma_host.cpp"]
+SOURCES = ["ma_atom.hip", "ma_basis_g9.hip", "ma_basis_g4.hip", "ma_basis_g0.hip", "ma_basis_s.hip",
+           "ma_basis_m.hip", "ma_kernels.hip", "ma_post.hip", "ma_mlp.hip", "ma_noalloc.hip", "ma_host.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

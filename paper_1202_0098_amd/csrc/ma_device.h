@@ -375,6 +375,15 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
         start = 1;
         __syncthreads();
     }
+    if (J.x0full) {
+        // a start on the whole region (the kept s_j of an earlier solve)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int i = tid + rr * NT;
+            if (i < n) x[rr] = J.x0full[(int64_t)c * S.nmax + i];
+        }
+        start = 3;
+    }
     if (PREC == 0) {
         double r[R], p[R], q[R];
         // r = e_j - S x
@@ -385,9 +394,9 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
         for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
         double rho2 = block_sum<NWV>(dot_rows<R, NT>(r, r, n), red);
         ++nres;
-        if (start == 1 && !(rho2 < 1.0)) {
-            // the residual judge rejects the predicted start: zero start
-            start = 2;
+        if ((start == 1 || start == 3) && !(rho2 < 1.0)) {
+            // the residual judge rejects the given start: zero start
+            start += 1;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 x[rr] = 0.0;
@@ -438,8 +447,8 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
             for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
             double rho2 = block_sum<NWV>(dot_rows<R, NT>(r64, r64, n), red);
             ++nres;
-            if (ref == 0 && start == 1 && !(rho2 < 1.0)) {
-                start = 2;
+            if (ref == 0 && (start == 1 || start == 3) && !(rho2 < 1.0)) {
+                start += 1;
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) {
                     x[rr] = 0.0;
@@ -463,7 +472,9 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
             for (int rr = 0; rr < R; ++rr)
                 if (tid + rr * NT < n) rrf += rf[rr] * rf[rr];
             rrf = block_sum<NWV>(rrf, redf);
-            const float thr = (float)J.inner_tol;
+            // relative target of the pass; no lower than what brings the
+            // absolute residual to a tenth of cg_tol
+            const float thr = (float)fmax(J.inner_tol, 0.1 * J.cg_tol / rho);
             for (int k = 0; k < n && sqrtf(rrf) > thr; ++k) {
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
@@ -496,6 +507,16 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
         }
     }
     if (status == 0 && !converged) status = -5;
+    if (J.sj_store && status == 0) {
+        // keep s_j for a later solve (MA_START_PREVIOUS)
+        const int64_t jg = J.cols[c];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int i = tid + rr * NT;
+            if (i < n) J.sj_store[jg * S.nmax + i] = x[rr];
+        }
+        if (tid == 0) J.sj_have[jg] = 1;
+    }
     if (J.sj_near) {
         // s_j on the orbitals of the kNbOut nearest atoms (training targets)
         __syncthreads();
@@ -1549,7 +1570,9 @@ __device__ void basis_group(const DevSystem &S, const DevJob &J, const SmemM &sm
             }, sm.scratch, gs);
 #pragma unroll
             for (int k = 0; k < B; ++k) rrf[k] = (float)gs[k];
-            const float thr = (float)J.inner_tol;
+            float thr[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) thr[k] = (float)fmax(J.inner_tol, 0.1 * J.cg_tol / rho[k]);
             int it[B];
 #pragma unroll
             for (int k = 0; k < B; ++k) it[k] = 0;
@@ -1558,7 +1581,7 @@ __device__ void basis_group(const DevSystem &S, const DevJob &J, const SmemM &sm
                 bool anyact = false;
 #pragma unroll
                 for (int k = 0; k < B; ++k) {
-                    act[k] = status[k] == 0 && !conv[k] && it[k] < n && sqrtf(rrf[k]) > thr;
+                    act[k] = status[k] == 0 && !conv[k] && it[k] < n && sqrtf(rrf[k]) > thr[k];
                     anyact |= act[k];
                 }
                 if (!anyact) break;
@@ -2902,5 +2925,6 @@ void *basis_g_kernel_o9(int R, int prec);
 void *basis_g_kernel_o0(int R, int prec);
 void *basis_s_kernel(int o, int nt, int nucap, int prec);
 void *basis_m_kernel(int o, int prec);
+void *basis_a_kernel(int o, int R, int prec);   // ma_atom.hip
 
 }  // namespace ma

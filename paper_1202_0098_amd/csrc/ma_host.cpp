@@ -112,6 +112,16 @@ struct ma_ctx {
     std::vector<int32_t> pat_blocks;        // host: blocks in each atom's block-row
 
     // device system
+    DevBuf blk_t;                     // per block (A, B): the index of block (B, A)
+    DevBuf reg_atoms;                 // the atoms of every region (ascending per region)
+    // kept s_j (opts.keep_sj) and the regions of the geometry they belong to
+    DevBuf sj_store, sj_have, sj_reg_id, sj_reg_off, sj_reg_len, sj_reg_atoms, x0full;
+    bool sj_valid = false;
+    uint64_t sj_gen = 0;
+    int sj_nmax = 0, sj_n_atoms = 0, sj_o = 0;
+    int64_t sj_nreg = 0, sj_natoms_total = 0;
+    int64_t nreg = 0, reg_atoms_total = 0;
+    DevBuf dos_E, dos_part, dos_out;  // density-of-states buffers
     DevBuf blk_ptr, blk_col, Hd, Sd, Hf, Sf, reg_id, reg_off, reg_len, lrp_off, lrp, lblk, jloc,
         blk_loc;
     bool have_geo = false;            // neighbour descriptors were built
@@ -153,7 +163,8 @@ struct ma_ctx {
     // The last solve that bisected the chemical potential: its Ritz data and
     // amplitudes stay where that solve wrote them, for ma_find_mu, until the
     // next solve, build or workspace change.
-    bool last_valid = false;
+    bool last_valid = false;   // amplitudes of a bisected solve (ma_find_mu, ma_green)
+    bool last_ritz = false;    // Ritz values and weights of the last solve (ma_dos)
     ma::DevSystem lastS{};
     ma::DevJob lastJ{};
     double *last_lohi = nullptr, *last_partial = nullptr, *last_sums = nullptr;
@@ -450,6 +461,7 @@ MA_API void ma_default_opts(ma_opts *o)
     o->basis_kernel = MA_BASIS_AUTO;
     o->chunk_columns = 0;
     o->pipeline = 4;
+    o->keep_sj = 0;
 }
 
 MA_API ma_status ma_create(ma_ctx **out, int32_t device, void *stream)
@@ -519,7 +531,7 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     if (!ctx) return MA_EINVAL;
     if (!sys || !reg) return ctx->fail(MA_EINVAL, "null system or region");
     ctx->built = false;
-    ctx->last_valid = false;
+    ctx->last_valid = ctx->last_ritz = false;
     ctx->drop_graph();
     ctx->generation++;
     const int n = sys->n_atoms, o = sys->n_orb;
@@ -726,6 +738,17 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
         });
     }
 
+    // transpose map of the block pattern: block (A, B) -> block (B, A)
+    std::vector<int32_t> h_blk_t(nblk);
+    parallel_for(n, [&](int64_t a0, int64_t a1, int) {
+        for (int64_t a = a0; a < a1; ++a)
+            for (int64_t k = bp[a]; k < bp[a + 1]; ++k) {
+                const int b = bc[k];
+                const int32_t *q = std::lower_bound(bc + bp[b], bc + bp[b + 1], (int32_t)a);
+                h_blk_t[k] = (int32_t)(q - bc);
+            }
+    });
+
     // ---- upload ----
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     std::vector<float> Hf(nblk * oo), Sf(nblk * oo);
@@ -760,6 +783,8 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     count_ = (int64_t)h_lblk.size(); UP(lblk, h_lblk.data(), "lblk")
     count_ = n;           UP(jloc, h_jloc.data(), "jloc")
     count_ = nblk;        UP(blk_loc, h_blk_loc.data(), "blk_loc")
+    count_ = nblk;        UP(blk_t, h_blk_t.data(), "blk_t")
+    count_ = (int64_t)h_reg_atoms.size(); UP(reg_atoms, h_reg_atoms.data(), "reg_atoms")
     if (have_geo) {
         count_ = (int64_t)h_geo.size();     UP(geo, h_geo.data(), "descriptors")
         count_ = (int64_t)h_out_loc.size(); UP(out_loc, h_out_loc.data(), "neighbours")
@@ -775,6 +800,8 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
     ctx->nmax = nmax;
     ctx->maxpat = maxpat;
     ctx->max_nat = max_nat;
+    ctx->nreg = nreg;
+    ctx->reg_atoms_total = (int64_t)h_reg_atoms.size();
     ctx->max_lnnz = 0;
     for (int r = 0; r < nreg; ++r) ctx->max_lnnz = std::max<int64_t>(ctx->max_lnnz, cnt[r + 1]);
     ctx->reg_len_of_atom.resize(n);
@@ -906,8 +933,14 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         return ctx->fail(MA_EINVAL, "unknown precision %d", opts.precision);
     if (!(opts.cg_tol > 0) || !(opts.breakdown_tau >= 0) || !(opts.inner_tol > 0) || opts.max_refine < 0)
         return ctx->fail(MA_EINVAL, "invalid tolerances");
-    if (opts.start != MA_START_ZERO && opts.start != MA_START_LEARNED)
+    if (opts.start != MA_START_ZERO && opts.start != MA_START_LEARNED &&
+        opts.start != MA_START_PREVIOUS)
         return ctx->fail(MA_EINVAL, "unknown start %d", opts.start);
+    if (opts.start == MA_START_PREVIOUS &&
+        !(ctx->sj_valid && ctx->sj_n_atoms == ctx->n_atoms && ctx->sj_o == ctx->o))
+        return ctx->fail(MA_EINVAL, "the previous start needs s_j kept (keep_sj) by a solve on "
+                         "the same atoms");
+    if (opts.keep_sj != 0 && opts.keep_sj != 1) return ctx->fail(MA_EINVAL, "keep_sj must be 0 or 1");
     if (opts.start == MA_START_LEARNED && !(ctx->net.ready && ctx->have_geo))
         return ctx->fail(MA_EINVAL, "learned start needs a start model and positions");
     if (opts.schedule < -1 || opts.schedule > MA_SCHED_XCD_LPT)
@@ -949,33 +982,47 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     J.inner_tol = opts.inner_tol;
     J.tau = opts.breakdown_tau;
     J.max_refine = opts.max_refine;
-    if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_GROUP)
+    if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_ATOM)
         return ctx->fail(MA_EINVAL, "unknown basis kernel %d", opts.basis_kernel);
     if (opts.chunk_columns < 0) return ctx->fail(MA_EINVAL, "chunk_columns must be >= 0");
     if (opts.pipeline < 0) return ctx->fail(MA_EINVAL, "pipeline must be >= 0");
     const bool fits = ma::basis_small_fits(ctx->nmax, P.nu, q, ctx->o);
     const bool gfits = ma::basis_group_fits(ctx->nmax, P.nu, ctx->o);
+    const bool afits = ma::basis_atom_fits(ctx->nmax, P.nu, ctx->o, opts.precision);
     if (opts.basis_kernel == MA_BASIS_ONCHIP && !fits)
         return ctx->fail(MA_EINVAL, "the on-chip basis kernel cannot hold regions of %d orbitals "
                          "with p = %d, q = %d", ctx->nmax, p, q);
     if (opts.basis_kernel == MA_BASIS_GROUP && !gfits)
         return ctx->fail(MA_EINVAL, "the atom-group basis kernel needs 4 or 9 orbitals per atom "
                          "and regions it can stage (o = %d, %d orbitals)", ctx->o, ctx->nmax);
+    if (opts.basis_kernel == MA_BASIS_ATOM && !afits)
+        return ctx->fail(MA_EINVAL, "the atom basis kernel needs 4 or 9 orbitals per atom, an "
+                         "FP64-vector precision mode and regions it can stage (o = %d, %d "
+                         "orbitals, precision %d)", ctx->o, ctx->nmax, opts.precision);
     // automatic choice: the autotuned kernel if there is one, else the
     // workspace kernel (the fastest untuned choice on every shape measured)
     int want_kernel = opts.basis_kernel;
     if (want_kernel == MA_BASIS_AUTO)
         want_kernel = tn && tn->kernel != MA_BASIS_AUTO ? tn->kernel : MA_BASIS_WORKSPACE;
-    if ((want_kernel == MA_BASIS_ONCHIP && !fits) || (want_kernel == MA_BASIS_GROUP && !gfits))
+    // the group kernel neither starts from nor keeps whole-region s_j
+    const bool sj_io = opts.start == MA_START_PREVIOUS || opts.keep_sj;
+    if (opts.basis_kernel == MA_BASIS_GROUP && sj_io)
+        return ctx->fail(MA_EINVAL, "the atom-group basis kernel does not keep or reuse s_j");
+    if ((want_kernel == MA_BASIS_ONCHIP && !fits) || (want_kernel == MA_BASIS_GROUP && !gfits) ||
+        (want_kernel == MA_BASIS_ATOM && !afits) || (want_kernel == MA_BASIS_GROUP && sj_io))
         want_kernel = MA_BASIS_WORKSPACE;
     P.kind = want_kernel == MA_BASIS_ONCHIP ? ma::kBasisOnchip
-             : want_kernel == MA_BASIS_GROUP ? ma::kBasisGroup : ma::kBasisWorkspace;
+             : want_kernel == MA_BASIS_GROUP ? ma::kBasisGroup
+             : want_kernel == MA_BASIS_ATOM ? ma::kBasisAtom : ma::kBasisWorkspace;
     const int o = ctx->o;
     J.lidx = P.kind == ma::kBasisWorkspace ? S.lidx
              : P.kind == ma::kBasisOnchip
                  ? (ma::onchip_lidx_fits(ctx->nmax, P.nu, ctx->max_nat, (int)ctx->max_lnnz) ? 1 : 0)
+             : P.kind == ma::kBasisAtom
+                 ? (ma::atom_lidx_fits(ctx->nmax, o, ctx->max_nat, (int)ctx->max_lnnz) ? 1 : 0)
                  : 0;
     J.ws_stride = P.kind == ma::kBasisOnchip ? 0
+                  : P.kind == ma::kBasisAtom ? ma::atom_ws_doubles(o, P.nu, q, ctx->nmax)
                   : (int64_t)(P.kind == ma::kBasisGroup ? ma::basis_group_width(o) : 1) *
                         (3 * P.nu + q) * ctx->nmax;
     int bpc = 0;
@@ -991,10 +1038,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     // Work items: single columns, or (atom-group kernel) the requested
     // columns of one atom.  items[w] lists the output rows of item w.
     std::vector<int32_t> item_start, item_cols;
-    if (P.kind == ma::kBasisGroup) {
+    if (P.kind == ma::kBasisGroup || P.kind == ma::kBasisAtom) {
         // the requested columns of each atom (atoms in order of first
         // appearance), cut into runs of at most the kernel's width
-        const int width = ma::basis_group_width(o);
+        const int width = P.kind == ma::kBasisAtom ? o : ma::basis_group_width(o);
         std::vector<int32_t> first(ctx->n_atoms, -1), count(ctx->n_atoms, 0);
         std::vector<int32_t> atoms;
         for (int64_t c = 0; c < ncols; ++c) {
@@ -1142,6 +1189,8 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
                  n_stats = col_stats ? 0 : sizeof(int32_t) * (size_t)ncols * ma::kStats,
                  n_feat = learned ? sizeof(float) * (size_t)ncols * ctx->net.nf : 0,
                  n_x0 = learned ? sizeof(float) * (size_t)ncols * ctx->net.no : 0,
+                 n_x0full = opts.start == MA_START_PREVIOUS
+                                ? sizeof(double) * (size_t)ncols * ctx->nmax : 0,
                  n_ctl = sizeof(int) * 16, n_lohi = sizeof(double) * 2,
                  n_partial = sizeof(double) * (ma::kCountBlocks * ma::kBisectTrials + 1),
                  n_E = sizeof(double) * ncols, n_sums = sizeof(double) * 2,
@@ -1149,7 +1198,8 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
                  slot_bytes = P.kind == ma::kBasisOnchip ? 0 : sizeof(double) * (size_t)J.ws_stride;
     void *b_cols, *b_order, *b_qb, *b_gstart, *b_ws = nullptr, *b_mid, *b_eps = nullptr,
          *b_wts = nullptr, *b_amp = nullptr, *b_aoff = nullptr, *b_stats = nullptr,
-         *b_feat = nullptr, *b_x0 = nullptr, *b_ctl, *b_lohi, *b_partial, *b_E, *b_N, *b_sums;
+         *b_feat = nullptr, *b_x0 = nullptr, *b_x0full = nullptr, *b_ctl, *b_lohi, *b_partial,
+         *b_E, *b_N, *b_sums;
     if (src->region()) {
         b_cols = src->take(n_cols);
         b_order = src->take(n_order);
@@ -1163,6 +1213,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         if (n_stats) b_stats = src->take(n_stats);
         if (n_feat) b_feat = src->take(n_feat);
         if (n_x0) b_x0 = src->take(n_x0);
+        if (n_x0full) b_x0full = src->take(n_x0full);
         b_ctl = src->take(n_ctl);
         b_lohi = src->take(n_lohi);
         b_partial = src->take(n_partial);
@@ -1201,6 +1252,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         if (n_stats) HIPCHK(ctx, ctx->stats.reserve(n_stats), "stats");
         if (n_feat) HIPCHK(ctx, ctx->feat.reserve(n_feat), "descriptors");
         if (n_x0) HIPCHK(ctx, ctx->x0.reserve(n_x0), "start vectors");
+        if (n_x0full) HIPCHK(ctx, ctx->x0full.reserve(n_x0full), "previous start vectors");
         HIPCHK(ctx, ctx->ctl.reserve(n_ctl), "ctl");
         HIPCHK(ctx, ctx->lohi.reserve(n_lohi), "lohi");
         HIPCHK(ctx, ctx->partial.reserve(n_partial), "partial");
@@ -1220,6 +1272,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         b_stats = n_stats ? ctx->stats.p : nullptr;
         b_feat = n_feat ? ctx->feat.p : nullptr;
         b_x0 = n_x0 ? ctx->x0.p : nullptr;
+        b_x0full = n_x0full ? ctx->x0full.p : nullptr;
         b_ctl = ctx->ctl.p;
         b_lohi = ctx->lohi.p;
         b_partial = ctx->partial.p;
@@ -1235,6 +1288,39 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     HIPCHK(ctx, hipMemcpyAsync(b_gstart, gstart.data(), n_gstart, hipMemcpyHostToDevice, st), "work items");
     if (P.bisect)
         HIPCHK(ctx, hipMemcpyAsync(b_aoff, aoff.data(), n_aoff, hipMemcpyHostToDevice, st), "amplitude offsets");
+    // start vectors from the kept s_j (mapped onto the current regions)
+    if (opts.start == MA_START_PREVIOUS) {
+        ma::RegionView cur{ctx->reg_id.as<int32_t>(), ctx->reg_len.as<int32_t>(),
+                           ctx->reg_atoms.as<int32_t>(), ctx->reg_off.as<int64_t>(), ctx->nmax};
+        ma::RegionView old{ctx->sj_reg_id.as<int32_t>(), ctx->sj_reg_len.as<int32_t>(),
+                           ctx->sj_reg_atoms.as<int32_t>(), ctx->sj_reg_off.as<int64_t>(),
+                           ctx->sj_nmax};
+        HIPCHK(ctx, ma::launch_map_sj((int)ncols, static_cast<int32_t *>(b_cols), o, cur, old,
+                                      ctx->sj_store.as<double>(), ctx->sj_have.as<int32_t>(),
+                                      static_cast<double *>(b_x0full), st), "previous start");
+    }
+    // s_j to keep: the store belongs to the current geometry (re-initialised
+    // after the mapping above has read the previous one)
+    if (opts.keep_sj && (!ctx->sj_valid || ctx->sj_gen != ctx->generation)) {
+        HIPCHK(ctx, hipStreamSynchronize(st), "previous start");
+        ctx->sj_valid = false;
+        HIPCHK(ctx, ctx->sj_store.reserve(sizeof(double) * (size_t)ctx->M * ctx->nmax), "kept s_j");
+        HIPCHK(ctx, ctx->sj_have.reserve(sizeof(int32_t) * (size_t)ctx->M), "kept s_j flags");
+        HIPCHK(ctx, ctx->sj_reg_id.reserve(sizeof(int32_t) * ctx->n_atoms), "kept regions");
+        HIPCHK(ctx, ctx->sj_reg_off.reserve(sizeof(int64_t) * (ctx->nreg + 1)), "kept regions");
+        HIPCHK(ctx, ctx->sj_reg_len.reserve(sizeof(int32_t) * ctx->nreg), "kept regions");
+        HIPCHK(ctx, ctx->sj_reg_atoms.reserve(sizeof(int32_t) * ctx->reg_atoms_total), "kept regions");
+        HIPCHK(ctx, hipMemsetAsync(ctx->sj_have.p, 0, sizeof(int32_t) * (size_t)ctx->M, st), "kept s_j flags");
+        HIPCHK(ctx, hipMemcpyAsync(ctx->sj_reg_id.p, ctx->reg_id.p, sizeof(int32_t) * ctx->n_atoms, hipMemcpyDeviceToDevice, st), "kept regions");
+        HIPCHK(ctx, hipMemcpyAsync(ctx->sj_reg_off.p, ctx->reg_off.p, sizeof(int64_t) * (ctx->nreg + 1), hipMemcpyDeviceToDevice, st), "kept regions");
+        HIPCHK(ctx, hipMemcpyAsync(ctx->sj_reg_len.p, ctx->reg_len.p, sizeof(int32_t) * ctx->nreg, hipMemcpyDeviceToDevice, st), "kept regions");
+        HIPCHK(ctx, hipMemcpyAsync(ctx->sj_reg_atoms.p, ctx->reg_atoms.p, sizeof(int32_t) * ctx->reg_atoms_total, hipMemcpyDeviceToDevice, st), "kept regions");
+        ctx->sj_gen = ctx->generation;
+        ctx->sj_nmax = ctx->nmax;
+        ctx->sj_n_atoms = ctx->n_atoms;
+        ctx->sj_o = ctx->o;
+        ctx->sj_valid = true;
+    }
     // the copies read pageable host vectors: finish them before those go away
     HIPCHK(ctx, hipStreamSynchronize(st), "upload");
 
@@ -1261,6 +1347,9 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     P.partial = static_cast<double *>(b_partial);
     P.sums = static_cast<double *>(b_sums);
     J.x0 = learned ? P.x0 : nullptr;
+    J.x0full = static_cast<double *>(b_x0full);
+    J.sj_store = opts.keep_sj ? ctx->sj_store.as<double>() : nullptr;
+    J.sj_have = opts.keep_sj ? ctx->sj_have.as<int32_t>() : nullptr;
     J.sj_near = sj_near;
     J.direct = P.bisect ? 0 : 1;
     J.mu = P.bisect ? 0.0 : mu;
@@ -1494,7 +1583,7 @@ MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *col
     if (!ctx) return MA_EINVAL;
     if (!out) return ctx->fail(MA_EINVAL, "null result");
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    ctx->last_valid = false;
+    ctx->last_valid = ctx->last_ritz = false;
     Plan P;
     BufSource src;
     if (ctx->user_ws) {
@@ -1505,6 +1594,11 @@ MA_API ma_status ma_solve_columns(ma_ctx *ctx, int64_t ncols, const int32_t *col
                             out->wts, out->col_stats, out->sj_near, 0, -1, P, &src);
     if (s != MA_OK) return s;
     s = run_plan(ctx, P, out);
+    if (s == MA_OK) {
+        ctx->last_ritz = true;
+        ctx->lastS = P.S;
+        ctx->lastJ = P.J;
+    }
     if (s == MA_OK && P.bisect) {
         ctx->last_valid = true;
         ctx->lastS = P.S;
@@ -1556,6 +1650,63 @@ MA_API ma_status ma_find_mu(ma_ctx *ctx, double n_target, double kT, double spin
     return MA_OK;
 }
 
+MA_API ma_status ma_forces(ma_ctx *ctx, const double *dH, const double *dS, const double *rho,
+                           const double *pi, double spin, double *forces)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->built) return ctx->fail(MA_ESTATE, "ma_build_system has not succeeded");
+    if (!dH || !dS || !rho || !pi || !forces) return ctx->fail(MA_EINVAL, "null array");
+    if (!std::isfinite(spin)) return ctx->fail(MA_EINVAL, "spin must be finite");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    HIPCHK(ctx, ma::launch_forces(ctx->n_atoms, ctx->o, ctx->blk_ptr.as<int64_t>(),
+                                  ctx->blk_col.as<int32_t>(), ctx->blk_t.as<int32_t>(), dH, dS, rho,
+                                  pi, spin, forces, st), "forces");
+    HIPCHK(ctx, hipStreamSynchronize(st), "forces");
+    return MA_OK;
+}
+
+MA_API ma_status ma_dos(ma_ctx *ctx, int64_t n_energies, const double *energies, double eta,
+                        double spin, double *dos)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->last_ritz) return ctx->fail(MA_ESTATE, "no solve whose Ritz data are kept");
+    if (n_energies < 1 || n_energies > INT_MAX || !energies || !dos)
+        return ctx->fail(MA_EINVAL, "need n_energies >= 1 and host arrays");
+    if (!(eta > 0) || !std::isfinite(eta) || !std::isfinite(spin))
+        return ctx->fail(MA_EINVAL, "eta must be positive");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const ma::DevJob &J = ctx->lastJ;
+    const int nE = (int)n_energies;
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    HIPCHK(ctx, ctx->dos_E.reserve(sizeof(double) * nE), "energies");
+    HIPCHK(ctx, ctx->dos_out.reserve(sizeof(double) * nE), "dos");
+    HIPCHK(ctx, ctx->dos_part.reserve(sizeof(double) * std::max<size_t>(1, ma::dos_partial_doubles(J.ncols, J.nu, nE))), "dos partials");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->dos_E.p, energies, sizeof(double) * nE, hipMemcpyHostToDevice, st), "energies");
+    HIPCHK(ctx, ma::launch_dos(J.eps, J.wts, J.stats, J.ncols, J.nu, ctx->dos_E.as<double>(), nE, eta,
+                               spin, ctx->dos_part.as<double>(), ctx->dos_out.as<double>(), st), "dos");
+    HIPCHK(ctx, hipMemcpyAsync(dos, ctx->dos_out.p, sizeof(double) * nE, hipMemcpyDeviceToHost, st), "dos");
+    HIPCHK(ctx, hipStreamSynchronize(st), "dos");
+    return MA_OK;
+}
+
+MA_API ma_status ma_green(ma_ctx *ctx, double z_re, double z_im, double *g_re, double *g_im)
+{
+    if (!ctx) return MA_EINVAL;
+    if (!ctx->last_valid)
+        return ctx->fail(MA_ESTATE, "no bisected solve whose amplitudes are kept");
+    if (!std::isfinite(z_re) || !std::isfinite(z_im) || z_im == 0.0)
+        return ctx->fail(MA_EINVAL, "z must be finite with a nonzero imaginary part");
+    HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->work_stream();
+    HIPCHK(ctx, ctx->after_caller(), "stream order");
+    HIPCHK(ctx, ma::launch_green(ctx->lastS, ctx->lastJ, z_re, z_im, g_re, g_im, st), "green");
+    HIPCHK(ctx, hipStreamSynchronize(st), "green");
+    return MA_OK;
+}
+
 MA_API size_t ma_workspace_size(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
                                 int32_t q, double mu, const ma_opts *opts)
 {
@@ -1578,7 +1729,7 @@ MA_API ma_status ma_set_workspace(ma_ctx *ctx, void *device_ptr, size_t bytes)
         return ctx->fail(MA_EINVAL, "a workspace needs both a pointer and a size");
     if (reinterpret_cast<uintptr_t>(device_ptr) % 256 != 0)
         return ctx->fail(MA_EINVAL, "the workspace must be 256-byte aligned");
-    ctx->last_valid = false;
+    ctx->last_valid = ctx->last_ritz = false;
     ctx->drop_graph();
     ctx->user_ws = static_cast<char *>(device_ptr);
     ctx->user_ws_bytes = bytes;
@@ -1598,10 +1749,11 @@ MA_API ma_status ma_solve_columns_noalloc(ma_ctx *ctx, int64_t ncols, const int3
     if (o.start != MA_START_ZERO)
         return ctx->fail(MA_EINVAL, "the allocation-free solve supports the zero CG start only");
     if (out->sj_near) return ctx->fail(MA_EINVAL, "the allocation-free solve does not write sj_near");
+    if (o.keep_sj) return ctx->fail(MA_EINVAL, "the allocation-free solve does not keep s_j");
     o.use_graph = 0;   // instantiating a graph allocates
     o.pipeline = 0;    // one stream, chunks in sequence over one chunk buffer
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    ctx->last_valid = false;
+    ctx->last_valid = ctx->last_ritz = false;
     Plan P;
     BufSource src;
     src.base = static_cast<char *>(ctx->scratch);
@@ -1622,7 +1774,7 @@ MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precis
 {
     if (!ctx) return MA_EINVAL;
     if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT ||
-        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_GROUP)
+        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_ATOM)
         return ctx->fail(MA_EINVAL, "invalid tuning");
     for (auto &t : ctx->tunes)
         if (t.p == p && t.q == q && t.prec == precision) {
@@ -1643,7 +1795,7 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     if (!out || reps < 1) return ctx->fail(MA_EINVAL, "null result or reps < 1");
     if (!std::isfinite(mu)) return ctx->fail(MA_EINVAL, "autotuning needs a finite mu");
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    ctx->last_valid = false;
+    ctx->last_valid = ctx->last_ritz = false;
     BufSource src;
     if (ctx->user_ws) {
         src.base = ctx->user_ws;
@@ -1652,12 +1804,14 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     ma_opts o;
     ma_default_opts(&o);
     if (opts_in) o = *opts_in;
+    o.keep_sj = 0;   // timing solves leave the kept s_j alone
     o.use_graph = 0;
     std::memset(out, 0, sizeof(*out));
     out->best_ms = INFINITY;
-    for (int kern = MA_BASIS_ONCHIP; kern <= MA_BASIS_GROUP; ++kern) {
+    for (int kern = MA_BASIS_ONCHIP; kern <= MA_BASIS_ATOM; ++kern) {
         if (kern == MA_BASIS_ONCHIP && !ma::basis_small_fits(ctx->nmax, p + q, q, ctx->o)) continue;
         if (kern == MA_BASIS_GROUP && !ma::basis_group_fits(ctx->nmax, p + q, ctx->o)) continue;
+        if (kern == MA_BASIS_ATOM && !ma::basis_atom_fits(ctx->nmax, p + q, ctx->o, o.precision)) continue;
         o.basis_kernel = kern;
         // occupancy limit of this kernel and shape
         Plan P0;

@@ -85,6 +85,10 @@ struct DevJob {
     int32_t *stats;            // ncols * kStats
     const float *x0;           // optional: predicted s_j on the kNbOut nearest atoms
                                // (ncols * kNbOut * o), else zero start
+    const double *x0full;      // optional: a start for s_j on the whole region (ncols *
+                               // nmax, local order), e.g. the previous geometry's s_j
+    double *sj_store;          // optional: s_j of global column j kept at j * nmax
+    int32_t *sj_have;          // with sj_store: 1 where column j's s_j was kept
     float *sj_near;            // optional output: converged s_j on the same orbitals
     // Given chemical potential: the eigensolver kernel applies the Fermi
     // weights and writes rho, pi (either may be null) and E_j, N_j.
@@ -112,9 +116,15 @@ constexpr int kStats = 8;      // nu_eff, CG iterations, FP64 residual evaluatio
 // for all of them, bases in the workspace.
 constexpr int kMaxQueues = 8;
 constexpr int kSmallRows = 512;
-enum { kBasisWorkspace = 0, kBasisOnchip = 1, kBasisGroup = 2 };
+enum { kBasisWorkspace = 0, kBasisOnchip = 1, kBasisGroup = 2, kBasisAtom = 3 };
 bool basis_small_fits(int nmax, int nu, int q, int o);
 bool basis_group_fits(int nmax, int nu, int o);
+// Atom kernel: the o columns of one atom in lockstep, every operator pass an
+// SpMM over one staged set (o = 4 or 9; FP64 and FP64-accumulation modes).
+bool basis_atom_fits(int nmax, int nu, int o, int precision);
+bool atom_lidx_fits(int nmax, int o, int max_nat, int max_lnnz);
+__host__ __device__ int64_t atom_slice_doubles(int nu, int q, int64_t ld);
+__host__ __device__ int64_t atom_ws_doubles(int o, int nu, int q, int64_t ld);
 int basis_group_width(int o);   // columns of one atom solved together
 size_t basis_smem_bytes(int nmax, int nu, int kind, int o);
 // whether the workspace (resp. on-chip) kernel keeps a region's local block
@@ -139,6 +149,27 @@ hipError_t launch_bisect(const double *eps, const double *wts, const int32_t *st
 hipError_t launch_rho(const DevSystem &S, const DevJob &J, const double *mu_ptr, double kT,
                       double *rho, double *pi, double *Ecol, double *Ncol, hipStream_t st);
 hipError_t launch_sum2(const double *a, const double *b, int n, double *out, hipStream_t st);
+
+// Forces, density of states and Green's function from a solve's outputs
+// (ma_post.hip).
+hipError_t launch_forces(int n_atoms, int o, const int64_t *blk_ptr, const int32_t *blk_col,
+                         const int32_t *blk_t, const double *dH, const double *dS,
+                         const double *rho, const double *pi, double spin, double *F,
+                         hipStream_t st);
+size_t dos_partial_doubles(int ncols, int nu, int nE);
+hipError_t launch_dos(const double *eps, const double *wts, const int32_t *stats, int ncols,
+                      int nu, const double *E, int nE, double eta, double spin, double *part,
+                      double *out, hipStream_t st);
+hipError_t launch_green(const DevSystem &S, const DevJob &J, double zr, double zi, double *gre,
+                        double *gim, hipStream_t st);
+// Map kept s_j (old regions) onto the current regions: x0full[c][i].
+struct RegionView {
+    const int32_t *reg_id, *reg_len, *reg_atoms;
+    const int64_t *reg_off;
+    int nmax;
+};
+hipError_t launch_map_sj(int ncols, const int32_t *cols, int o, RegionView cur, RegionView old,
+                         const double *store, const int32_t *have, double *x0full, hipStream_t st);
 
 // Allocation-free solve: a static device scratch of kScratchBytes per device
 // (ma_noalloc.hip).  scratch_address returns this device's address of it; the

@@ -56,6 +56,19 @@ void *group_kernel(int o, int nmax, int prec)
 
 int basis_group_width(int o) { return o == 9 ? 3 : o == 4 ? 4 : 0; }
 
+// LDS of the atom kernel besides the region index: one staged set of o
+// vectors (FP64) and the fixed shared state (column states, dot-sweep jobs,
+// reduction scratch; 8 KB bounds it)
+size_t atom_smem_bytes(int nmax, int o) { return sizeof(double) * (size_t)nmax * o; }
+constexpr size_t kAtomStaticLds = 8 * 1024;
+
+bool basis_atom_fits(int nmax, int nu, int o, int precision)
+{
+    (void)nu;
+    if (!(o == 4 || o == 9) || precision == 1) return false;
+    return atom_smem_bytes(nmax, o) + kAtomStaticLds <= 160 * 1024;
+}
+
 bool basis_group_fits(int nmax, int nu, int o)
 {
     if (!((o == 4 && nmax <= 512) || (o == 9 && nmax <= 1024))) return false;
@@ -90,6 +103,13 @@ bool onchip_lidx_fits(int nmax, int nu, int max_nat, int max_lnnz)
     return basis_smem_bytes(nmax, nu, kBasisOnchip, 0) + lidx_bytes(max_nat, max_lnnz) <= 160 * 1024;
 }
 
+// whether the atom kernel keeps the region index in LDS: only where two
+// workgroups still fit on a compute unit
+bool atom_lidx_fits(int nmax, int o, int max_nat, int max_lnnz)
+{
+    return atom_smem_bytes(nmax, o) + lidx_bytes(max_nat, max_lnnz) + kAtomStaticLds <= 80 * 1024;
+}
+
 bool global_lidx_fits(int nmax, int max_nat, int max_lnnz)
 {
     return sizeof(double) * (size_t)global_smem_doubles(nmax) + lidx_bytes(max_nat, max_lnnz) <=
@@ -106,6 +126,7 @@ size_t basis_smem_bytes(int nmax, int nu, int kind, int o)
                                                    : small_smem_doubles_fixed<512, 32>());
         return sizeof(double) * ((size_t)nu * nmax + 3 * (size_t)nmax + fixed);
     }
+    if (kind == kBasisAtom) return atom_smem_bytes(nmax, o);
     if (kind == kBasisGroup) {
         const int b = basis_group_width(o);
         return sizeof(double) * (2 * (size_t)b * nmax + 2 * (size_t)b * kMaxNu + (512 / 64) * 16);
@@ -132,6 +153,10 @@ hipError_t launch_basis(const DevSystem &S, const DevJob &J, int kind, int slots
         basis_fn k = (basis_fn)group_kernel(S.o, S.nmax, J.precision);
         return launch_with_smem(k, slots, 512, smem, st, S, J);
     }
+    if (kind == kBasisAtom) {
+        basis_fn k = (basis_fn)basis_a_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision);
+        return launch_with_smem(k, slots, 256, smem, st, S, J);
+    }
     basis_fn k = (basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision);
     return launch_with_smem(k, slots, NTG, smem, st, S, J);
 }
@@ -147,6 +172,9 @@ hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *b
     }
     if (kind == kBasisGroup)
         return occupancy_of((basis_fn)group_kernel(S.o, S.nmax, J.precision), 512, smem, bpc);
+    if (kind == kBasisAtom)
+        return occupancy_of((basis_fn)basis_a_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision),
+                            256, smem, bpc);
     return occupancy_of((basis_fn)global_kernel(S.o, basis_rows_per_thread(S.nmax), J.precision),
                         NTG, smem, bpc);
 }

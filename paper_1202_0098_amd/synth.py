@@ -160,12 +160,14 @@ def sk_blocks(dvec: np.ndarray, prm: dict) -> np.ndarray:
     Orbital order: s, x, y, z [, xy, yz, zx, x2-y2, 3z2-r2].  Row index is the
     orbital on the origin atom, column the orbital on the atom at +dvec.
     """
-    dist = np.linalg.norm(dvec, axis=1)
+    # written with analytic operations only, so that a complex bond vector
+    # gives the complex-step derivative (sk_block_derivs)
+    dist = np.sqrt(np.sum(dvec * dvec, axis=1))
     l, m, n = (dvec / dist[:, None]).T
     V = _bond_integrals(dist, prm)
     kind = prm["orbitals"]
     o = n_orbitals(kind)
-    E = np.zeros((len(dist), o, o))
+    E = np.zeros((len(dist), o, o), dtype=np.result_type(dvec.dtype, np.float64))
     # s-s, s-p, p-p
     E[:, 0, 0] = V["sss"]
     dc = (l, m, n)
@@ -238,6 +240,19 @@ def sk_blocks(dvec: np.ndarray, prm: dict) -> np.ndarray:
     return E
 
 
+def sk_block_derivs(dvec: np.ndarray, prm: dict) -> np.ndarray:
+    """d E_ab / d dvec_c for bond vectors dvec (n, 3) -> (n, 3, o, o), by
+    complex-step differentiation (Squire and Trapp, SIAM Rev. 40, 1998): the
+    imaginary part of E(dvec + i h e_c) / h, exact to rounding for h = 1e-30."""
+    h = 1e-30
+    out = []
+    for c in range(3):
+        dz = np.asarray(dvec, float).astype(complex)
+        dz[:, c] += 1j * h
+        out.append(sk_blocks(dz, prm).imag / h)
+    return np.stack(out, 1)
+
+
 def onsite_block(prm: dict) -> np.ndarray:
     kind = prm["orbitals"]
     e = prm["eps"]
@@ -277,6 +292,7 @@ class TBSystem:
     q: int = 8
     kT: float = 0.1
     seed: int = 0
+    params: Optional[dict] = None   # the generator parameters (for rebuilds and derivatives)
 
     @property
     def n_atoms(self) -> int:
@@ -345,7 +361,47 @@ def build_tb(pos: np.ndarray, box, prm: dict, name: str = "") -> TBSystem:
     np.add.at(blk_ptr, rows + 1, 1)
     blk_ptr = np.cumsum(blk_ptr)
     return TBSystem(pos=pos, box=box, n_orb=o, blk_ptr=blk_ptr,
-                    blk_col=cols.astype(np.int32), H=H, S=S, name=name)
+                    blk_col=cols.astype(np.int32), H=H, S=S, name=name, params=prm)
+
+
+def derivative_blocks(s: TBSystem):
+    """dH, dS of shape (nblk, 3, o, o): the derivative of block k = (A, B) with
+    respect to the position of its column atom B (zero on the atom-diagonal
+    blocks, which do not depend on the geometry); the derivative with respect
+    to R_A is its negative."""
+    prm = s.params
+    rows = np.repeat(np.arange(s.n_atoms), np.diff(s.blk_ptr))
+    off = rows != s.blk_col
+    d = min_image(s.pos[s.blk_col[off]] - s.pos[rows[off]], s.box)
+    o = s.n_orb
+    dH = np.zeros((s.nblk, 3, o, o))
+    dH[off] = sk_block_derivs(d, prm)
+    dS = prm["c_overlap"] * dH / prm["V_ref"]
+    return dH, dS
+
+
+def rebuild(s: TBSystem, pos: np.ndarray, name: str = "") -> TBSystem:
+    """The same workload (generator, regions, p, q, kT) at new positions; the
+    pattern is rebuilt from the cutoff."""
+    t = build_tb(pos, s.box, s.params, name or s.name)
+    t.region_mode, t.region_radius, t.region_nrp = s.region_mode, s.region_radius, s.region_nrp
+    t.p, t.q, t.kT, t.seed = s.p, s.q, s.kT, s.seed
+    return t
+
+
+def md_updates(s: TBSystem, n_steps: int, sigma: float, seed0: int):
+    """Successive geometry updates of an MD-style sequence: step k adds
+    i.i.d. N(0, sigma^2) displacements (seed seed0 + k) to the previous
+    positions and rebuilds the pattern."""
+    out = []
+    cur = s
+    for k in range(1, n_steps + 1):
+        rng = np.random.default_rng(seed0 + k)
+        pos = cur.pos + rng.normal(0, sigma, size=cur.pos.shape)
+        cur = rebuild(cur, pos, f"{s.name}_update{k}")
+        cur.seed = seed0 + k
+        out.append(cur)
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -87,7 +87,7 @@ def _compare(s, ora, cols, gpu, rho_tol, e_tol, mu_tol=1e-9):
     return d_rho, d_e
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
+@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group", "atom"])
 def test_fp64_diamond64_all_columns_bisected(ctx, torch_cuda, kernel):
     import oracle
     s = synth.config_diamond64()
@@ -108,14 +108,15 @@ def test_fp64_diamond64_all_columns_bisected(ctx, torch_cuda, kernel):
 def test_fp64_random_pencils(ctx, torch_cuda, n_atoms, o, seed, p, q):
     import oracle
     s = synth.random_pencil(n_atoms, o, seed=seed)
-    _say(f"pencil n={s.M} o={o} p={p} q={q}")
     ctx.build_tb(s)
-    gpu = _gpu_solve(ctx, torch_cuda, s, None, p, q, 0.2, 0.25)
     ora = oracle.solve(s, mu=0.2, kT=0.25, p=p, q=q)
-    _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
+    for kernel in ["auto"] + (["atom"] if o in (4, 9) else []):
+        _say(f"pencil n={s.M} o={o} p={p} q={q} ({kernel} basis)")
+        gpu = _gpu_solve(ctx, torch_cuda, s, None, p, q, 0.2, 0.25, basis_kernel=kernel)
+        _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
+@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group", "atom"])
 def test_fp64_q0_generalized_arnoldi(ctx, torch_cuda, kernel):
     """q = 0: the basis is K_p(H; e_j) alone, S-orthonormalised (the
     generalized Arnoldi variant of Sec. 2 without the dual vector); every
@@ -137,18 +138,19 @@ def test_fp64_q0_generalized_arnoldi(ctx, torch_cuda, kernel):
     _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-def test_fp64_breakdown_identity_overlap(ctx, torch_cuda):
+@pytest.mark.parametrize("kernel", ["workspace", "atom"])
+def test_fp64_breakdown_identity_overlap(ctx, torch_cuda, kernel):
     import oracle
     s = synth.random_pencil(6, 4, seed=31, s_scale=0.0)
-    _say("pencil S=I breakdown")
+    _say(f"pencil S=I breakdown ({kernel} basis)")
     ctx.build_tb(s)
-    gpu = _gpu_solve(ctx, torch_cuda, s, None, 6, 4, 0.0, 0.3)
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, 6, 4, 0.0, 0.3, basis_kernel=kernel)
     assert np.all(gpu[5][:, 0] == 6)
     ora = oracle.solve(s, mu=0.0, kT=0.3, p=6, q=4)
     _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
+@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group", "atom"])
 def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda, kernel):
     """Full-size 4,096-atom system, regions of 120 atoms (480 orbitals),
     p = q = 15, a seeded sample of columns spanning every orbital type."""
@@ -165,7 +167,8 @@ def test_fp64_diamond4096_sampled_columns(ctx, torch_cuda, kernel):
     _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
-def test_fp64_disordered_uneven_regions(ctx, torch_cuda):
+@pytest.mark.parametrize("kernel", ["workspace", "atom"])
+def test_fp64_disordered_uneven_regions(ctx, torch_cuda, kernel):
     """Disordered cell with per-atom region sizes 60..260 atoms (240..1,040
     orbitals), p = q = 20: the largest and smallest regions and a random
     sample."""
@@ -179,7 +182,7 @@ def test_fp64_disordered_uneven_regions(ctx, torch_cuda):
     cols = np.unique((atoms[:, None] * 4 + np.arange(4)[None, :]).ravel()).astype(np.int32)
     _say(f"disordered8000 fp64 {len(cols)} columns, regions {s.region_nrp[atoms].min()}.."
          f"{s.region_nrp[atoms].max()} atoms")
-    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.7, s.kT)
+    gpu = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, 0.7, s.kT, basis_kernel=kernel)
     ora = oracle.solve(s, cols=cols, mu=0.7)
     _compare(s, ora, cols, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
@@ -217,8 +220,10 @@ def _compare_mixed(s, raw, cols, gpu, mu_oracle, prec):
     assert d_pi <= MIXED_RHO_TOL[prec] * max(1.0, np.abs(pi_o).max())
 
 
-@pytest.mark.parametrize("kernel", ["onchip", "workspace", "group"])
-@pytest.mark.parametrize("prec", ["mixed", "mixed_f64acc"])
+@pytest.mark.parametrize("prec,kernel", [("mixed", "onchip"), ("mixed", "workspace"),
+                                         ("mixed", "group"), ("mixed_f64acc", "onchip"),
+                                         ("mixed_f64acc", "workspace"), ("mixed_f64acc", "group"),
+                                         ("mixed_f64acc", "atom")])
 def test_mixed_diamond64(ctx, torch_cuda, prec, kernel):
     import oracle
     s = synth.config_diamond64()
@@ -248,7 +253,7 @@ def test_given_mu_matches_bisected_path(ctx, torch_cuda):
     path of the bisection."""
     s = synth.config_diamond64()
     ctx.build_tb(s)
-    for kernel in ["onchip", "workspace", "group"]:
+    for kernel in ["onchip", "workspace", "group", "atom"]:
         _say(f"diamond64 bisected vs given mu ({kernel} basis)")
         a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
         b = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, a[0].mu, s.kT, basis_kernel=kernel)
@@ -265,7 +270,7 @@ def test_chunked_solve_matches_single_chunk(ctx, torch_cuda):
     s = synth.config_diamond4096()
     ctx.build_tb(s)
     cols = np.arange(0, s.M, 11, dtype=np.int32)
-    for kernel in ["onchip", "workspace", "group"]:
+    for kernel in ["onchip", "workspace", "group", "atom"]:
         _say(f"diamond4096 {len(cols)} columns, chunks of 97 vs one chunk ({kernel} basis)")
         a = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, math.nan, s.kT, basis_kernel=kernel)
         b = _gpu_solve(ctx, torch_cuda, s, cols, s.p, s.q, math.nan, s.kT, basis_kernel=kernel,
@@ -281,7 +286,7 @@ def test_pipelined_chunks_match_sequential(ctx, torch_cuda):
     bit for bit."""
     s = synth.config_diamond4096()
     ctx.build_tb(s)
-    for kernel in ["workspace", "group"]:
+    for kernel in ["workspace", "group", "atom"]:
         _say(f"diamond4096 all columns, pipelined vs sequential chunks ({kernel} basis)")
         a = _gpu_solve(ctx, torch_cuda, s, None, s.p, s.q, math.nan, s.kT, basis_kernel=kernel,
                        pipeline=4)
@@ -292,7 +297,7 @@ def test_pipelined_chunks_match_sequential(ctx, torch_cuda):
         assert np.array_equal(a[5], b[5])
 
 
-@pytest.mark.parametrize("other", ["onchip", "group"])
+@pytest.mark.parametrize("other", ["onchip", "group", "atom"])
 def test_basis_kernels_agree(ctx, torch_cuda, other):
     """The basis kernels (same method, different storage, grouping and
     reduction order) agree to rounding on a whole 4,096-atom solve."""
@@ -309,7 +314,7 @@ def test_basis_kernels_agree(ctx, torch_cuda, other):
     assert abs(a[0].energy - b[0].energy) <= 1e-12 * abs(a[0].energy)
 
 
-@pytest.mark.parametrize("kernel", ["workspace", "group"])
+@pytest.mark.parametrize("kernel", ["workspace", "group", "atom"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_f64acc"])
 def test_fcc_spd_regions(ctx, torch_cuda, prec, kernel):
     """spd fcc metal (9 orbitals per atom), regions of radius 7 A (about 83
@@ -348,6 +353,10 @@ def test_invalid_arguments_rejected(ctx, torch_cuda):
     with pytest.raises(ma.MarnoldiError):
         ctx.solve_columns(np.array([0], np.int32), 4, 4, mu=0.0, kT=0.1,
                           opts=ma.default_opts(basis_kernel=7))
+    with pytest.raises(ma.MarnoldiError) as ei:   # the atom kernel keeps FP64 vectors
+        ctx.solve_columns(np.array([0], np.int32), 4, 4, mu=0.0, kT=0.1,
+                          opts=ma.default_opts(basis_kernel="atom", precision="mixed"))
+    assert ei.value.status == ma.MA_EINVAL
     big = synth.config_disordered8000(3001)
     ctx.build_tb(big)
     for kern in ["onchip", "group"]:   # regions of up to 1,040 orbitals

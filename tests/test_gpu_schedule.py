@@ -92,7 +92,7 @@ def test_autotune_then_auto_solve(env):
     _say(f"autotune chose the {t['basis_kernel']} basis kernel, {t['slots_per_cu']} slots/CU, "
          f"schedule {t['schedule']}, {t['best_ms']:.2f} ms of {len(t['tried'])} candidates")
     assert t["slots_per_cu"] >= 1 and len(t["tried"]) >= 8
-    assert {k for _, _, _, k in t["tried"]} == {"onchip", "workspace", "group"}
+    assert {k for _, _, _, k in t["tried"]} == {"onchip", "workspace", "group", "atom"}
     assert t["best_ms"] == min(m for _, _, m, _ in t["tried"])
     res, rho = _run(torch, ma, ctx, s, cols, mu=0.9)
     ref, rho_ref = _run(torch, ma, ctx, s, cols, mu=0.9, schedule="lpt", slots_per_cu=1)
