@@ -77,6 +77,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="columns of the oracle CPU baseline sample (0 = skip, -1 = whole "
                          "workload up to 16,384 columns)")
+    ap.add_argument("--region-buckets", type=int, default=0, metavar="N",
+                    help="after the timed steps, solve the columns of N groups of atoms of "
+                         "ascending region size one group at a time (at the bisected mu) and "
+                         "report columns/s per group")
+    ap.add_argument("--updates", type=int, default=0, metavar="K",
+                    help="after the timed steps, K MD-style geometry updates (Gaussian steps "
+                         "of 0.02 A, pattern rebuilt), each solved from the zero start and "
+                         "from the s_j kept at the previous geometry")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -118,10 +126,14 @@ def main():
         log(f"fixed tuning {tuning}")
     elif not args.no_autotune:
         t0 = time.perf_counter()
-        # large systems: tune on a seeded sample of 65,536 columns
+        # large systems: tune on every column of a seeded sample of atoms
+        # (about 65,536 columns; whole atoms, as the atom-lockstep kernels
+        # process all columns of an atom together)
         tcols = None
         if s.M > 65536:
-            tcols = np.sort(np.random.default_rng(99).choice(s.M, 65536, replace=False)).astype(np.int32)
+            na = 65536 // o
+            atoms = np.sort(np.random.default_rng(99).choice(s.n_atoms, na, replace=False))
+            tcols = (atoms[:, None] * o + np.arange(o)).ravel().astype(np.int32)
         first = ctx.solve_columns(tcols, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
         log(f"first solve {first.elapsed_ms:.1f} ms (mu {first.mu:.6f}); autotuning")
         tuning = ctx.autotune(tcols, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
@@ -165,6 +177,12 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 5 launches of {args.copy_calib} MiB read + {args.copy_calib} MiB written")
         del a, b
+
+    buckets = region_buckets(ctx, s, opts, r.mu, args.region_buckets) \
+        if args.region_buckets > 0 else None
+    updates = geometry_updates(ctx, s, opts, args.updates) if args.updates > 0 else None
+    if updates is not None:
+        ctx.build_tb(s)
 
     # ---- roofline of the column kernel -------------------------------------
     k_ms = float(np.mean(kernel_ms))
@@ -235,7 +253,76 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if buckets is not None:
+        out["region_buckets"] = buckets
+    if updates is not None:
+        out["geometry_updates"] = updates
     print(json.dumps(out), flush=True)
+
+
+def region_buckets(ctx, s, opts, mu, nb, reps=3):
+    """Columns/s by region size: the atoms sorted by region size and cut
+    into nb groups of equal atom count; each group's columns solved alone
+    (mu given, the launch shape of the full solve), best of reps by device
+    time."""
+    import paper_1202_0098_amd as ma
+    o = s.n_orb
+    reg_atoms, _ = ctx.region_sizes(s.n_atoms)
+    order = np.argsort(reg_atoms, kind="stable")
+    out = []
+    for g in np.array_split(order, nb):
+        cols = (np.sort(g)[:, None] * o + np.arange(o)).ravel().astype(np.int32)
+        best = math.inf
+        for _ in range(reps):
+            r = ctx.solve_columns(cols, s.p, s.q, mu=mu, kT=s.kT, opts=opts)
+            best = min(best, r.elapsed_ms)
+        out.append({"region_atoms": [int(reg_atoms[g].min()), int(reg_atoms[g].max())],
+                    "mean_region_atoms": round(float(reg_atoms[g].mean()), 1),
+                    "columns": len(cols), "ms": round(best, 3),
+                    "columns_per_s": round(len(cols) / (best * 1e-3), 1)})
+        log(f"region bucket {out[-1]}")
+    return out
+
+
+def geometry_updates(ctx, s, opts, k_updates, sigma=0.02):
+    """k_updates MD-style updates of the workload (Gaussian steps of sigma,
+    seeds seed + k, pattern and regions rebuilt); each update is solved from
+    the zero start and from the s_j kept at the previous geometry.  Returns
+    per update: device ms, mean CG iterations and columns/s of both starts."""
+    import torch
+    import paper_1202_0098_amd as ma
+    from paper_1202_0098_amd import synth
+    o = s.n_orb
+    st = torch.zeros(s.M * ma.STATS, dtype=torch.int32, device="cuda")
+    keep = type(opts).from_buffer_copy(opts)
+    keep.keep_sj = 1
+    ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=keep)
+    out = []
+    cur = s
+    for k in range(1, k_updates + 1):
+        t0 = time.perf_counter()
+        cur = synth.md_updates(cur, 1, sigma, seed0=s.seed + k - 1)[0]
+        gen_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ctx.build_tb(cur)
+        build_s = time.perf_counter() - t0
+        rec = {"update": k, "seed": int(cur.seed), "generate_s": round(gen_s, 2),
+               "build_s": round(build_s, 3)}
+        for name, start in (("zero", 0), ("previous", 2)):
+            o2 = type(opts).from_buffer_copy(opts)
+            o2.start = start
+            o2.keep_sj = 1 if start == 2 else 0
+            r = ctx.solve_columns(None, cur.p, cur.q, mu=math.nan, kT=cur.kT, opts=o2,
+                                  col_stats=st)
+            torch.cuda.synchronize()
+            a = st.cpu().numpy().reshape(cur.M, ma.STATS)
+            rec[name] = {"ms": round(r.elapsed_ms, 2), "basis_ms": round(r.kernel_ms, 2),
+                         "cg_iters_mean": round(float(a[:, 1].mean()), 3),
+                         "columns_per_s": round(cur.M / (r.elapsed_ms * 1e-3), 1),
+                         "energy": r.energy, "mu": r.mu}
+        log(f"update {rec}")
+        out.append(rec)
+    return out
 
 
 def device_source_digest():
