@@ -9,8 +9,11 @@
 // of all o columns together, and every operator product is a block SpMM over
 // the o vectors of one staged set:
 //
-//   pass 1  H, S of the vectors finished in the previous step (-> H U, S U)
-//   pass 2  S of the pending vectors, and H of them while block 1 runs
+//   pass 1  H, S of the vectors finished in the previous step (-> H U, S U;
+//           FP64 values only: with FP32 values the images of a finished
+//           vector come from pass 2 over its pending form, see the loop)
+//   pass 2  S and H of the pending vectors (FP64 values: H only while
+//           block 1 runs)
 //   pass 3  H of the pending block-2 chain vectors
 //
 // The staged set lives in LDS as [row][column] (o doubles per row); a thread
@@ -36,11 +39,11 @@ __host__ __device__ int64_t atom_slice_doubles(int nu, int q, int64_t ld)
     return (d + 31) & ~(int64_t)31;
 }
 
-// doubles of one workgroup's workspace: o column slices and the two
-// interleaved SpMM result sets ([row][column], ld * o each)
+// doubles of one workgroup's workspace: o column slices and three SpMM
+// result sets (column-major, ld * o each)
 __host__ __device__ int64_t atom_ws_doubles(int o, int nu, int q, int64_t ld)
 {
-    return (int64_t)o * atom_slice_doubles(nu, q, ld) + 2 * ld * o;
+    return (int64_t)o * atom_slice_doubles(nu, q, ld) + 3 * ld * o;
 }
 
 namespace {
@@ -71,7 +74,8 @@ struct AState {
 // passes keep r, p, d in U as floats.  Basis: P the pending vector
 // (projected once), Z the pending chain vector, D the H image of the step's
 // candidate source.  After the o slices, the SpMM results of a pass,
-// interleaved [row][column]: RH (H x) and RS (S x).
+// column-major (column k at k * ld): RH (H x), RS (S x) and RH2 (H of the
+// chain vectors, so that RH keeps H of the pending vectors).
 struct Slices {
     double *base;
     int64_t cs, ld;
@@ -99,18 +103,19 @@ struct Slices {
     __device__ float *F(int k, int v) const { return reinterpret_cast<float *>(U(k)) + v * ld; }
 };
 
-// Sink of an SpMM pass: all columns' results of row i into the interleaved
+// Sink of an SpMM pass: all columns' results of row i into the column-major
 // result sets (one base pointer each, so no per-column addresses stay live
 // through the operator loop).
 template <int O, typename TX, bool DH, bool DS>
 struct ToRows {
     TX *rh, *rs;
+    int64_t ld;
     __device__ __forceinline__ void operator()(int i, const TX (&h)[O], const TX (&s)[O]) const
     {
 #pragma unroll
         for (int k = 0; k < O; ++k) {
-            if (DH) rh[i * O + k] = h[k];
-            if (DS) rs[i * O + k] = s[k];
+            if (DH) rh[k * ld + i] = h[k];
+            if (DS) rs[k * ld + i] = s[k];
         }
     }
 };
@@ -321,7 +326,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
     const int nu = J.nu, p = J.p, q = J.q;
     const int64_t ld = S.nmax;
     Slices W{ws, atom_slice_doubles(nu, q, ld), ld, nu, q};
-    double *RH = ws + O * W.cs, *RS = RH + ld * O;
+    double *RH = ws + O * W.cs, *RS = RH + ld * O, *RH2 = RS + ld * O;
     float *RSf = reinterpret_cast<float *>(RS);
     AState *st = sm.st;
     const int p0 = J.gstart[gpos];
@@ -398,14 +403,14 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
         stage_set<O, double, double>(xsd, n, mask, [&](int k) { return W.Z(k); });
         __syncthreads();
         spmm_set<O, double, double, false, true>(S, g, S.Hd, S.Sd, xsd,
-                                                 ToRows<O, double, false, true>{RH, RS});
+                                                 ToRows<O, double, false, true>{RH, RS, ld});
         __syncthreads();
         sum_cols<O>(mask, [&](int k) __attribute__((always_inline)) {
             double *D = W.D(k);
             const int jk = st[k].jl;
             double a = 0.0;
             for (int i = tid; i < n; i += NTA) {
-                const double r = (i == jk ? 1.0 : 0.0) - RS[i * O + k];
+                const double r = (i == jk ? 1.0 : 0.0) - RS[k * ld + i];
                 D[i] = r;
                 a += r * r;
             }
@@ -459,12 +464,12 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                 stage_set<O, double, double>(xsd, n, a2, [&](int k) { return W.P(k); });
                 __syncthreads();
                 spmm_set<O, double, double, false, true>(S, g, S.Hd, S.Sd, xsd,
-                                                         ToRows<O, double, false, true>{RH, RS});
+                                                         ToRows<O, double, false, true>{RH, RS, ld});
                 __syncthreads();
                 sum_cols<O>(a2, [&](int k) __attribute__((always_inline)) {
                     const double *P = W.P(k);
                     double a = 0.0;
-                    for (int i = tid; i < n; i += NTA) a += P[i] * RS[i * O + k];
+                    for (int i = tid; i < n; i += NTA) a += P[i] * RS[k * ld + i];
                     return a;
                 }, sm.scratch, sm.red);
                 if (tid < O && on(a2, tid)) {
@@ -485,7 +490,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                     double a = 0.0;
                     for (int i = tid; i < n; i += NTA) {
                         Z[i] += al * P[i];
-                        const double r = D[i] - al * RS[i * O + k];
+                        const double r = D[i] - al * RS[k * ld + i];
                         D[i] = r;
                         a += r * r;
                     }
@@ -593,12 +598,12 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                 stage_set<O, float, float>(xsf, n, a2, [&](int k) { return W.F(k, 1); });
                 __syncthreads();
                 spmm_set<O, float, float, false, true>(S, g, S.Hf, S.Sf, xsf,
-                                                       ToRows<O, float, false, true>{nullptr, RSf});
+                                                       ToRows<O, float, false, true>{nullptr, RSf, ld});
                 __syncthreads();
                 sum_cols<O>(a2, [&](int k) __attribute__((always_inline)) {
                     const float *pf = W.F(k, 1);
                     float acc = 0.0f;
-                    for (int i = tid; i < n; i += NTA) acc += pf[i] * RSf[i * O + k];
+                    for (int i = tid; i < n; i += NTA) acc += pf[i] * RSf[k * ld + i];
                     return (double)acc;
                 }, sm.scratch, sm.red);
                 if (tid < O && on(a2, tid)) {
@@ -619,7 +624,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                     float acc = 0.0f;
                     for (int i = tid; i < n; i += NTA) {
                         df[i] += al * pf[i];
-                        const float r = rf[i] - al * RSf[i * O + k];
+                        const float r = rf[i] - al * RSf[k * ld + i];
                         rf[i] = r;
                         acc += r * r;
                     }
@@ -713,6 +718,13 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
     }
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
+    // With FP32 operator values the images of a finished vector
+    // u = (p - U a) / beta are taken as S p / beta and H p / beta from the
+    // pass over its pending form p: the dropped (S U) a / beta and K a / beta
+    // are second-pass corrections, of the order of the first pass's loss of
+    // orthogonality (far below the FP32 rounding of S p itself), and pass 1
+    // disappears.  With FP64 values every image is applied to u itself.
+    constexpr bool DERIVE = PREC != 0;
     for (;;) {
         __syncthreads();
         if (tid < O) {
@@ -737,12 +749,12 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
         if (!go) break;
 
         // pass 1: H and S of the vectors finished in the previous step
-        if (fin) {
+        if (!DERIVE && fin) {
             stage_set<O, double, double>(xsd, n, fin,
                                          [&](int k) { return W.U(k) + (st[k].L - 1) * ld; });
             __syncthreads();
             spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd,
-                                                ToRows<O, double, true, true>{RH, RS});
+                                                ToRows<O, double, true, true>{RH, RS, ld});
             __syncthreads();
 #pragma unroll 1
             for (int k = 0; k < O; ++k) {
@@ -750,8 +762,8 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                 const int64_t off = (int64_t)(st[k].L - 1) * ld;
                 double *SUk = W.SU(k) + off, *Kk = W.K(k) + off;
                 for (int i = tid; i < n; i += NTA) {
-                    SUk[i] = RS[i * O + k];
-                    Kk[i] = RH[i * O + k];
+                    SUk[i] = RS[k * ld + i];
+                    Kk[i] = RH[k * ld + i];
                 }
             }
             __syncthreads();
@@ -760,32 +772,22 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
         // vector's images are stored
         if (tid < O && on(go, tid) && !on(rest, tid)) st[tid].has_fin = 0;
         if (!rest) continue;
-        // pass 2: S of the pending vectors (E), and H of them in block 1 (D)
+        // pass 2: S and H of the pending vectors (RS, RH; FP64 values: H only
+        // while block 1 runs)
         stage_set<O, double, double>(xsd, n, rest, [&](int k) { return W.P(k); });
         __syncthreads();
-        if (b1) spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS});
-        else spmm_set<O, TM, double, false, true>(S, g, Hv, Sv, xsd, ToRows<O, double, false, true>{RH, RS});
+        if (DERIVE || b1)
+            spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS, ld});
+        else
+            spmm_set<O, TM, double, false, true>(S, g, Hv, Sv, xsd, ToRows<O, double, false, true>{RH, RS, ld});
         __syncthreads();
-        // D of the block-1 columns: H of the pending vector
-#pragma unroll 1
-        for (int k = 0; k < O; ++k) {
-            if (!on(b1, k)) continue;
-            double *D = W.D(k);
-            for (int i = tid; i < n; i += NTA) D[i] = RH[i * O + k];
-        }
-        // pass 3: H of the pending chain vectors (D of the chain columns);
-        // RS keeps S of the pending vectors
+        // pass 3: H of the pending chain vectors into RH2 (RH keeps H of the
+        // pending vectors, RS their S)
         if (ch) {
             stage_set<O, double, double>(xsd, n, ch, [&](int k) { return W.Z(k); });
             __syncthreads();
-            spmm_set<O, TM, double, true, false>(S, g, Hv, Sv, xsd, ToRows<O, double, true, false>{RH, RS});
-            __syncthreads();
-#pragma unroll 1
-            for (int k = 0; k < O; ++k) {
-                if (!on(ch, k)) continue;
-                double *D = W.D(k);
-                for (int i = tid; i < n; i += NTA) D[i] = RH[i * O + k];
-            }
+            spmm_set<O, TM, double, true, false>(S, g, Hv, Sv, xsd,
+                                                 ToRows<O, double, true, false>{RH2, nullptr, ld});
         }
         __syncthreads();
         if (tid < O) {
@@ -799,13 +801,13 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             jb.V = W.SU(tid);
             jb.LV = La > Lb ? La : Lb;
             jb.x1 = W.P(tid);
-            jb.x2 = on(ch, tid) ? W.Z(tid) : W.D(tid);
+            jb.x2 = on(ch, tid) ? W.Z(tid) : RH + tid * ld;
             jb.o1 = W.CA(tid);
             jb.o2 = W.CB(tid, s.ping);
             jb.W = W.T(tid);
             jb.LW = on(ch, tid) ? s.kch : 0;
             jb.y1 = W.Z(tid);
-            jb.y2 = W.D(tid);
+            jb.y2 = RH2 + tid * ld;
             jb.p1 = W.CAT(tid);
             jb.p2 = W.CTB(tid, s.ping);
         }
@@ -817,16 +819,17 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
 #pragma unroll
             for (int k = 0; k < O; ++k) {
                 if (!on(rest, k)) continue;
-                const double *P = W.P(k), *Z = W.Z(k), *D = W.D(k);
+                const double *P = W.P(k), *Z = W.Z(k);
                 double x0 = 0.0, x1 = 0.0;
                 if (grp == 0) {
-                    const double *C = on(ch, k) ? Z : D;
+                    const double *C = on(ch, k) ? Z : RH + k * ld;
                     for (int i = tid; i < n; i += NTA) {
-                        const double e = RS[i * O + k];
+                        const double e = RS[k * ld + i];
                         x0 += P[i] * e;
                         x1 += e * C[i];
                     }
                 } else if (on(ch, k)) {
+                    const double *D = RH2 + k * ld;
                     for (int i = tid; i < n; i += NTA) {
                         const double z = Z[i];
                         x0 += z * z;
@@ -909,7 +912,10 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                        new_chain = s.new_chain, chain = s.kind == kChain;
             const double inv_b = s.inv_b, inv_e = s.inv_e, f = s.f, ft = s.ft, sc = s.sc;
             double *U = W.U(k), *T = W.T(k), *P = W.P(k), *Z = W.Z(k);
-            const double *D = W.D(k);
+            double *SUd = W.SU(k), *Kd = W.K(k);
+            // H image of the candidate source: H z (chain) or H of the pending vector
+            const double *D = (chain ? RH2 : RH) + k * ld;
+            const double *RSk = RS + k * ld, *RHk = RH + k * ld;
             double sa[R], sb[R], ta[R], tb[R];
             comb2_rows<R>(U, ld, (acc_u || new_pend) ? L : 0, W.CA(k), W.CB(k, s.ping), n, sa, sb);
             comb2_rows<R>(T, ld, acc_t ? kk : 0, W.CAT(k), W.CTB(k, s.ping), n, ta, tb);
@@ -924,7 +930,13 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                     const double t = (zt - ta[rr]) * inv_e;
                     const double nz = (hv - tb[rr] - ft * t) * inv_e;
                     if (acc_t) T[kk * ld + i] = t;
-                    if (acc_u) U[L * ld + i] = u;
+                    if (acc_u) {
+                        U[L * ld + i] = u;
+                        if (DERIVE) {
+                            SUd[L * ld + i] = RSk[i] * inv_b;
+                            Kd[L * ld + i] = RHk[i] * inv_b;
+                        }
+                    }
                     P[i] = new_pend ? nl : 0.0;
                     if (new_chain) Z[i] = nz;
                 }
@@ -950,7 +962,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             if (s.acc_u) ++s.L;
             s.cp_scale = s.sc;
             s.ctp_scale = s.inv_e;
-            s.has_fin = s.acc_u;
+            s.has_fin = DERIVE ? 0 : s.acc_u;
             s.has_pend = s.new_pend;
             s.ping ^= 1;
         }
