@@ -62,12 +62,13 @@ def main():
                     help="default: mixed_f64acc for the spd cells, fp64 otherwise")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default="",
-                    help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE[,BASIS_KERNEL]' instead of "
-                         "the autotuner")
+                    help="fixed launch shape 'SLOTS_PER_CU,SCHEDULE[,BASIS_KERNEL[,PIPELINE]]' "
+                         "instead of the autotuner")
     ap.add_argument("--no-graph", action="store_true", help="launch without hipGraph replay")
     ap.add_argument("--pipeline", type=int, default=-1,
-                    help="chunks pipelining the eigensolver beside the basis kernel (library "
-                         "default 4; 0 = one chunk, replayed as hipGraphs)")
+                    help="chunks pipelining the eigensolver beside the basis kernel (default: "
+                         "the autotuned choice, else 4; 0 = chunks in sequence, one chunk "
+                         "replayed as hipGraphs)")
     ap.add_argument("--basis-kernel", default="auto",
                     choices=["auto", "onchip", "workspace", "group", "atom"],
                     help="basis kernel: on-chip basis (regions up to 512 orbitals) or workspace")
@@ -119,10 +120,13 @@ def main():
         opts.pipeline = args.pipeline
     tuning = None
     if args.tuning:
-        slots, sched = args.tuning.split(",")[:2]
-        kern = args.tuning.split(",")[2] if args.tuning.count(",") >= 2 else args.basis_kernel
-        ctx.set_tuning(s.p, s.q, args.precision, int(slots), sched, kern)
-        tuning = {"slots_per_cu": int(slots), "schedule": sched, "basis_kernel": kern}
+        parts = args.tuning.split(",")
+        slots, sched = parts[:2]
+        kern = parts[2] if len(parts) >= 3 else args.basis_kernel
+        pipe = int(parts[3]) if len(parts) >= 4 else -1
+        ctx.set_tuning(s.p, s.q, args.precision, int(slots), sched, kern, pipe)
+        tuning = {"slots_per_cu": int(slots), "schedule": sched, "basis_kernel": kern,
+                  "pipeline": pipe}
         log(f"fixed tuning {tuning}")
     elif not args.no_autotune:
         t0 = time.perf_counter()
@@ -138,9 +142,9 @@ def main():
         log(f"first solve {first.elapsed_ms:.1f} ms (mu {first.mu:.6f}); autotuning")
         tuning = ctx.autotune(tcols, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
         log(f"autotune ({time.perf_counter() - t0:.1f}s): {tuning['basis_kernel']} basis kernel, "
-            f"{tuning['slots_per_cu']} slots/CU, schedule {tuning['schedule']}, "
-            f"{tuning['best_ms']:.2f} ms; tried "
-            f"{[(k, a, b, round(c, 2)) for a, b, c, k in tuning['tried']]}")
+            f"{tuning['slots_per_cu']} slots/CU, schedule {tuning['schedule']}, pipeline "
+            f"{tuning['pipeline']}, {tuning['best_ms']:.2f} ms; tried "
+            f"{[(k, a, b, pl, round(c, 2)) for (a, b, c, k), pl in zip(tuning['tried'], tuning['tried_pipeline'])]}")
 
     def step():
         return ctx.solve_columns(None, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts,
@@ -243,13 +247,12 @@ def main():
         "config": {"workload": s.name, "atoms": s.n_atoms, "columns": s.M, "p": s.p, "q": s.q,
                    "kT": s.kT, "mu": "bisected at half filling", "precision": args.precision,
                    "build_s": round(build_s, 3),
-                   "launch": ("eager, eigensolver pipelined beside the basis kernel"
-                              if opts.pipeline >= 2 and s.M >= opts.pipeline * 2048 else
-                              "eager" if args.no_graph else "hipGraph replay"),
+                   "launch": launch_form(opts, tuning, s.M, args.no_graph),
                    "basis_kernel": args.basis_kernel,
                    "tuning": None if tuning is None else {
                        "slots_per_cu": tuning["slots_per_cu"], "schedule": tuning["schedule"],
-                       "basis_kernel": tuning["basis_kernel"]}},
+                       "basis_kernel": tuning["basis_kernel"],
+                       "pipeline": tuning["pipeline"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -258,6 +261,18 @@ def main():
     if updates is not None:
         out["geometry_updates"] = updates
     print(json.dumps(out), flush=True)
+
+
+def launch_form(opts, tuning, ncols, no_graph):
+    """How the library launches a solve of ncols columns with these options
+    (the pipeline option: explicit, else the tuned one, else 4)."""
+    pipe = opts.pipeline if opts.pipeline >= 0 else (
+        tuning["pipeline"] if tuning is not None and tuning.get("pipeline", -1) >= 0 else 4)
+    if pipe >= 2 and ncols >= pipe * 2048:
+        return "eager, eigensolver pipelined beside the basis kernel"
+    if no_graph:
+        return "eager, chunks in sequence"
+    return "chunks in sequence on one stream (one chunk: hipGraph replay)"
 
 
 def region_buckets(ctx, s, opts, mu, nb, reps=3):

@@ -150,12 +150,14 @@ typedef struct {
     int32_t chunk_columns;  /* columns per chunk of the processing order (0 = as many
                                as a 4 GiB chunk buffer holds); a solve of several
                                chunks launches eagerly instead of replaying graphs */
-    int32_t pipeline;       /* >= 2 (default 4): a solve of at least 2048 * pipeline
-                               columns is cut into pipeline + 2 chunks of geometrically
-                               falling size (equal chunks where the 4 GiB chunk buffer
-                               caps the first), and the eigensolver of chunk k runs on
-                               a second stream beside the later basis kernels, with a
-                               ring of chunk buffers of at most 8 GiB (0 or 1: off) */
+    int32_t pipeline;       /* >= 2: a solve of at least 2048 * pipeline columns is cut
+                               into pipeline + 2 chunks of geometrically falling size
+                               (equal chunks where the 4 GiB chunk buffer caps the
+                               first), and the eigensolver of chunk k runs on a second
+                               stream beside the later basis kernels, with a ring of
+                               chunk buffers of at most 8 GiB; 0 or 1: off (chunks in
+                               sequence on one stream); -1 (default): the autotuned
+                               choice for (p, q, precision) if ma_autotune ran, else 4 */
     int32_t keep_sj;        /* 1: keep each solved column's s_j = S_A^-1 e_j (region
                                vector, FP64, M * nmax doubles in all) for a later solve
                                with MA_START_PREVIOUS; the kept set belongs to the
@@ -208,6 +210,8 @@ typedef struct {
     double tried_ms[64];        /* whole-solve device time of each candidate (best of reps) */
     int32_t basis_kernel;       /* chosen: MA_BASIS_ONCHIP, _WORKSPACE, _GROUP or _ATOM */
     int32_t tried_kernel[64];
+    int32_t pipeline;           /* chosen: the pipeline option of the solve (0 = off) */
+    int32_t tried_pipeline[64];
 } ma_tuning;
 
 /* Library version string (static storage). */
@@ -404,20 +408,23 @@ MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, 
 /* Autotuner of the launch (not part of the paper's method, which runs the
  * columns of Sec. 2 independently): time the solve on cols[0..ncols) (NULL = all) for every
  * candidate -- basis kernel (each one that can hold the shape) x
- * slots per CU from 1 to that kernel's occupancy limit x every schedule --
+ * slots per CU from 1 to that kernel's occupancy limit x every schedule, with
+ * the pipeline option of opts (-1: 4), and each kernel's fastest
+ * configuration again with pipelining off --
  * `reps` times each at chemical potential mu (finite), and keep the fastest
  * configuration for this (p, q, opts->precision) in the context; solves with
- * basis_kernel = MA_BASIS_AUTO, slots_per_cu = 0 and schedule = -1 then use
- * it.  Outputs (rho, pi) are not written. */
+ * basis_kernel = MA_BASIS_AUTO, slots_per_cu = 0, schedule = -1 and
+ * pipeline = -1 then use it.  Outputs (rho, pi) are not written. */
 MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,
                              int32_t q, double mu, double kT, const ma_opts *opts, int32_t reps,
                              ma_tuning *out);
 
 /* Store a previously found launch tuning for (p, q, precision) (e.g. from a cache);
- * basis_kernel is MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE or MA_BASIS_GROUP
- * (MA_BASIS_AUTO keeps the automatic choice). */
+ * basis_kernel is MA_BASIS_ONCHIP, MA_BASIS_WORKSPACE, MA_BASIS_GROUP or MA_BASIS_ATOM
+ * (MA_BASIS_AUTO keeps the automatic choice); pipeline as in ma_opts (-1: 4). */
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
-                               int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel);
+                               int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel,
+                               int32_t pipeline);
 
 /* ------------------------------------------------------------------------
  * For callers that cannot allocate device memory (code under hipGraph

@@ -68,7 +68,8 @@ class _Tuning(ctypes.Structure):
                 ("best_ms", ctypes.c_double), ("n_tried", ctypes.c_int32),
                 ("tried_slots", ctypes.c_int32 * 64), ("tried_schedule", ctypes.c_int32 * 64),
                 ("tried_ms", ctypes.c_double * 64), ("basis_kernel", ctypes.c_int32),
-                ("tried_kernel", ctypes.c_int32 * 64)]
+                ("tried_kernel", ctypes.c_int32 * 64), ("pipeline", ctypes.c_int32),
+                ("tried_pipeline", ctypes.c_int32 * 64)]
 
 
 SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
@@ -128,7 +129,7 @@ def load_library():
     lib.ma_region_atoms.restype = ctypes.c_int64
     lib.ma_autotune.argtypes = [P, i64, P, i32, i32, f64, f64, ctypes.POINTER(_Opts), i32,
                                 ctypes.POINTER(_Tuning)]
-    lib.ma_set_tuning.argtypes = [P, i32, i32, i32, i32, i32, i32]
+    lib.ma_set_tuning.argtypes = [P, i32, i32, i32, i32, i32, i32, i32]
     lib.ma_mlp_shape_of.argtypes = [P, ctypes.POINTER(_MlpShape)]
     lib.ma_mlp_init.argtypes = [P, ctypes.c_uint64]
     lib.ma_mlp_set_params.argtypes = [P, P, i64]
@@ -293,9 +294,11 @@ class Context:
         return ra, lb
 
     def autotune(self, cols, p, q, mu, kT, opts=None, reps=2):
-        """Search basis kernel x slots per CU x schedule on the whole solve's
-        device time; the best configuration is kept for (p, q, precision).
-        Returns a dict."""
+        """Search basis kernel x slots per CU x schedule (and pipelining on or
+        off) on the whole solve's device time; the best configuration is kept
+        for (p, q, precision).  Returns a dict; `tried` holds (slots,
+        schedule, ms, kernel) and `tried_pipeline` the pipeline option of
+        each."""
         if cols is None:
             cptr, n = None, 0
         else:
@@ -308,16 +311,18 @@ class Context:
         names = {v: k for k, v in SCHEDULES.items()}
         knames = {v: k for k, v in BASIS_KERNELS.items()}
         return dict(slots_per_cu=t.slots_per_cu, schedule=names[t.schedule], best_ms=t.best_ms,
-                    basis_kernel=knames[t.basis_kernel],
+                    basis_kernel=knames[t.basis_kernel], pipeline=t.pipeline,
                     tried=[(t.tried_slots[i], names[t.tried_schedule[i]], t.tried_ms[i],
-                            knames[t.tried_kernel[i]]) for i in range(t.n_tried)])
+                            knames[t.tried_kernel[i]]) for i in range(t.n_tried)],
+                    tried_pipeline=[t.tried_pipeline[i] for i in range(t.n_tried)])
 
-    def set_tuning(self, p, q, precision, slots_per_cu, schedule, basis_kernel="auto"):
+    def set_tuning(self, p, q, precision, slots_per_cu, schedule, basis_kernel="auto",
+                   pipeline=-1):
         prec = PREC[precision] if isinstance(precision, str) else int(precision)
         sch = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         kern = BASIS_KERNELS[basis_kernel] if isinstance(basis_kernel, str) else int(basis_kernel)
         self._check(self._lib.ma_set_tuning(self._h, int(p), int(q), prec, int(slots_per_cu), sch,
-                                            kern))
+                                            kern, int(pipeline)))
 
     # ---- learned CG start ----------------------------------------------------
     def mlp_shape(self):

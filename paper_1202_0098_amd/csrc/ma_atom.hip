@@ -120,6 +120,63 @@ struct ToRows {
     }
 };
 
+// Row-triple form of the SpMM for o = 9 with FP32 operator values: a thread
+// takes three rows of one atom, so each staged entry read from LDS serves
+// three rows, and a region of up to 85 atoms is one task per thread (the
+// row-pair form needs five tasks per atom, the last half empty).
+template <int O, typename TM, typename TX, bool DH, bool DS, typename F>
+__device__ __forceinline__ void spmm_set_t(const DevSystem &S, const Col &g, const TM *__restrict__ Hv,
+                                           const TM *__restrict__ Sv, const TX *xs, F &&sink)
+{
+    constexpr int RT = 3, G = O / RT;
+    static_assert(O % RT == 0, "rows split in triples");
+    const int ntask = g.n_at * G;
+    for (int t = threadIdx.x; t < ntask; t += NTA) {
+        const int a = t / G, r0 = (t - a * G) * RT;
+        TX h[RT][O], s[RT][O];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int k = 0; k < O; ++k) h[r][k] = s[r][k] = (TX)0;
+        int64_t kb0, kb1;
+        if (g.lidx) {
+            kb0 = g.srp[a];
+            kb1 = g.srp[a + 1];
+        } else {
+            kb0 = g.rp[a];
+            kb1 = g.rp[a + 1];
+        }
+        for (int64_t kb = kb0; kb < kb1; ++kb) {
+            const int2 e = g.lidx ? g.sblk[kb] : S.lblk[kb];
+            const int64_t base = (int64_t)e.y * (O * O) + r0 * O;
+            TM hv[RT][O], sv[RT][O];
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int c = 0; c < O; ++c) {
+                    if (DH) hv[r][c] = Hv[base + r * O + c];
+                    if (DS) sv[r][c] = Sv[base + r * O + c];
+                }
+            const TX *xr = xs + (int64_t)e.x * (O * O);
+#pragma unroll
+            for (int c = 0; c < O; ++c) {
+                TX xv[O];
+#pragma unroll
+                for (int k = 0; k < O; ++k) xv[k] = xr[c * O + k];
+#pragma unroll
+                for (int k = 0; k < O; ++k)
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) {
+                        if (DH) h[r][k] += (TX)hv[r][c] * xv[k];
+                        if (DS) s[r][k] += (TX)sv[r][c] * xv[k];
+                    }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r) sink(a * O + r0 + r, h[r], s[r]);
+    }
+}
+
 // y = M x for every column of the staged set xs (LDS [row][column], O
 // columns): H when DH, S when DS.  `sink(i, h, s)` receives row i's results.
 // With FP32 operator values, the next block's values are loaded while the
@@ -129,6 +186,10 @@ template <int O, typename TM, typename TX, bool DH, bool DS, typename F>
 __device__ __forceinline__ void spmm_set(const DevSystem &S, const Col &g, const TM *__restrict__ Hv,
                                          const TM *__restrict__ Sv, const TX *xs, F &&sink)
 {
+    if constexpr (O == 9 && sizeof(TM) == 4) {
+        spmm_set_t<O, TM, TX, DH, DS>(S, g, Hv, Sv, xs, sink);
+        return;
+    }
     constexpr int G = (O + 1) / 2;   // row pairs per atom
     const int ntask = g.n_at * G;
     for (int t = threadIdx.x; t < ntask; t += NTA) {
@@ -237,6 +298,10 @@ struct DotJob {
     const double *V, *W, *x1, *x2, *y1, *y2;
     double *o1, *o2, *p1, *p2;
     int LV, LW;
+    // one more vector after V (resp. W), or null: its dots with x1, x2
+    // (y1, y2) go to v1, v2 (w1, w2)
+    const double *Vx, *Wx;
+    double *v1, *v2, *w1, *w2;
 };
 
 template <int O>
@@ -301,6 +366,75 @@ __device__ __forceinline__ void dot_sweep_cols(const DotJob *jobs, int64_t ld, i
             const int m = m0 + (kk & 3);
             double *dst = (kk < 4) ? (first ? jb.o1 : jb.p1) : (first ? jb.o2 : jb.p2);
             if ((kk & 3) < nm) dst[m] = v[0];
+        }
+    }
+}
+
+// The same dots with whole vectors per lane: one wavefront per (column, part)
+// holds x1, x2 (rows lane + 64 r, r < RR) in registers, reads the basis
+// vectors VB at a time over all rows (one round trip per batch) and reduces
+// each batch across the wavefront; the extra vector (Vx, Wx) is the last of
+// the sequence.  Tasks: the V parts of the columns, then the W parts, so
+// that the heavier V parts spread over the wavefronts.
+template <int O, int RR>
+__device__ __forceinline__ void dot_sweep_rows(const DotJob *jobs, int64_t ld, int n)
+{
+    constexpr int VB = RR <= 8 ? 4 : 2;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int task = w; task < 2 * O; task += NWA) {
+        const bool first = task < O;
+        const int k = first ? task : task - O;
+        const DotJob &jb = jobs[k];
+        const int L = first ? jb.LV : jb.LW;
+        const double *Bx = first ? jb.Vx : jb.Wx;
+        const int cnt = L + (Bx ? 1 : 0);
+        if (cnt == 0) continue;
+        const double *B = first ? jb.V : jb.W;
+        const double *X1 = first ? jb.x1 : jb.y1;
+        const double *X2 = first ? jb.x2 : jb.y2;
+        double *D1 = first ? jb.o1 : jb.p1, *D2 = first ? jb.o2 : jb.p2;
+        double *E1 = first ? jb.v1 : jb.w1, *E2 = first ? jb.v2 : jb.w2;
+        double xv[RR], zv[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int i = lane + 64 * r;
+            const bool ok = i < n;
+            xv[r] = ok ? X1[ok ? i : 0] : 0.0;
+            zv[r] = ok ? X2[ok ? i : 0] : 0.0;
+        }
+        for (int m0 = 0; m0 < cnt; m0 += VB) {
+            double e[VB][RR];
+#pragma unroll
+            for (int j = 0; j < VB; ++j) {
+                const int m = m0 + j < cnt ? m0 + j : m0;
+                const double *v = m < L ? B + (int64_t)m * ld : Bx;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    const int i = lane + 64 * r;
+                    e[j][r] = v[i < n ? i : 0];   // rows past n meet zero x
+                }
+            }
+            double acc[2 * VB];
+#pragma unroll
+            for (int j = 0; j < VB; ++j) {
+                double a = 0.0, b = 0.0;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    a += e[j][r] * xv[r];
+                    b += e[j][r] * zv[r];
+                }
+                acc[j] = a;
+                acc[VB + j] = b;
+            }
+            wave_transpose_reduce<2 * VB>(acc);
+            if (tr_writer<2 * VB>(lane)) {
+                const int kk = tr_index<2 * VB>(lane);
+                const int m = m0 + (kk % VB);
+                if (m < cnt) {
+                    if (m < L) (kk < VB ? D1 : D2)[m] = acc[0];
+                    else *(kk < VB ? E1 : E2) = acc[0];
+                }
+            }
         }
     }
 }
@@ -810,39 +944,45 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             jb.y2 = RH2 + tid * ld;
             jb.p1 = W.CAT(tid);
             jb.p2 = W.CTB(tid, s.ping);
+            // and the scalars: pending^T S pending, (S pending)^T candidate
+            // (red[2k], red[2k + 1]); chain^T chain, chain^T (H chain)
+            // (red[32 + 2k], red[33 + 2k])
+            jb.Vx = r ? RS + tid * ld : nullptr;
+            jb.Wx = on(ch, tid) ? W.Z(tid) : nullptr;
+            jb.v1 = sm.red + 2 * tid;
+            jb.v2 = sm.red + 2 * tid + 1;
+            jb.w1 = sm.red + 32 + 2 * tid;
+            jb.w2 = sm.red + 33 + 2 * tid;
         }
-        // pending^T S pending, pending^T S candidate (red[2k], red[2k + 1]);
-        // chain^T chain, chain^T (H chain) (red[32 + 2k], red[33 + 2k])
-        block_reduce<NWA, 32, 2>([&](int grp, double (&v)[32]) __attribute__((always_inline)) {
+        __syncthreads();
+        // dots: a = (S U)^T pending, b = (S U)^T candidate; chain a_T, b_T;
+        // the four scalars
+        if constexpr (4 * R <= 16) {
+            dot_sweep_rows<O, 4 * R>(sm.jobs, ld, n);
+        } else {
+            // regions of more than 1,024 rows: the scalars by a workgroup
+            // reduction, then the dot sweep in tasks of four vectors
+            block_reduce<NWA, 32, 2>([&](int grp, double (&v)[32]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int k = 0; k < 32; ++k) v[k] = 0.0;
+                for (int k = 0; k < 32; ++k) v[k] = 0.0;
 #pragma unroll
-            for (int k = 0; k < O; ++k) {
-                if (!on(rest, k)) continue;
-                const double *P = W.P(k), *Z = W.Z(k);
-                double x0 = 0.0, x1 = 0.0;
-                if (grp == 0) {
-                    const double *C = on(ch, k) ? Z : RH + k * ld;
+                for (int k = 0; k < O; ++k) {
+                    const DotJob &jb = sm.jobs[k];
+                    const double *X = grp == 0 ? jb.Vx : jb.Wx;
+                    if (!X) continue;
+                    const double *A1 = grp == 0 ? jb.x1 : jb.y1, *A2 = grp == 0 ? jb.x2 : jb.y2;
+                    double x0 = 0.0, x1 = 0.0;
                     for (int i = tid; i < n; i += NTA) {
-                        const double e = RS[k * ld + i];
-                        x0 += P[i] * e;
-                        x1 += e * C[i];
+                        const double e = X[i];
+                        x0 += e * A1[i];
+                        x1 += e * A2[i];
                     }
-                } else if (on(ch, k)) {
-                    const double *D = RH2 + k * ld;
-                    for (int i = tid; i < n; i += NTA) {
-                        const double z = Z[i];
-                        x0 += z * z;
-                        x1 += z * D[i];
-                    }
+                    v[2 * k] = x0;
+                    v[2 * k + 1] = x1;
                 }
-                v[2 * k] = x0;
-                v[2 * k + 1] = x1;
-            }
-        }, sm.scratch, sm.red);   // ends with a barrier
-
-        // dots: a = (S U)^T pending, b = (S U)^T candidate; chain a_T, b_T
-        dot_sweep_cols<O>(sm.jobs, ld, n);
+            }, sm.scratch, sm.red);   // ends with a barrier
+            dot_sweep_cols<O>(sm.jobs, ld, n);
+        }
         __syncthreads();
 
         // decisions of column k, by thread k (the workspace kernel's rule)

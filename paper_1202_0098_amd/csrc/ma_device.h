@@ -694,7 +694,7 @@ __device__ __forceinline__ void dot_sweep(const double *__restrict__ V, int LV, 
 // products, so MB R loads are in flight; the last batch is padded with
 // copies of its first vector at coefficient zero, so every batch is one round
 // trip (the sums are the same, term by term, as without the padding).
-template <int R>
+template <int R, int MB = 4>
 __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t ld, int cnt,
                                            const double *c1, const double *c2, int n,
                                            double (&s1)[R], double (&s2)[R])
@@ -707,7 +707,8 @@ __device__ __forceinline__ void comb2_rows(const double *__restrict__ V, int64_t
         s1[rr] = 0.0;
         s2[rr] = 0.0;
     }
-    constexpr int MB = 4;   // vectors per batch
+    // MB vectors per batch: their loads are issued together (the last batch
+    // is padded at coefficient zero, so every batch is one round trip)
     for (int m = 0; m < cnt; m += MB) {
         double v[MB][R];
 #pragma unroll

@@ -170,7 +170,7 @@ struct ma_ctx {
     double *last_lohi = nullptr, *last_partial = nullptr, *last_sums = nullptr;
 
     // autotuned (slots per CU, schedule) per (p, q, precision)
-    struct Tune { int p, q, prec, slots, sched, kernel; };
+    struct Tune { int p, q, prec, slots, sched, kernel, pipe; };
     std::vector<Tune> tunes;
     const Tune *find_tune(int p, int q, int prec) const
     {
@@ -460,7 +460,7 @@ MA_API void ma_default_opts(ma_opts *o)
     o->use_graph = 1;
     o->basis_kernel = MA_BASIS_AUTO;
     o->chunk_columns = 0;
-    o->pipeline = 4;
+    o->pipeline = -1;
     o->keep_sj = 0;
 }
 
@@ -968,6 +968,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     const ma_ctx::Tune *tn = ctx->find_tune(p, q, opts.precision);
     P.sched = sched_override >= 0 ? sched_override
               : opts.schedule >= 0 ? opts.schedule : (tn ? tn->sched : MA_SCHED_LPT);
+    const int pipe = opts.pipeline >= 0 ? opts.pipeline : (tn && tn->pipe >= 0 ? tn->pipe : 4);
 
     ma::DevSystem &S = P.S;
     ma::DevJob &J = P.J;
@@ -985,7 +986,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     if (opts.basis_kernel < MA_BASIS_AUTO || opts.basis_kernel > MA_BASIS_ATOM)
         return ctx->fail(MA_EINVAL, "unknown basis kernel %d", opts.basis_kernel);
     if (opts.chunk_columns < 0) return ctx->fail(MA_EINVAL, "chunk_columns must be >= 0");
-    if (opts.pipeline < 0) return ctx->fail(MA_EINVAL, "pipeline must be >= 0");
+    if (opts.pipeline < -1) return ctx->fail(MA_EINVAL, "pipeline must be >= -1");
     const bool fits = ma::basis_small_fits(ctx->nmax, P.nu, q, ctx->o);
     const bool gfits = ma::basis_group_fits(ctx->nmax, P.nu, ctx->o);
     const bool afits = ma::basis_atom_fits(ctx->nmax, P.nu, ctx->o, opts.precision);
@@ -1085,8 +1086,8 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     // and the last one, which nothing overlaps, is short; equal chunks where
     // the chunk buffer caps the first
     std::vector<int64_t> target;   // column target per chunk
-    if (opts.pipeline >= 2 && ncols >= (int64_t)opts.pipeline * 2048) {
-        const int nch = opts.pipeline + 2;
+    if (pipe >= 2 && ncols >= (int64_t)pipe * 2048) {
+        const int nch = pipe + 2;
         const double r = 0.75;
         double norm = 0.0;
         for (int k = 0; k < nch; ++k) norm += std::pow(r, k);
@@ -1094,7 +1095,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
             target.push_back(std::max<int64_t>(1, std::llround((double)ncols * std::pow(r, k) / norm)));
         if (target[0] > budget) {
             target.clear();
-            budget = std::min<int64_t>(budget, (ncols + opts.pipeline - 1) / opts.pipeline);
+            budget = std::min<int64_t>(budget, (ncols + pipe - 1) / pipe);
         }
     }
     std::vector<int32_t> ch_item0;   // first work item of each chunk
@@ -1112,7 +1113,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         ch_item0.push_back(nitems);
     }
     P.nchunks = (int)ch_item0.size() - 1;
-    P.pipelined = opts.pipeline >= 2 && P.nchunks >= 2;
+    P.pipelined = pipe >= 2 && P.nchunks >= 2;
 
     // processing order of the work items, per chunk and queue
     std::vector<int32_t> witem(nitems);
@@ -1770,20 +1771,22 @@ MA_API ma_status ma_solve_columns_noalloc(ma_ctx *ctx, int64_t ncols, const int3
 }
 
 MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precision,
-                               int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel)
+                               int32_t slots_per_cu, int32_t schedule, int32_t basis_kernel,
+                               int32_t pipeline)
 {
     if (!ctx) return MA_EINVAL;
     if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT ||
-        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_ATOM)
+        basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_ATOM || pipeline < -1)
         return ctx->fail(MA_EINVAL, "invalid tuning");
     for (auto &t : ctx->tunes)
         if (t.p == p && t.q == q && t.prec == precision) {
             t.slots = slots_per_cu;
             t.sched = schedule;
             t.kernel = basis_kernel;
+            t.pipe = pipeline;
             return MA_OK;
         }
-    ctx->tunes.push_back({p, q, precision, slots_per_cu, schedule, basis_kernel});
+    ctx->tunes.push_back({p, q, precision, slots_per_cu, schedule, basis_kernel, pipeline});
     return MA_OK;
 }
 
@@ -1806,13 +1809,50 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
     if (opts_in) o = *opts_in;
     o.keep_sj = 0;   // timing solves leave the kept s_j alone
     o.use_graph = 0;
+    const int pipe_on = o.pipeline >= 0 ? o.pipeline : 4;
     std::memset(out, 0, sizeof(*out));
     out->best_ms = INFINITY;
+    // one timed candidate: best of reps over the whole solve (with
+    // pipelining, a basis kernel that leaves no room for the eigensolver
+    // beside it can be faster alone and slower in the solve)
+    auto trial = [&](int kern, int sched, int bpc, int pipe, double &best) -> ma_status {
+        o.basis_kernel = kern;
+        o.pipeline = pipe;
+        Plan P;
+        BufSource run = src;
+        ma_status s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, bpc, sched, P, &run);
+        if (s != MA_OK) return s;
+        best = INFINITY;
+        for (int r = 0; r < reps; ++r) {
+            ma_result res{};
+            s = run_plan(ctx, P, &res);
+            if (s != MA_OK) return s;
+            best = std::min(best, res.elapsed_ms);
+        }
+        if (out->n_tried < 64) {
+            const int t = out->n_tried++;
+            out->tried_slots[t] = bpc;
+            out->tried_schedule[t] = sched;
+            out->tried_kernel[t] = kern;
+            out->tried_pipeline[t] = pipe;
+            out->tried_ms[t] = best;
+        }
+        if (best < out->best_ms) {
+            out->best_ms = best;
+            out->slots_per_cu = bpc;
+            out->schedule = sched;
+            out->basis_kernel = kern;
+            out->pipeline = pipe;
+        }
+        return MA_OK;
+    };
     for (int kern = MA_BASIS_ONCHIP; kern <= MA_BASIS_ATOM; ++kern) {
         if (kern == MA_BASIS_ONCHIP && !ma::basis_small_fits(ctx->nmax, p + q, q, ctx->o)) continue;
         if (kern == MA_BASIS_GROUP && !ma::basis_group_fits(ctx->nmax, p + q, ctx->o)) continue;
         if (kern == MA_BASIS_ATOM && !ma::basis_atom_fits(ctx->nmax, p + q, ctx->o, o.precision)) continue;
         o.basis_kernel = kern;
+        o.pipeline = pipe_on;
         // occupancy limit of this kernel and shape
         Plan P0;
         BufSource sz;
@@ -1822,38 +1862,28 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
                                 nullptr, nullptr, nullptr, 1 << 20, MA_SCHED_LPT, P0, &sz);
         if (s != MA_OK) return s;
         const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
+        double kbest = INFINITY;
+        int kb_sched = 0, kb_bpc = 1;
         for (int sched = 0; sched <= MA_SCHED_XCD_LPT; ++sched)
-            for (int bpc = 1; bpc <= max_bpc && out->n_tried < 64; ++bpc) {
-                Plan P;
-                BufSource run = src;
-                s = make_plan(ctx, ncols, cols, p, q, mu, kT, &o, nullptr, nullptr, nullptr, nullptr,
-                              nullptr, nullptr, bpc, sched, P, &run);
+            for (int bpc = 1; bpc <= max_bpc && out->n_tried < 63; ++bpc) {
+                double best;
+                s = trial(kern, sched, bpc, pipe_on, best);
                 if (s != MA_OK) return s;
-                double best = INFINITY;
-                for (int r = 0; r < reps; ++r) {
-                    ma_result res{};
-                    s = run_plan(ctx, P, &res);
-                    if (s != MA_OK) return s;
-                    // the whole solve: with pipelining, a basis kernel that leaves
-                    // no room for the eigensolver beside it can be faster alone
-                    // and slower in the solve
-                    best = std::min(best, res.elapsed_ms);
-                }
-                const int t = out->n_tried++;
-                out->tried_slots[t] = bpc;
-                out->tried_schedule[t] = sched;
-                out->tried_kernel[t] = kern;
-                out->tried_ms[t] = best;
-                if (best < out->best_ms) {
-                    out->best_ms = best;
-                    out->slots_per_cu = bpc;
-                    out->schedule = sched;
-                    out->basis_kernel = kern;
+                if (best < kbest) {
+                    kbest = best;
+                    kb_sched = sched;
+                    kb_bpc = bpc;
                 }
             }
+        // the kernel's fastest configuration with the chunks in sequence
+        if (pipe_on >= 2 && std::isfinite(kbest) && out->n_tried < 64) {
+            double best;
+            s = trial(kern, kb_sched, kb_bpc, 0, best);
+            if (s != MA_OK) return s;
+        }
     }
     return ma_set_tuning(ctx, p, q, o.precision, out->slots_per_cu, out->schedule,
-                         out->basis_kernel);
+                         out->basis_kernel, out->pipeline);
 }
 
 }  // extern "C"
