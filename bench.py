@@ -69,6 +69,8 @@ def main():
                     help="chunks pipelining the eigensolver beside the basis kernel (default: "
                          "the autotuned choice, else 4; 0 = chunks in sequence, one chunk "
                          "replayed as hipGraphs)")
+    ap.add_argument("--chunk-columns", type=int, default=0,
+                    help="columns per chunk of the solve (0: the library's choice)")
     ap.add_argument("--basis-kernel", default="auto",
                     choices=["auto", "onchip", "workspace", "group", "atom"],
                     help="basis kernel: on-chip basis (regions up to 512 orbitals) or workspace")
@@ -118,6 +120,8 @@ def main():
                            basis_kernel=args.basis_kernel)
     if args.pipeline >= 0:
         opts.pipeline = args.pipeline
+    if args.chunk_columns > 0:
+        opts.chunk_columns = args.chunk_columns
     tuning = None
     if args.tuning:
         parts = args.tuning.split(",")

@@ -889,7 +889,13 @@ struct Plan {
 // one chunk (the rest of the solve's memory is proportional to the system);
 // a pipelined solve keeps a ring of such buffers within kRingBudget, so the
 // basis kernel of chunk k waits only for the eigensolver of chunk k - nbuf.
+// Unpipelined solves on the library's own buffers take a fifth of the device
+// memory that is free (counting the chunk buffer they already hold), between
+// 4 and 64 GiB: fewer, longer chunks lose less to each chunk's drain (on the
+// 262,144-atom cell 60 chunks of 4 GiB cost 4.6 % over 4 of 65 GB); a
+// caller's workspace and size queries keep 4 GiB so that the two agree.
 constexpr size_t kMidBudget = (size_t)4 << 30;
+constexpr size_t kMidBudgetMax = (size_t)64 << 30;
 constexpr size_t kRingBudget = (size_t)8 << 30;
 
 // Where the per-solve buffers of a plan come from: the library's own
@@ -1077,7 +1083,12 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
 
     // chunks: whole work items, at most the chunk budget of columns each
     J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
-    const size_t mid_budget = src->limited ? src->cap / 4 : kMidBudget;
+    size_t mid_budget = src->limited ? src->cap / 4 : kMidBudget;
+    if (!src->region() && pipe < 2) {   // (a pipelined ring keeps 4 GiB buffers)
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+            mid_budget = std::min(kMidBudgetMax, std::max(kMidBudget, (fr + ctx->mid.bytes) / 5));
+    }
     const int64_t per_chunk = std::max<int64_t>(o, (int64_t)(mid_budget / (sizeof(double) * J.mid_stride)));
     int64_t budget = std::max<int64_t>(1, opts.chunk_columns > 0 ? opts.chunk_columns : per_chunk);
     // pipelining: for solves large enough, opts.pipeline + 2 chunks whose
