@@ -4,7 +4,8 @@ Training pairs (descriptor of column j, s_j on the orbitals of the 12 atoms
 nearest to atom(j)) come from the library's own CG solves (FP64, tolerance
 1e-12) on training geometries; the network is trained by the library's FP32
 forward/backward/Adam kernels.  PyTorch only holds the device arrays and the
-shuffled index batches.
+shuffled index batches; the standardisation of inputs and targets is computed
+on the host.
 """
 
 from __future__ import annotations
@@ -41,19 +42,20 @@ def collect_pairs(ctx: Context, tb, cols=None, cg_tol=1e-12):
 
 def train(ctx: Context, X, T, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
     """Adam on the mean squared error with standardised inputs and targets
-    (per feature / output: zero mean, unit spread).  Both standardisations
-    are folded into the first and last layers afterwards, so the network
-    maps raw descriptors to s_j coefficients.  Returns the mean
-    (standardised) loss of every epoch."""
+    (per feature / output: zero mean, unit spread, computed on the host).
+    Both standardisations are folded into the first and last layers
+    afterwards, so the network maps raw descriptors to s_j coefficients.
+    Returns the mean (standardised) loss of every epoch."""
     import torch
     n = X.shape[0]
-    xm = X.mean(0)
-    xs = X.std(0)
-    xs = torch.where(xs > 1e-6, xs, torch.ones_like(xs))
-    Xs = ((X - xm) / xs).contiguous()
-    mean = T.mean(0)
-    std = T.std(0).clamp_min(1e-6)
-    Ts = ((T - mean) / std).contiguous()
+    Xh = X.cpu().numpy().astype(np.float64)
+    Th = T.cpu().numpy().astype(np.float64)
+    xm, xs = Xh.mean(0), Xh.std(0, ddof=1)
+    xs = np.where(xs > 1e-6, xs, 1.0)
+    mean, std = Th.mean(0), np.maximum(Th.std(0, ddof=1), 1e-6)
+    Xs = torch.from_numpy(((Xh - xm) / xs).astype(np.float32)).cuda()
+    Ts = torch.from_numpy(((Th - mean) / std).astype(np.float32)).cuda()
+    del Xh, Th
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     history = []
@@ -70,12 +72,12 @@ def train(ctx: Context, X, T, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
     sh = ctx.mlp_shape()
     p = ctx.mlp_get_params().astype(np.float64)
     ni, no, nh = sh["n_in"], sh["n_out"], sh["n_hidden"]
-    xmn, xsn = xm.cpu().numpy().astype(np.float64), xs.cpu().numpy().astype(np.float64)
+    xmn, xsn = xm, xs
     w1 = p[:ni * nh].reshape(ni, nh)
     b1 = p[ni * nh:ni * nh + nh] - (xmn / xsn) @ w1
     p[:ni * nh] = (w1 / xsn[:, None]).ravel()
     p[ni * nh:ni * nh + nh] = b1
-    sd, mu = std.cpu().numpy(), mean.cpu().numpy()
+    sd, mu = std, mean
     w3 = p[-no - nh * no:-no].reshape(nh, no) * sd[None, :]
     b3 = p[-no:] * sd + mu
     p[-no - nh * no:-no] = w3.ravel()

@@ -237,3 +237,47 @@ def test_trained_network_reduces_cg_iterations(env):
     assert ez < 1e-4 and el < 1e-4
     ctx.build_tb(s)
     ctx.mlp_init(seed=3)
+
+
+def test_c4_protocol_on_a_fresh_disordered_seed(env):
+    """The start network's evaluation protocol at test size: train on pairs
+    from the 64-atom cell and one 4,096-atom geometry (crystalline), evaluate
+    on a fresh seed of the 8,000-atom disordered cell with the CG tolerance at
+    1e-8, mixed_f64acc, against the zero start: CG iterations, columns/s and
+    the max rho error against the FP64 solve at tolerance 1e-12 for both.
+    What holds and is asserted: at CG tolerance 1e-8 both starts stay within
+    1e-3 of the FP64 result (with p = q = 20 the block-2 Krylov space
+    K_20(H; s_j) amplifies the s_j error the tolerance allows: 7.6e-5 for the
+    zero start, 6.0e-4 for the learned one on this seed), and every column
+    either uses or rejects its prediction; the numbers are reported.  The
+    network does not transfer from crystalline to disordered environments
+    well enough to cut the iterations, and at equal CG tolerance its rho
+    error is larger (a negative result that the printed numbers record)."""
+    torch, ma, ctx, s = env
+    from paper_1202_0098_amd import learned
+    Xs, Ts = [], []
+    for tb in (synth.config_diamond64(1001), synth.config_diamond4096(2101)):
+        X, T = learned.collect_pairs(ctx, tb)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
+    ctx.mlp_init(seed=7)
+    hist = learned.train(ctx, X, T, epochs=8, batch=512, lr=1e-3)
+    _say(f"{X.shape[0]} pairs, training loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    tb = synth.config_disordered8000(3006)
+    ctx.build_tb(tb)
+    ref = learned.cg_stats(ctx, tb, "zero", cg_tol=1e-12, precision="fp64", reps=1)
+    z = learned.cg_stats(ctx, tb, "zero", cg_tol=1e-8, precision="mixed_f64acc", reps=2,
+                         mu=ref["mu"])
+    lr_ = learned.cg_stats(ctx, tb, "learned", cg_tol=1e-8, precision="mixed_f64acc", reps=2,
+                           mu=ref["mu"])
+    ez = float(np.abs(z["rho"] - ref["rho"]).max())
+    el = float(np.abs(lr_["rho"] - ref["rho"]).max())
+    _say(f"disordered8000 seed 3006: CG iterations zero {z['cg_mean']:.2f} learned "
+         f"{lr_['cg_mean']:.2f}; columns/s {z['cols_per_s']:.4g} -> {lr_['cols_per_s']:.4g}; "
+         f"predictions used {lr_['learned']:.3f}, rejected {lr_['fallback']:.3f}; max rho error "
+         f"zero {ez:.2e} learned {el:.2e}")
+    assert ez <= 1e-3 and el <= 1e-3
+    assert abs(lr_["learned"] + lr_["fallback"] - 1.0) < 1e-12
+    ctx.build_tb(s)
+    ctx.mlp_init(seed=3)
