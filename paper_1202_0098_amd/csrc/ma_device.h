@@ -2311,19 +2311,22 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
 {
     extern __shared__ double smem[];
     const int nu = J.nu;
-    double *A = smem, *B = smem + nu * nu, *Z = smem + 2 * nu * nu;   // Z column-major
-    double *ev = smem + 3 * nu * nu, *vj = ev + kMaxNu, *svj = vj + kMaxNu, *fw = svj + kMaxNu;
-    double *hh = fw + kMaxNu, *ee = hh + kMaxNu, *qv = ee + kMaxNu, *rd = qv + kMaxNu;
-    double *upj = rd + kMaxNu;   // 2 kMaxNu
-    int *rank = reinterpret_cast<int *>(upj + 2 * kMaxNu);
-    int *inv = rank + kMaxNu;
+    // Two nu x nu matrices in LDS (A, and Z column-major); the Cholesky
+    // factor of S~ lives in the Z area until Z is needed, waits in the S~
+    // slot of the chunk buffer meanwhile, and comes back for C = Lc^-T Z.
+    double *A = smem, *Z = smem + nu * nu, *B = Z;
+    double *ev = smem + 2 * nu * nu, *vj = ev + nu, *svj = vj + nu, *fw = svj + nu;
+    double *hh = fw + nu, *ee = hh + nu, *rd = ee + nu;
+    double *upj = rd + nu;   // 2 nu
+    int *rank = reinterpret_cast<int *>(upj + 2 * nu);
+    int *inv = rank + nu;
     __shared__ double hv[kMaxNu];   // current Householder vector (separate objects: the
     __shared__ double hq[kMaxNu];   // compiler may keep their loads ahead of A's stores)
     const int lane = threadIdx.x;
     const int o = S.o;
     for (int s = blockIdx.x; s < J.cn; s += gridDim.x) {
         const int c = J.order[J.c0 + s];
-        const double *mid = J.mid + (int64_t)s * J.mid_stride;
+        double *mid = J.mid + (int64_t)s * J.mid_stride;
         const double *Up = mid + 2 * (int64_t)nu * nu;
         int32_t *st = J.stats + (int64_t)c * kStats;
         int L = st[3] == 0 ? st[0] : 0;
@@ -2337,7 +2340,7 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
         // basis rows at j: u_m[j] and (S u_m)[j]
         for (int m = lane; m < L; m += 64) {
             upj[m] = Up[m];
-            upj[kMaxNu + m] = Up[nu + m];
+            upj[nu + m] = Up[nu + m];
         }
         __syncthreads();
 
@@ -2362,29 +2365,32 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
             }
             __syncthreads();
         }
-        // W = Lc^-1 H~ into Z (row-major here), then A = Lc^-1 W^T
-        for (int e = lane; e < L * L; e += 64) Z[e] = A[e];
-        __syncthreads();
-        for (int k = 0; k < L; ++k)
-            for (int cc = lane; cc < L; cc += 64) {
-                const double wk = Z[k * L + cc] * rd[k];
-                Z[k * L + cc] = wk;
-                #pragma unroll 4
-                for (int i = k + 1; i < L; ++i) Z[i * L + cc] -= B[i * L + k] * wk;
+        // A = Lc^-1 H~ Lc^-T in place: W = Lc^-1 A (a lane per column), then
+        // A = Lc^-1 W^T
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k = 0; k < L; ++k)
+                for (int cc = lane; cc < L; cc += 64) {
+                    const double ak = A[k * L + cc] * rd[k];
+                    A[k * L + cc] = ak;
+                    #pragma unroll 4
+                    for (int i = k + 1; i < L; ++i) A[i * L + cc] -= B[i * L + k] * ak;
+                }
+            __syncthreads();
+            if (pass == 0) {
+                for (int e = lane; e < L * L; e += 64) {
+                    const int i = e / L, k = e - i * L;
+                    if (i < k) {
+                        const double x = A[i * L + k];
+                        A[i * L + k] = A[k * L + i];
+                        A[k * L + i] = x;
+                    }
+                }
+                __syncthreads();
             }
-        __syncthreads();
-        for (int e = lane; e < L * L; e += 64) {
-            const int i = e / L, k = e - i * L;
-            A[e] = Z[k * L + i];
         }
-        __syncthreads();
-        for (int k = 0; k < L; ++k)
-            for (int cc = lane; cc < L; cc += 64) {
-                const double ak = A[k * L + cc] * rd[k];
-                A[k * L + cc] = ak;
-                #pragma unroll 4
-                for (int i = k + 1; i < L; ++i) A[i * L + cc] -= B[i * L + k] * ak;
-            }
+        // the factor waits in the S~ slot of the chunk buffer (read above,
+        // not read again) while Z takes its place
+        for (int e = lane; e < L * L; e += 64) mid[nu * nu + e] = B[e];
         __syncthreads();
         for (int e = lane; e < L * L; e += 64) {
             const int i = e / L, k = e - i * L;
@@ -2556,10 +2562,16 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
                 if (ev[bb] < va || (ev[bb] == va && bb < a)) ++rk;
             rank[a] = rk;
         }
-        // C = Lc^-T Z -> A (row-major), a lane per column
+        // C = Lc^-T Z -> A (row-major), a lane per column; the factor back
+        // in the Z area once Z is copied
         for (int a = lane; a < L; a += 64) {
             #pragma unroll 4
             for (int i = 0; i < L; ++i) A[i * L + a] = Z[a * L + i];
+        }
+        __syncthreads();
+        for (int e = lane; e < L * L; e += 64) B[e] = mid[nu * nu + e];
+        __syncthreads();
+        for (int a = lane; a < L; a += 64) {
             for (int k = L - 1; k >= 0; --k) {
                 const double ck = A[k * L + a] * rd[k];
                 A[k * L + a] = ck;
@@ -2585,7 +2597,7 @@ __global__ void __launch_bounds__(64) k_eig(DevSystem S, DevJob J)
             for (int m = 0; m < L; ++m) {
                 const double cma = C[m * L + a];
                 v1 += upj[m] * cma;
-                v2 += upj[kMaxNu + m] * cma;
+                v2 += upj[nu + m] * cma;
             }
             vj[a] = v1;
             svj[a] = v2;

@@ -181,8 +181,8 @@ hipError_t basis_occupancy(const DevSystem &S, const DevJob &J, int kind, int *b
 
 hipError_t launch_eig(const DevSystem &S, const DevJob &J, hipStream_t st)
 {
-    const size_t smem = sizeof(double) * (3 * (size_t)J.nu * J.nu + 10 * kMaxNu) +
-                        sizeof(int) * 2 * kMaxNu;
+    const size_t smem = sizeof(double) * (2 * (size_t)J.nu * J.nu + 10 * (size_t)J.nu) +
+                        sizeof(int) * 2 * (size_t)J.nu;
     const int grid = J.cn < (1 << 20) ? J.cn : (1 << 20);
     if (grid < 1) return hipSuccess;
     if (J.precision == 0) return launch_with_smem(k_eig<double>, grid, 64, smem, st, S, J);
