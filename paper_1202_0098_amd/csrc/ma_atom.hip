@@ -852,13 +852,14 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
     }
     const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
     const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
-    // With FP32 operator values the images of a finished vector
-    // u = (p - U a) / beta are taken as S p / beta and H p / beta from the
-    // pass over its pending form p: the dropped (S U) a / beta and K a / beta
-    // are second-pass corrections, of the order of the first pass's loss of
-    // orthogonality (far below the FP32 rounding of S p itself), and pass 1
-    // disappears.  With FP64 values every image is applied to u itself.
-    constexpr bool DERIVE = PREC != 0;
+    // With FP32 operator values (FP64 sums: this kernel has no FP32-sum
+    // mode) the images of a finished vector u = (p - U a) / beta are taken as
+    // S p / beta and H p / beta from the pass over its pending form p: the
+    // basis is orthonormal in the metric of the rounded S that every product
+    // uses, so the dropped (S U) a / beta and K a / beta are second-pass
+    // corrections at the FP64 rounding level, and pass 1 disappears.  With
+    // FP64 values every image is applied to u itself.
+    constexpr bool DERIVE = PREC == 2;
     for (;;) {
         __syncthreads();
         if (tid < O) {
