@@ -394,16 +394,19 @@ MA_API ma_status ma_column_features(ma_ctx *ctx, int64_t ncols, const int32_t *c
 MA_API ma_status ma_mlp_forward(ma_ctx *ctx, const float *x, int64_t n, float *y, int32_t bf16);
 
 /* Mean squared error of the start network over n rows (rows idx[i] of x and
- * t, device, if idx != NULL, else rows 0..n-1) and its gradient (host,
- * n_params floats, may be NULL).  Indices are checked on the host. */
-MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
-                                  int64_t n, double *loss, float *grad);
+ * t, device tables of n_rows rows, if idx != NULL, else rows 0..n-1) and its
+ * gradient (host, n_params floats, may be NULL).  The gather checks the device
+ * indices: one outside [0, n_rows) fails the call with MA_EINVAL. */
+MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, int64_t n_rows,
+                                  const int32_t *idx, int64_t n, double *loss, float *grad);
 
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) of the start network on the
  * mean squared error of the n rows idx[i] (device int32, NULL = rows
- * 0..n-1) of x and t (device); the loss before the step in *loss. */
-MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
-                                   int64_t n, float lr, double *loss);
+ * 0..n-1) of x and t (device tables of n_rows rows); the loss before the step
+ * in *loss.  An index outside [0, n_rows) fails the call with MA_EINVAL
+ * before the parameters change. */
+MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, int64_t n_rows,
+                                   const int32_t *idx, int64_t n, float lr, double *loss);
 
 /* Autotuner of the launch (not part of the paper's method, which runs the
  * columns of Sec. 2 independently): time the solve on cols[0..ncols) (NULL = all) for every

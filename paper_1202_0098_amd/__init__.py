@@ -136,8 +136,8 @@ def load_library():
     lib.ma_mlp_get_params.argtypes = [P, P, i64]
     lib.ma_column_features.argtypes = [P, i64, P, P]
     lib.ma_mlp_forward.argtypes = [P, P, i64, P, i32]
-    lib.ma_mlp_loss_grad.argtypes = [P, P, P, P, i64, P, P]
-    lib.ma_mlp_train_step.argtypes = [P, P, P, P, i64, ctypes.c_float, P]
+    lib.ma_mlp_loss_grad.argtypes = [P, P, P, i64, P, i64, P, P]
+    lib.ma_mlp_train_step.argtypes = [P, P, P, i64, P, i64, ctypes.c_float, P]
     lib.ma_find_mu.argtypes = [P, f64, f64, f64, ctypes.POINTER(_Result)]
     lib.ma_find_mu.restype = ctypes.c_int
     lib.ma_workspace_size.argtypes = [P, i64, P, i32, i32, f64, ctypes.POINTER(_Opts)]
@@ -350,17 +350,25 @@ class Context:
     def mlp_forward(self, x, n, y, bf16=True):
         self._check(self._lib.ma_mlp_forward(self._h, _ptr(x), int(n), _ptr(y), int(bool(bf16))))
 
-    def mlp_loss_grad(self, x, t, n, idx=None, want_grad=True):
+    def _rows(self, x, n_rows):
+        if n_rows is not None:
+            return int(n_rows)
+        return int(x.numel() // self.mlp_shape()["n_in"])
+
+    def mlp_loss_grad(self, x, t, n, idx=None, want_grad=True, n_rows=None):
+        """Loss and gradient on n rows (idx: rows of the tables x, t; n_rows:
+        rows of the tables, default from x's size)."""
         loss = ctypes.c_double()
         g = np.zeros(self.mlp_shape()["n_params"], np.float32) if want_grad else None
-        self._check(self._lib.ma_mlp_loss_grad(self._h, _ptr(x), _ptr(t), _ptr(idx), int(n),
-                                               ctypes.byref(loss), _ptr(g)))
+        self._check(self._lib.ma_mlp_loss_grad(self._h, _ptr(x), _ptr(t), self._rows(x, n_rows),
+                                               _ptr(idx), int(n), ctypes.byref(loss), _ptr(g)))
         return loss.value, g
 
-    def mlp_train_step(self, x, t, n, lr, idx=None):
+    def mlp_train_step(self, x, t, n, lr, idx=None, n_rows=None):
         loss = ctypes.c_double()
-        self._check(self._lib.ma_mlp_train_step(self._h, _ptr(x), _ptr(t), _ptr(idx), int(n),
-                                                ctypes.c_float(lr), ctypes.byref(loss)))
+        self._check(self._lib.ma_mlp_train_step(self._h, _ptr(x), _ptr(t), self._rows(x, n_rows),
+                                                _ptr(idx), int(n), ctypes.c_float(lr),
+                                                ctypes.byref(loss)))
         return loss.value
 
     def solve_columns(self, cols, p, q, mu=math.nan, kT=0.1, opts=None, rho=None, pi=None,

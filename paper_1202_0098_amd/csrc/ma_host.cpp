@@ -134,7 +134,7 @@ struct ma_ctx {
         int nf = 0, nh = 0, no = 0, nf_pad = 0, no_pad = 0, step = 0;
         int64_t P = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
         DevBuf params, grad, m, v, W1t, W2t, W3t;
-        DevBuf Xb, Tb, Z1, A1, Z2, A2, Yb, dY, dA, partial;
+        DevBuf Xb, Tb, Z1, A1, Z2, A2, Yb, dY, dA, partial, bad;
     } net;
     DevBuf feat, x0;                  // per-solve descriptors and predicted starts
 
@@ -1970,19 +1970,33 @@ hipError_t net_forward_f32(ma_ctx *ctx, const float *x, int64_t n, float *y, hip
 
 // Loss and gradient of the mean squared error on n rows; optional Adam step.
 ma_status net_train_core(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx, int64_t n,
-                         bool update, float lr, double *loss, float *grad_host)
+                         int64_t n_rows, bool update, float lr, double *loss, float *grad_host)
 {
     auto &N = ctx->net;
     if (!N.ready) return ctx->fail(MA_ESTATE, "no start network (ma_mlp_init or ma_mlp_set_params)");
     if (!x || !t || n < 1 || n > INT_MAX) return ctx->fail(MA_EINVAL, "invalid training batch");
+    if (n_rows < 1 || (!idx && n > n_rows))
+        return ctx->fail(MA_EINVAL, "batch of %lld rows from a table of %lld", (long long)n,
+                         (long long)n_rows);
     ma_status s = net_workspace(ctx, n);
     if (s != MA_OK) return s;
     hipStream_t st = ctx->work_stream();
     HIPCHK(ctx, ctx->after_caller(), "stream order");
     const float *X = x, *T = t;
     if (idx) {
-        HIPCHK(ctx, ma::launch_gather_rows(x, idx, n, N.nf, N.Xb.as<float>(), st), "gather");
-        HIPCHK(ctx, ma::launch_gather_rows(t, idx, n, N.no, N.Tb.as<float>(), st), "gather");
+        // the device indices are checked by the gather: one outside the
+        // table fails the call before any update
+        HIPCHK(ctx, N.bad.reserve(sizeof(int)), "index flag");
+        HIPCHK(ctx, hipMemsetAsync(N.bad.p, 0, sizeof(int), st), "index flag");
+        HIPCHK(ctx, ma::launch_gather_rows(x, idx, n, N.nf, n_rows, N.Xb.as<float>(),
+                                           N.bad.as<int>(), st), "gather");
+        HIPCHK(ctx, ma::launch_gather_rows(t, idx, n, N.no, n_rows, N.Tb.as<float>(),
+                                           N.bad.as<int>(), st), "gather");
+        int bad = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&bad, N.bad.p, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+        HIPCHK(ctx, hipStreamSynchronize(st), "gather");
+        if (bad) return ctx->fail(MA_EINVAL, "a row index is outside the table of %lld rows",
+                                  (long long)n_rows);
         X = N.Xb.as<float>();
         T = N.Tb.as<float>();
     }
@@ -2162,21 +2176,21 @@ MA_API ma_status ma_mlp_forward(ma_ctx *ctx, const float *x, int64_t n, float *y
     return MA_OK;
 }
 
-MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
-                                  int64_t n, double *loss, float *grad)
+MA_API ma_status ma_mlp_loss_grad(ma_ctx *ctx, const float *x, const float *t, int64_t n_rows,
+                                  const int32_t *idx, int64_t n, double *loss, float *grad)
 {
     if (!ctx) return MA_EINVAL;
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    return net_train_core(ctx, x, t, idx, n, false, 0.0f, loss, grad);
+    return net_train_core(ctx, x, t, idx, n, n_rows, false, 0.0f, loss, grad);
 }
 
-MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, const int32_t *idx,
-                                   int64_t n, float lr, double *loss)
+MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, int64_t n_rows,
+                                   const int32_t *idx, int64_t n, float lr, double *loss)
 {
     if (!ctx) return MA_EINVAL;
     if (!(lr > 0)) return ctx->fail(MA_EINVAL, "lr must be positive");
     HIPCHK(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    return net_train_core(ctx, x, t, idx, n, true, lr, loss, nullptr);
+    return net_train_core(ctx, x, t, idx, n, n_rows, true, lr, loss, nullptr);
 }
 
 }  // extern "C"

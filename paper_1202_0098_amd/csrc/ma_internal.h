@@ -180,8 +180,8 @@ hipError_t scratch_address(int device, void **ptr, size_t *bytes);
 // Start network (ma_mlp.hip).
 hipError_t launch_features(const int32_t *cols, int ncols, int o, const float *geo, int nf_geo,
                            int nf, float *feat, hipStream_t st);
-hipError_t launch_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, float *out,
-                              hipStream_t st);
+hipError_t launch_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, int64_t rows,
+                              float *out, int *bad, hipStream_t st);
 hipError_t launch_to_bf16_t(const float *W, int rows, int cols, int rows_pad, int cols_pad,
                             unsigned short *Wt, hipStream_t st);
 size_t mlp_infer_smem(int nf_pad, int nh);

@@ -260,13 +260,19 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t cou
     }
 }
 
-__global__ void k_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, float *out)
+// out row i = in row idx[i]; an index outside [0, rows) writes zeros and
+// sets *bad
+__global__ void k_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, int64_t rows,
+                              float *out, int *bad)
 {
     const int64_t total = n * m;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / m;
-        out[e] = in[(int64_t)idx[i] * m + (e - i * m)];
+        const int64_t r = idx[i];
+        const bool ok = r >= 0 && r < rows;
+        if (!ok && e == i * m) atomicOr(bad, 1);
+        out[e] = ok ? in[r * m + (e - i * m)] : 0.0f;
     }
 }
 
@@ -282,10 +288,11 @@ hipError_t launch_features(const int32_t *cols, int ncols, int o, const float *g
     return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, float *out,
-                              hipStream_t st)
+hipError_t launch_gather_rows(const float *in, const int32_t *idx, int64_t n, int m, int64_t rows,
+                              float *out, int *bad, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(n * m, 256)), dim3(256), 0, st, in, idx, n, m, out);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(n * m, 256)), dim3(256), 0, st, in, idx, n, m,
+                       rows, out, bad);
     return hipGetLastError();
 }
 

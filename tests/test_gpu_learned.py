@@ -281,3 +281,27 @@ def test_c4_protocol_on_a_fresh_disordered_seed(env):
     assert abs(lr_["learned"] + lr_["fallback"] - 1.0) < 1e-12
     ctx.build_tb(s)
     ctx.mlp_init(seed=3)
+
+
+def test_training_rejects_an_index_outside_the_table(env):
+    """The gather checks the device row indices: an index past the end of
+    the table (or negative) fails the training step with MA_EINVAL before
+    the parameters change."""
+    torch, ma, ctx, s = env
+    sh = ctx.mlp_shape()
+    n = 64
+    rng = np.random.default_rng(21)
+    X = torch.from_numpy(rng.normal(size=(n, sh["n_in"])).astype(np.float32)).cuda()
+    T = torch.from_numpy((rng.normal(size=(n, sh["n_out"])) * 0.1).astype(np.float32)).cuda()
+    p0 = ctx.mlp_get_params()
+    for bad in (n, -1):
+        idx = torch.arange(32, dtype=torch.int32, device="cuda")
+        idx[7] = bad
+        with pytest.raises(ma.MarnoldiError) as ei:
+            ctx.mlp_train_step(X, T, 32, 1e-3, idx=idx)
+        assert ei.value.status == ma.MA_EINVAL
+    assert np.array_equal(ctx.mlp_get_params(), p0)
+    # in range: accepted
+    idx = torch.arange(32, dtype=torch.int32, device="cuda") + 32
+    ctx.mlp_train_step(X, T, 32, 1e-3, idx=idx)
+    ctx.mlp_init(seed=3)
