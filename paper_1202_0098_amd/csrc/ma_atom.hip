@@ -32,18 +32,18 @@ namespace ma {
 
 // doubles of one column's slice of the workspace (rounded to 256 bytes):
 // U, S U, H U (nu vectors each), the chain T (q vectors), the working
-// vectors P, Z, D and six coefficient arrays of nu + 1
+// vectors P, Z, D, P2 and nine coefficient arrays of nu + 1
 __host__ __device__ int64_t atom_slice_doubles(int nu, int q, int64_t ld)
 {
-    const int64_t d = (3 * (int64_t)nu + q + 3) * ld + 6 * (int64_t)(nu + 1);
+    const int64_t d = (3 * (int64_t)nu + q + 4) * ld + 9 * (int64_t)(nu + 1);
     return (d + 31) & ~(int64_t)31;
 }
 
-// doubles of one workgroup's workspace: o column slices and three SpMM
+// doubles of one workgroup's workspace: o column slices and five SpMM
 // result sets (column-major, ld * o each)
 __host__ __device__ int64_t atom_ws_doubles(int o, int nu, int q, int64_t ld)
 {
-    return (int64_t)o * atom_slice_doubles(nu, q, ld) + 3 * ld * o;
+    return (int64_t)o * atom_slice_doubles(nu, q, ld) + 5 * ld * o;
 }
 
 namespace {
@@ -53,6 +53,9 @@ constexpr int NWA = NTA / 64;
 static_assert(NTA == NTG, "comb2_rows assumes rows tid + r * 256");
 
 enum { kNone = 0, kB1 = 1, kChain = 2 };
+// source of a candidate in the paired recurrence: H of the pending block-1
+// vector, a finished chain vector, or the chain vector of the step
+enum { kSrcNone = 0, kSrcH = 1, kSrcT = 2, kSrcZ = 3 };
 
 // Per-column state shared by the workgroup; column k's fields are written
 // only by thread k, between barriers.
@@ -67,15 +70,25 @@ struct AState {
     double cp_scale, ctp_scale, inv_b, inv_e, f, ft, sc;
     double rho2, alpha, beta, rho;
     float rrf, alphaf, betaf;
+    // paired recurrence: pending vectors (np), whether the first is a
+    // block-1 vector, chain vectors used as seeds (tq), this step's
+    // candidates (nc planned, nv valid; sources c3k/c4k, chain index
+    // c3m/c4m), the second pending vector's acceptance, 1/beta2, its
+    // coefficient g on u1, the candidates' coefficients on u1 and u2, and
+    // the scale of the second pending vector's first-pass coefficients
+    int np, pk1, tq, nc, nv, c3k, c3m, c4k, c4m, acc2;
+    double inv_b2, g, f31, f32, f41, f42, cp2_scale;
 };
 
 // Column k's vectors in the workgroup's workspace (leading dimension ld).
 // CG: Z the solution (then s_j), D the residual, P the direction; the FP32
 // passes keep r, p, d in U as floats.  Basis: P the pending vector
 // (projected once), Z the pending chain vector, D the H image of the step's
-// candidate source.  After the o slices, the SpMM results of a pass,
-// column-major (column k at k * ld): RH (H x), RS (S x) and RH2 (H of the
-// chain vectors, so that RH keeps H of the pending vectors).
+// candidate source, P2 the second pending vector of the paired recurrence.
+// After the o slices, the SpMM results of a pass, column-major (column k at
+// k * ld): RH (H x), RS (S x), RH2 (H of the chain vectors, so that RH keeps
+// H of the pending vectors) and RHb, RSb (H and S of the second pending
+// vectors).
 struct Slices {
     double *base;
     int64_t cs, ld;
@@ -96,10 +109,13 @@ struct Slices {
     __device__ double *P(int k) const { return T(k) + q * ld; }
     __device__ double *Z(int k) const { return P(k) + ld; }
     __device__ double *D(int k) const { return Z(k) + ld; }
-    __device__ double *CA(int k) const { return D(k) + ld; }
+    __device__ double *P2(int k) const { return D(k) + ld; }
+    __device__ double *CA(int k) const { return P2(k) + ld; }
     __device__ double *CB(int k, int which) const { return CA(k) + (1 + which) * (nu + 1); }
     __device__ double *CAT(int k) const { return CA(k) + 3 * (nu + 1); }
     __device__ double *CTB(int k, int which) const { return CA(k) + (4 + which) * (nu + 1); }
+    __device__ double *CA2(int k) const { return CA(k) + 6 * (nu + 1); }
+    __device__ double *CB4(int k, int which) const { return CA(k) + (7 + which) * (nu + 1); }
     __device__ float *F(int k, int v) const { return reinterpret_cast<float *>(U(k)) + v * ld; }
 };
 
@@ -439,12 +455,130 @@ __device__ __forceinline__ void dot_sweep_rows(const DotJob *jobs, int64_t ld, i
     }
 }
 
+// One column's share of the paired dot sweep: V rows against x[0..3] (the
+// pending vectors P1, P2 and the candidates c3, c4; null when absent) into
+// o[0..3], then the extra vectors Vx[0], Vx[1] (S P1, S P2) against the same
+// four into sc[4 e + j]; W rows against y1, y2 into p1, p2, then Wx against
+// them into sc[8], sc[9].
+struct PJob {
+    const double *V, *W;
+    const double *x[4], *Vx[2];
+    const double *y1, *y2, *Wx;
+    double *o[4], *p1, *p2, *sc;
+    int LV, LW;
+};
+
+// dot_sweep_rows with four vectors held per lane: each basis vector read
+// serves the dots of two pending vectors and two candidates.
+template <int O, int RR>
+__device__ __forceinline__ void dot_sweep_pairs(const PJob *jobs, int64_t ld, int n)
+{
+    constexpr int VB = 2;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int task = w; task < 2 * O; task += NWA) {
+        const bool first = task < O;
+        const int k = first ? task : task - O;
+        const PJob &jb = jobs[k];
+        const int L = first ? jb.LV : jb.LW;
+        const double *X0 = first ? jb.Vx[0] : jb.Wx;
+        const double *X1 = first ? jb.Vx[1] : nullptr;
+        const int cnt = L + (X0 ? 1 : 0) + (X1 ? 1 : 0);
+        if (cnt == 0) continue;
+        const double *B = first ? jb.V : jb.W;
+        const double *xp[4] = {first ? jb.x[0] : jb.y1, first ? jb.x[1] : jb.y2,
+                               first ? jb.x[2] : nullptr, first ? jb.x[3] : nullptr};
+        double xv[4][RR];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const int i = lane + 64 * r;
+                xv[j][r] = (xp[j] && i < n) ? xp[j][i < n ? i : 0] : 0.0;
+            }
+        for (int m0 = 0; m0 < cnt; m0 += VB) {
+            double e[VB][RR];
+#pragma unroll
+            for (int v = 0; v < VB; ++v) {
+                const int m = m0 + v < cnt ? m0 + v : m0;
+                const double *vec = m < L ? B + (int64_t)m * ld : (m == L ? X0 : X1);
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    const int i = lane + 64 * r;
+                    e[v][r] = vec[i < n ? i : 0];   // rows past n meet zero x
+                }
+            }
+            double acc[4 * VB];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int v = 0; v < VB; ++v) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) a += e[v][r] * xv[j][r];
+                    acc[j * VB + v] = a;
+                }
+            wave_transpose_reduce<4 * VB>(acc);
+            if (tr_writer<4 * VB>(lane)) {
+                const int kk = tr_index<4 * VB>(lane);
+                const int j = kk / VB, m = m0 + kk % VB;
+                if (m < cnt && xp[j]) {
+                    if (m < L) (first ? jb.o[j] : (j == 0 ? jb.p1 : jb.p2))[m] = acc[0];
+                    else jb.sc[(first ? 0 : 8) + 4 * (m - L) + j] = acc[0];
+                }
+            }
+        }
+    }
+}
+
+// comb2_rows with four coefficient vectors: s_j[rr] = sum_m V[m][i] c_j[m]
+// over m < cnt on the thread's rows i = tid + rr * NTA (the same batching:
+// MB vectors' loads in flight, the last batch padded at coefficient zero).
+template <int R, int MB = 4>
+__device__ __forceinline__ void comb4_rows(const double *__restrict__ V, int64_t ld, int cnt,
+                                           const double *c1, const double *c2, const double *c3,
+                                           const double *c4, int n, double (&s1)[R], double (&s2)[R],
+                                           double (&s3)[R], double (&s4)[R])
+{
+    int off[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        const int i = threadIdx.x + rr * NTA;
+        off[rr] = i < n ? i : 0;
+        s1[rr] = s2[rr] = s3[rr] = s4[rr] = 0.0;
+    }
+    for (int m = 0; m < cnt; m += MB) {
+        double v[MB][R];
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            const int mj = m + j < cnt ? m + j : m;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) v[j][rr] = V[mj * ld + off[rr]];
+        }
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            const bool ok = m + j < cnt;
+            const int mj = ok ? m + j : m;
+            const double a = ok ? c1[mj] : 0.0, b = ok ? c2[mj] : 0.0;
+            const double c = ok ? c3[mj] : 0.0, d = ok ? c4[mj] : 0.0;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                s1[rr] += v[j][rr] * a;
+                s2[rr] += v[j][rr] * b;
+                s3[rr] += v[j][rr] * c;
+                s4[rr] += v[j][rr] * d;
+            }
+        }
+    }
+}
+
 struct SmemA {
     double *xs;          // staged set: nmax * O doubles (FP32 sets use it as floats)
     double *scratch;     // NWA * 64 doubles of reduction scratch
     double *red;         // 64 reduction results
     AState *st;          // O column states
     DotJob *jobs;        // O dot-sweep jobs
+    PJob *pjobs;         // O paired dot-sweep jobs
+    double *psc;         // 12 scalars per column of the paired dot sweep
     int *srp;            // staged region block index
     int2 *sblk;
 };
@@ -461,6 +595,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
     const int64_t ld = S.nmax;
     Slices W{ws, atom_slice_doubles(nu, q, ld), ld, nu, q};
     double *RH = ws + O * W.cs, *RS = RH + ld * O, *RH2 = RS + ld * O;
+    double *RHb = RH2 + ld * O, *RSb = RHb + ld * O;
     float *RSf = reinterpret_cast<float *>(RS);
     AState *st = sm.st;
     const int p0 = J.gstart[gpos];
@@ -831,281 +966,601 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
         if (st[k].live) live |= 1u << k;
 
     // ---------------- bases of K_p(H;e_j) + K_q(H;s_j), in lockstep (Eqs. 4, 6-9) ----------------
+    // Paired form (FP32 operator values with FP64 sums, regions of at most
+    // 1,024 rows).  The block-2 seeds come from the Euclidean chain on s_j,
+    // which does not depend on the S-orthonormal basis; the chain therefore
+    // advances one vector per step from the first step on, runs ahead while
+    // block 1 is built, and block 2 then takes its seeds two at a time.  A
+    // step finishes up to two pending vectors (the second pass of the
+    // delayed two-pass Gram-Schmidt, the second also against the first) and
+    // projects up to two candidates once, so each dot sweep and each update
+    // sweep over the stored basis serves two basis vectors.  The span is that
+    // of Eq. 4: block 1 is the same recurrence as in the sequential form, and
+    // every block-2 seed is a chain vector, taken in chain order.  The images
+    // S u, H u of the finished vectors are derived from those of the pending
+    // ones (u1 = (p1 - U a1) / beta1, u2 = (p2 - U a2 - g u1) / beta2) with
+    // the second-pass terms in U a dropped, as in the sequential form.
+    constexpr bool PAIRS = PREC == 2 && 4 * R <= 16;
+    if constexpr (PAIRS) {
 #pragma unroll 1
-    for (int k = 0; k < O; ++k)
-        if (on(live, k)) {
-            double *P = W.P(k);
-            for (int i = tid; i < n; i += NTA) P[i] = i == st[k].jl ? 1.0 : 0.0;   // block 1 starts at e_j
-        }
-    // (block 2 starts at s_j, which the CG left in Z)
-    if (tid < O) {
-        AState &s = st[tid];
-        s.L = 0;
-        s.nb1 = p > 0 ? 1 : 0;
-        s.kch = 0;
-        s.ping = 0;
-        s.b1_live = 1;
-        s.chain_live = q > 0;
-        s.has_fin = 0;
-        s.has_pend = p > 0;
-        s.cp_scale = s.ctp_scale = 1.0;
-    }
-    const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
-    const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
-    // With FP32 operator values (FP64 sums: this kernel has no FP32-sum
-    // mode) the images of a finished vector u = (p - U a) / beta are taken as
-    // S p / beta and H p / beta from the pass over its pending form p: the
-    // basis is orthonormal in the metric of the rounded S that every product
-    // uses, so the dropped (S U) a / beta and K a / beta are second-pass
-    // corrections at the FP64 rounding level, and pass 1 disappears.  With
-    // FP64 values every image is applied to u itself.
-    constexpr bool DERIVE = PREC == 2;
-    for (;;) {
-        __syncthreads();
-        if (tid < O) {
-            AState &s = st[tid];
-            s.kind = (s.b1_live && s.nb1 < p) ? kB1 : s.chain_live ? kChain : kNone;
-            s.need_z = s.kind == kChain && s.kch + 1 < q;
-            s.tail = s.kind == kNone && !s.has_pend;
-            if (!s.live || (!s.has_fin && !s.has_pend && s.kind == kNone)) s.live = 0;
-        }
-        __syncthreads();
-        unsigned go = 0, fin = 0, b1 = 0, ch = 0, rest = 0;
-#pragma unroll
-        for (int k = 0; k < O; ++k) {
-            const AState &s = st[k];
-            if (!s.live) continue;
-            go |= 1u << k;
-            if (s.has_fin) fin |= 1u << k;
-            if (!s.tail) rest |= 1u << k;
-            if (!s.tail && s.kind == kB1) b1 |= 1u << k;
-            if (!s.tail && s.kind == kChain) ch |= 1u << k;
-        }
-        if (!go) break;
-
-        // pass 1: H and S of the vectors finished in the previous step
-        if (!DERIVE && fin) {
-            stage_set<O, double, double>(xsd, n, fin,
-                                         [&](int k) { return W.U(k) + (st[k].L - 1) * ld; });
-            __syncthreads();
-            spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd,
-                                                ToRows<O, double, true, true>{RH, RS, ld});
-            __syncthreads();
-#pragma unroll 1
-            for (int k = 0; k < O; ++k) {
-                if (!on(fin, k)) continue;
-                const int64_t off = (int64_t)(st[k].L - 1) * ld;
-                double *SUk = W.SU(k) + off, *Kk = W.K(k) + off;
+        for (int k = 0; k < O; ++k)
+            if (on(live, k)) {
+                double *P = W.P(k), *P2 = W.P2(k);
                 for (int i = tid; i < n; i += NTA) {
-                    SUk[i] = RS[k * ld + i];
-                    Kk[i] = RH[k * ld + i];
+                    P[i] = i == st[k].jl ? 1.0 : 0.0;   // block 1 starts at e_j
+                    P2[i] = 0.0;
                 }
             }
-            __syncthreads();
-        }
-        // columns with nothing left to project are done once their last
-        // vector's images are stored
-        if (tid < O && on(go, tid) && !on(rest, tid)) st[tid].has_fin = 0;
-        if (!rest) continue;
-        // pass 2: S and H of the pending vectors (RS, RH; FP64 values: H only
-        // while block 1 runs)
-        stage_set<O, double, double>(xsd, n, rest, [&](int k) { return W.P(k); });
-        __syncthreads();
-        if (DERIVE || b1)
-            spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS, ld});
-        else
-            spmm_set<O, TM, double, false, true>(S, g, Hv, Sv, xsd, ToRows<O, double, false, true>{RH, RS, ld});
-        __syncthreads();
-        // pass 3: H of the pending chain vectors into RH2 (RH keeps H of the
-        // pending vectors, RS their S)
-        if (ch) {
-            stage_set<O, double, double>(xsd, n, ch, [&](int k) { return W.Z(k); });
-            __syncthreads();
-            spmm_set<O, TM, double, true, false>(S, g, Hv, Sv, xsd,
-                                                 ToRows<O, double, true, false>{RH2, nullptr, ld});
-        }
-        __syncthreads();
+        // (the chain starts at s_j, which the CG left in Z)
         if (tid < O) {
-            // this step's dot-sweep jobs of column tid
-            const AState &s = st[tid];
-            const bool r = on(rest, tid);
-            const int L = s.L;
-            const int La = r && s.has_pend ? L : 0;
-            const int Lb = r && s.kind != kNone ? L : 0;
-            DotJob &jb = sm.jobs[tid];
-            jb.V = W.SU(tid);
-            jb.LV = La > Lb ? La : Lb;
-            jb.x1 = W.P(tid);
-            jb.x2 = on(ch, tid) ? W.Z(tid) : RH + tid * ld;
-            jb.o1 = W.CA(tid);
-            jb.o2 = W.CB(tid, s.ping);
-            jb.W = W.T(tid);
-            jb.LW = on(ch, tid) ? s.kch : 0;
-            jb.y1 = W.Z(tid);
-            jb.y2 = RH2 + tid * ld;
-            jb.p1 = W.CAT(tid);
-            jb.p2 = W.CTB(tid, s.ping);
-            // and the scalars: pending^T S pending, (S pending)^T candidate
-            // (red[2k], red[2k + 1]); chain^T chain, chain^T (H chain)
-            // (red[32 + 2k], red[33 + 2k])
-            jb.Vx = r ? RS + tid * ld : nullptr;
-            jb.Wx = on(ch, tid) ? W.Z(tid) : nullptr;
-            jb.v1 = sm.red + 2 * tid;
-            jb.v2 = sm.red + 2 * tid + 1;
-            jb.w1 = sm.red + 32 + 2 * tid;
-            jb.w2 = sm.red + 33 + 2 * tid;
-        }
-        __syncthreads();
-        // dots: a = (S U)^T pending, b = (S U)^T candidate; chain a_T, b_T;
-        // the four scalars
-        if constexpr (4 * R <= 16) {
-            dot_sweep_rows<O, 4 * R>(sm.jobs, ld, n);
-        } else {
-            // regions of more than 1,024 rows: the scalars by a workgroup
-            // reduction, then the dot sweep in tasks of four vectors
-            block_reduce<NWA, 32, 2>([&](int grp, double (&v)[32]) __attribute__((always_inline)) {
-#pragma unroll
-                for (int k = 0; k < 32; ++k) v[k] = 0.0;
-#pragma unroll
-                for (int k = 0; k < O; ++k) {
-                    const DotJob &jb = sm.jobs[k];
-                    const double *X = grp == 0 ? jb.Vx : jb.Wx;
-                    if (!X) continue;
-                    const double *A1 = grp == 0 ? jb.x1 : jb.y1, *A2 = grp == 0 ? jb.x2 : jb.y2;
-                    double x0 = 0.0, x1 = 0.0;
-                    for (int i = tid; i < n; i += NTA) {
-                        const double e = X[i];
-                        x0 += e * A1[i];
-                        x1 += e * A2[i];
-                    }
-                    v[2 * k] = x0;
-                    v[2 * k + 1] = x1;
-                }
-            }, sm.scratch, sm.red);   // ends with a barrier
-            dot_sweep_cols<O>(sm.jobs, ld, n);
-        }
-        __syncthreads();
-
-        // decisions of column k, by thread k (the workspace kernel's rule)
-        if (tid < O && on(rest, tid)) {
             AState &s = st[tid];
-            const double *ca = W.CA(tid);
-            const double *cb = W.CB(tid, s.ping), *cp = W.CB(tid, s.ping ^ 1);
-            const double *cat = W.CAT(tid);
-            const double *ctb = W.CTB(tid, s.ping), *ctp = W.CTB(tid, s.ping ^ 1);
-            const double nu_p = sm.red[2 * tid], e_p = sm.red[2 * tid + 1];
-            const double nu_t = sm.red[32 + 2 * tid], e_t = sm.red[33 + 2 * tid];
-            const int L = s.L;
-            bool acc_u = false;
-            double beta = 1.0, f = 0.0;
-            if (s.has_pend) {
-                double asq = 0.0, tot = 0.0, ab = 0.0;
-                for (int m = 0; m < L; ++m) {
-                    const double cm = s.cp_scale * cp[m] + ca[m];
-                    asq += ca[m] * ca[m];
-                    tot += cm * cm;
-                    if (s.kind != kNone) ab += ca[m] * cb[m];
-                }
-                const double bb = nu_p - asq, b0 = bb + tot;
-                acc_u = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
-                if (acc_u) {
-                    beta = sqrt(bb);
-                    f = (e_p - ab) / beta;
-                }
-            }
-            bool acc_t = false;
-            double eta = 1.0, ft = 0.0;
-            if (s.kind == kChain) {
-                double asq = 0.0, tot = 0.0, ab = 0.0;
-                for (int m = 0; m < s.kch; ++m) {
-                    const double cm = s.ctp_scale * ctp[m] + cat[m];
-                    asq += cat[m] * cat[m];
-                    tot += cm * cm;
-                    ab += cat[m] * ctb[m];
-                }
-                const double ee = nu_t - asq, e0 = ee + tot;
-                acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
-                if (acc_t) {
-                    eta = sqrt(ee);
-                    ft = (e_t - ab) / eta;
-                }
-            }
-            s.acc_u = acc_u;
-            s.acc_t = acc_t;
-            s.new_pend = (s.kind == kB1 && acc_u) || (s.kind == kChain && acc_t);
-            s.new_chain = s.need_z && acc_t;
-            s.inv_b = 1.0 / beta;
-            s.inv_e = 1.0 / eta;
-            s.f = f;
-            s.ft = ft;
-            s.sc = s.kind == kB1 ? s.inv_b : 1.0;
+            s.L = 0;
+            s.nb1 = 0;
+            s.kch = 0;
+            s.tq = 0;
+            s.ping = 0;
+            s.chain_live = q > 0;
+            s.np = p > 0 ? 1 : 0;
+            s.pk1 = p > 0;
+            s.cp_scale = s.cp2_scale = s.ctp_scale = 1.0;
         }
-        __syncthreads();
-
-        // update sweep: finish u and t, project the candidates once
-#pragma unroll 1
-        for (int k = 0; k < O; ++k) {
-            if (!on(rest, k)) continue;
-            const AState &s = st[k];
-            const int L = s.L;
-            const int kk = s.kch;
-            const bool acc_u = s.acc_u, acc_t = s.acc_t, new_pend = s.new_pend,
-                       new_chain = s.new_chain, chain = s.kind == kChain;
-            const double inv_b = s.inv_b, inv_e = s.inv_e, f = s.f, ft = s.ft, sc = s.sc;
-            double *U = W.U(k), *T = W.T(k), *P = W.P(k), *Z = W.Z(k);
-            double *SUd = W.SU(k), *Kd = W.K(k);
-            // H image of the candidate source: H z (chain) or H of the pending vector
-            const double *D = (chain ? RH2 : RH) + k * ld;
-            const double *RSk = RS + k * ld, *RHk = RH + k * ld;
-            double sa[R], sb[R], ta[R], tb[R];
-            comb2_rows<R>(U, ld, (acc_u || new_pend) ? L : 0, W.CA(k), W.CB(k, s.ping), n, sa, sb);
-            comb2_rows<R>(T, ld, acc_t ? kk : 0, W.CAT(k), W.CTB(k, s.ping), n, ta, tb);
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const int i = tid + rr * NTA;
-                if (i < n) {
-                    const double up = P[i], zt = Z[i], hv = D[i];
-                    const double u = (up - sa[rr]) * inv_b;
-                    const double cand = chain ? zt : hv;
-                    const double nl = (cand - sb[rr] - (acc_u ? f * u : 0.0)) * sc;
-                    const double t = (zt - ta[rr]) * inv_e;
-                    const double nz = (hv - tb[rr] - ft * t) * inv_e;
-                    if (acc_t) T[kk * ld + i] = t;
-                    if (acc_u) {
-                        U[L * ld + i] = u;
-                        if (DERIVE) {
-                            SUd[L * ld + i] = RSk[i] * inv_b;
-                            Kd[L * ld + i] = RHk[i] * inv_b;
+        const float *Hv = S.Hf, *Sv = S.Sf;
+        auto src = [&](int k, int kind, int m) __attribute__((always_inline)) -> const double * {
+            return kind == kSrcH ? RH + k * ld : kind == kSrcT ? W.T(k) + (int64_t)m * ld : W.Z(k);
+        };
+        for (;;) {
+            __syncthreads();
+            // plan of column tid: the sources of this step's candidates
+            if (tid < O) {
+                AState &s = st[tid];
+                int nc = 0, k3 = kSrcNone, m3 = 0, k4 = kSrcNone, m4 = 0;
+                if (s.live) {
+                    if (s.np >= 1 && s.pk1 && s.nb1 + 1 < p) {
+                        nc = 1;
+                        k3 = kSrcH;
+                    } else {
+                        // block 2: finished chain vectors in chain order, then
+                        // the chain vector this step finishes
+                        for (int m = s.tq; nc < 2; ++m) {
+                            const int kind = m < s.kch ? kSrcT : (m == s.kch && s.chain_live) ? kSrcZ : kSrcNone;
+                            if (kind == kSrcNone) break;
+                            if (nc == 0) {
+                                k3 = kind;
+                                m3 = m;
+                            } else {
+                                k4 = kind;
+                                m4 = m;
+                            }
+                            ++nc;
                         }
                     }
-                    P[i] = new_pend ? nl : 0.0;
-                    if (new_chain) Z[i] = nz;
+                    if (s.np == 0 && nc == 0 && !s.chain_live) s.live = 0;
                 }
+                s.nc = nc;
+                s.c3k = k3;
+                s.c3m = m3;
+                s.c4k = k4;
+                s.c4m = m4;
+            }
+            __syncthreads();
+            unsigned go = 0, m1 = 0, m2 = 0, ch = 0;
+#pragma unroll
+            for (int k = 0; k < O; ++k) {
+                const AState &s = st[k];
+                if (!s.live) continue;
+                go |= 1u << k;
+                if (s.np >= 1) m1 |= 1u << k;
+                if (s.np == 2) m2 |= 1u << k;
+                if (s.chain_live) ch |= 1u << k;
+            }
+            if (!go) break;
+            // S and H of the pending vectors (RS, RH; RSb, RHb), H of the chain vectors (RH2)
+            if (m1) {
+                stage_set<O, double, double>(xsd, n, m1, [&](int k) { return W.P(k); });
+                __syncthreads();
+                spmm_set<O, float, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS, ld});
+                __syncthreads();
+            }
+            if (m2) {
+                stage_set<O, double, double>(xsd, n, m2, [&](int k) { return W.P2(k); });
+                __syncthreads();
+                spmm_set<O, float, double, true, true>(S, g, Hv, Sv, xsd,
+                                                       ToRows<O, double, true, true>{RHb, RSb, ld});
+                __syncthreads();
+            }
+            if (ch) {
+                stage_set<O, double, double>(xsd, n, ch, [&](int k) { return W.Z(k); });
+                __syncthreads();
+                spmm_set<O, float, double, true, false>(S, g, Hv, Sv, xsd,
+                                                        ToRows<O, double, true, false>{RH2, nullptr, ld});
+                __syncthreads();
+            }
+            if (tid < O) {
+                const AState &s = st[tid];
+                PJob &jb = sm.pjobs[tid];
+                const bool a = s.live;
+                jb.V = W.SU(tid);
+                jb.LV = a && (s.np > 0 || s.nc > 0) ? s.L : 0;
+                jb.x[0] = a && s.np >= 1 ? W.P(tid) : nullptr;
+                jb.x[1] = a && s.np == 2 ? W.P2(tid) : nullptr;
+                jb.x[2] = a && s.nc >= 1 ? src(tid, s.c3k, s.c3m) : nullptr;
+                jb.x[3] = a && s.nc == 2 ? src(tid, s.c4k, s.c4m) : nullptr;
+                jb.o[0] = W.CA(tid);
+                jb.o[1] = W.CA2(tid);
+                jb.o[2] = W.CB(tid, s.ping);
+                jb.o[3] = W.CB4(tid, s.ping);
+                jb.Vx[0] = a && s.np >= 1 ? RS + tid * ld : nullptr;
+                jb.Vx[1] = a && s.np == 2 ? RSb + tid * ld : nullptr;
+                jb.W = W.T(tid);
+                jb.LW = a && s.chain_live ? s.kch : 0;
+                jb.y1 = W.Z(tid);
+                jb.y2 = RH2 + tid * ld;
+                jb.p1 = W.CAT(tid);
+                jb.p2 = W.CTB(tid, s.ping);
+                jb.Wx = a && s.chain_live ? W.Z(tid) : nullptr;
+                jb.sc = sm.psc + 12 * tid;
+            }
+            __syncthreads();
+            // a1, a2 = (S U)^T p1, p2; b3, b4 = (S U)^T c3, c4; chain a_T, b_T;
+            // (S p1), (S p2) against p1, p2, c3, c4; z^T z, z^T H z
+            dot_sweep_pairs<O, 4 * R>(sm.pjobs, ld, n);
+            __syncthreads();
+
+            // decisions of column k, by thread k
+            if (tid < O && st[tid].live) {
+                AState &s = st[tid];
+                const double *sc = sm.psc + 12 * tid;
+                const double *a1 = W.CA(tid), *a2 = W.CA2(tid);
+                const double *b3 = W.CB(tid, s.ping), *b4 = W.CB4(tid, s.ping);
+                const double *cp1 = W.CB(tid, s.ping ^ 1), *cp2 = W.CB4(tid, s.ping ^ 1);
+                const double *cat = W.CAT(tid);
+                const double *ctb = W.CTB(tid, s.ping), *ctp = W.CTB(tid, s.ping ^ 1);
+                const int L = s.L;
+                // the first pending vector: beta1^2 = p1^T S p1 - |a1|^2
+                bool acc1 = false;
+                double ib1 = 1.0;
+                if (s.np >= 1) {
+                    double asq = 0.0, tot = 0.0;
+                    for (int m = 0; m < L; ++m) {
+                        const double cm = s.cp_scale * cp1[m] + a1[m];
+                        asq += a1[m] * a1[m];
+                        tot += cm * cm;
+                    }
+                    const double bb = sc[0] - asq, b0 = bb + tot;
+                    acc1 = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
+                    if (acc1) ib1 = 1.0 / sqrt(bb);
+                }
+                // the second: g = u1^T S p2, beta2^2 = p2^T S p2 - |a2|^2 - g^2
+                bool acc2 = false;
+                double ib2 = 1.0, gg = 0.0;
+                if (s.np == 2) {
+                    double asq = 0.0, tot = 0.0, x = 0.0;
+                    for (int m = 0; m < L; ++m) {
+                        const double cm = s.cp2_scale * cp2[m] + a2[m];
+                        asq += a2[m] * a2[m];
+                        tot += cm * cm;
+                        x += a1[m] * a2[m];
+                    }
+                    gg = acc1 ? (sc[1] - x) * ib1 : 0.0;
+                    const double bb = sc[5] - asq - gg * gg, b0 = bb + tot + gg * gg;
+                    acc2 = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
+                    if (acc2) ib2 = 1.0 / sqrt(bb);
+                }
+                // the candidates' coefficients on u1 and u2
+                double f[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+                for (int c = 0; c < s.nc; ++c) {
+                    const double *b = c == 0 ? b3 : b4;
+                    double ab1 = 0.0, ab2 = 0.0;
+                    for (int m = 0; m < L; ++m) {
+                        ab1 += a1[m] * b[m];
+                        ab2 += a2[m] * b[m];
+                    }
+                    f[c][0] = acc1 ? (sc[2 + c] - ab1) * ib1 : 0.0;
+                    f[c][1] = acc2 ? (sc[6 + c] - ab2 - gg * f[c][0]) * ib2 : 0.0;
+                }
+                // the chain vector
+                bool acc_t = false;
+                double eta = 1.0, ft = 0.0;
+                if (s.chain_live) {
+                    double asq = 0.0, tot = 0.0, ab = 0.0;
+                    for (int m = 0; m < s.kch; ++m) {
+                        const double cm = s.ctp_scale * ctp[m] + cat[m];
+                        asq += cat[m] * cat[m];
+                        tot += cm * cm;
+                        ab += cat[m] * ctb[m];
+                    }
+                    const double ee = sc[8] - asq, e0 = ee + tot;
+                    acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
+                    if (acc_t) {
+                        eta = sqrt(ee);
+                        ft = (sc[9] - ab) / eta;
+                    }
+                }
+                // a block-1 candidate needs its source accepted, the chain
+                // vector of the step its own acceptance
+                int nv = s.nc;
+                if (nv >= 1 && ((s.c3k == kSrcH && !acc1) || (s.c3k == kSrcZ && !acc_t))) nv = 0;
+                if (nv == 2 && s.c4k == kSrcZ && !acc_t) nv = 1;
+                s.acc_u = acc1;
+                s.acc2 = acc2;
+                s.inv_b = ib1;
+                s.inv_b2 = ib2;
+                s.g = gg;
+                s.f31 = f[0][0];
+                s.f32 = f[0][1];
+                s.f41 = f[1][0];
+                s.f42 = f[1][1];
+                s.nv = nv;
+                s.sc = s.c3k == kSrcH ? ib1 : 1.0;
+                s.acc_t = acc_t;
+                s.inv_e = 1.0 / eta;
+                s.ft = ft;
+                s.new_chain = s.chain_live && acc_t && s.kch + 1 < q;
+            }
+            __syncthreads();
+
+            // update sweep: finish u1, u2 and t, project the candidates once
+#pragma unroll 1
+            for (int k = 0; k < O; ++k) {
+                if (!on(go, k)) continue;
+                const AState &s = st[k];
+                const int L = s.L, kk = s.kch, nv = s.nv;
+                const bool acc1 = s.acc_u, acc2 = s.acc2, acc_t = s.acc_t, new_chain = s.new_chain;
+                const double ib1 = s.inv_b, ib2 = s.inv_b2, gg = s.g, ie = s.inv_e, ft = s.ft;
+                const double f31 = s.f31, f32 = s.f32, f41 = s.f41, f42 = s.f42, sc3 = s.sc;
+                double *U = W.U(k), *T = W.T(k), *P = W.P(k), *P2 = W.P2(k), *Z = W.Z(k);
+                double *SUd = W.SU(k), *Kd = W.K(k);
+                const double *C3 = nv >= 1 ? src(k, s.c3k, s.c3m) : Z;
+                const double *C4 = nv == 2 ? src(k, s.c4k, s.c4m) : Z;
+                const double *RSk = RS + k * ld, *RHk = RH + k * ld;
+                const double *RSbk = RSb + k * ld, *RHbk = RHb + k * ld, *RH2k = RH2 + k * ld;
+                const int l2 = L + (acc1 ? 1 : 0);
+                double s1[R], s2[R], s3[R], s4[R], ta[R], tb[R];
+                comb4_rows<R>(U, ld, (acc1 || acc2 || nv > 0) ? L : 0, W.CA(k), W.CA2(k), W.CB(k, s.ping),
+                              W.CB4(k, s.ping), n, s1, s2, s3, s4);
+                comb2_rows<R>(T, ld, acc_t ? kk : 0, W.CAT(k), W.CTB(k, s.ping), n, ta, tb);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int i = tid + rr * NTA;
+                    if (i < n) {
+                        const double u1 = acc1 ? (P[i] - s1[rr]) * ib1 : 0.0;
+                        const double u2 = acc2 ? (P2[i] - s2[rr] - gg * u1) * ib2 : 0.0;
+                        const double c3 = C3[i], c4 = C4[i], zt = Z[i];
+                        const double n1 = (c3 - s3[rr] - f31 * u1 - f32 * u2) * sc3;
+                        const double n2 = c4 - s4[rr] - f41 * u1 - f42 * u2;
+                        const double t = (zt - ta[rr]) * ie;
+                        const double nz = (RH2k[i] - tb[rr] - ft * t) * ie;
+                        const double rs1 = acc1 ? RSk[i] * ib1 : 0.0, rh1 = acc1 ? RHk[i] * ib1 : 0.0;
+                        if (acc_t) T[kk * ld + i] = t;
+                        if (acc1) {
+                            U[L * ld + i] = u1;
+                            SUd[L * ld + i] = rs1;
+                            Kd[L * ld + i] = rh1;
+                        }
+                        if (acc2) {
+                            U[l2 * ld + i] = u2;
+                            SUd[l2 * ld + i] = (RSbk[i] - gg * rs1) * ib2;
+                            Kd[l2 * ld + i] = (RHbk[i] - gg * rh1) * ib2;
+                        }
+                        P[i] = nv >= 1 ? n1 : 0.0;
+                        P2[i] = nv == 2 ? n2 : 0.0;
+                        if (new_chain) Z[i] = nz;
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < O && st[tid].live) {
+                AState &s = st[tid];
+                // first-pass coefficients of the new pending vectors on u1, u2
+                double *b3 = W.CB(tid, s.ping), *b4 = W.CB4(tid, s.ping);
+                int l = s.L;
+                if (s.acc_u) {
+                    b3[l] = s.f31;
+                    b4[l] = s.f41;
+                    ++l;
+                }
+                if (s.acc2) {
+                    b3[l] = s.f32;
+                    b4[l] = s.f42;
+                    ++l;
+                }
+                if (s.acc_t) W.CTB(tid, s.ping)[s.kch] = s.ft;
+                if (s.np >= 1 && s.pk1 && s.acc_u) ++s.nb1;   // a rejected block-1 vector ends block 1
+                if (s.c3k == kSrcT || s.c3k == kSrcZ) s.tq += s.nv;
+                if (s.chain_live) {
+                    if (s.acc_t) {
+                        ++s.kch;
+                        s.chain_live = s.kch < q;
+                    } else {
+                        s.chain_live = 0;
+                    }
+                }
+                s.L = l;
+                s.cp_scale = s.sc;
+                s.cp2_scale = 1.0;
+                s.ctp_scale = s.inv_e;
+                s.np = s.nv;
+                s.pk1 = s.nv >= 1 && s.c3k == kSrcH;
+                s.ping ^= 1;
             }
         }
-        __syncthreads();
-        if (tid < O && on(rest, tid)) {
-            AState &s = st[tid];
-            if (s.acc_u) W.CB(tid, s.ping)[s.L] = s.f;   // coefficient of the new pending vector on u_L
-            if (s.acc_t) W.CTB(tid, s.ping)[s.kch] = s.ft;
-            if (s.kind == kB1) {
-                if (s.acc_u) ++s.nb1;
-                else s.b1_live = 0;
+    } else {
+    #pragma unroll 1
+        for (int k = 0; k < O; ++k)
+            if (on(live, k)) {
+                double *P = W.P(k);
+                for (int i = tid; i < n; i += NTA) P[i] = i == st[k].jl ? 1.0 : 0.0;   // block 1 starts at e_j
             }
-            if (s.kind == kChain) {
-                if (s.acc_t) {
-                    ++s.kch;
-                    s.chain_live = s.kch < q;
-                } else {
-                    s.chain_live = 0;
+        // (block 2 starts at s_j, which the CG left in Z)
+        if (tid < O) {
+            AState &s = st[tid];
+            s.L = 0;
+            s.nb1 = p > 0 ? 1 : 0;
+            s.kch = 0;
+            s.ping = 0;
+            s.b1_live = 1;
+            s.chain_live = q > 0;
+            s.has_fin = 0;
+            s.has_pend = p > 0;
+            s.cp_scale = s.ctp_scale = 1.0;
+        }
+        const TM *Hv = PREC ? (const TM *)S.Hf : (const TM *)S.Hd;
+        const TM *Sv = PREC ? (const TM *)S.Sf : (const TM *)S.Sd;
+        // With FP32 operator values (FP64 sums: this kernel has no FP32-sum
+        // mode) the images of a finished vector u = (p - U a) / beta are taken as
+        // S p / beta and H p / beta from the pass over its pending form p: the
+        // basis is orthonormal in the metric of the rounded S that every product
+        // uses, so the dropped (S U) a / beta and K a / beta are second-pass
+        // corrections at the FP64 rounding level, and pass 1 disappears.  With
+        // FP64 values every image is applied to u itself.
+        constexpr bool DERIVE = PREC == 2;
+        for (;;) {
+            __syncthreads();
+            if (tid < O) {
+                AState &s = st[tid];
+                s.kind = (s.b1_live && s.nb1 < p) ? kB1 : s.chain_live ? kChain : kNone;
+                s.need_z = s.kind == kChain && s.kch + 1 < q;
+                s.tail = s.kind == kNone && !s.has_pend;
+                if (!s.live || (!s.has_fin && !s.has_pend && s.kind == kNone)) s.live = 0;
+            }
+            __syncthreads();
+            unsigned go = 0, fin = 0, b1 = 0, ch = 0, rest = 0;
+    #pragma unroll
+            for (int k = 0; k < O; ++k) {
+                const AState &s = st[k];
+                if (!s.live) continue;
+                go |= 1u << k;
+                if (s.has_fin) fin |= 1u << k;
+                if (!s.tail) rest |= 1u << k;
+                if (!s.tail && s.kind == kB1) b1 |= 1u << k;
+                if (!s.tail && s.kind == kChain) ch |= 1u << k;
+            }
+            if (!go) break;
+
+            // pass 1: H and S of the vectors finished in the previous step
+            if (!DERIVE && fin) {
+                stage_set<O, double, double>(xsd, n, fin,
+                                             [&](int k) { return W.U(k) + (st[k].L - 1) * ld; });
+                __syncthreads();
+                spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd,
+                                                    ToRows<O, double, true, true>{RH, RS, ld});
+                __syncthreads();
+    #pragma unroll 1
+                for (int k = 0; k < O; ++k) {
+                    if (!on(fin, k)) continue;
+                    const int64_t off = (int64_t)(st[k].L - 1) * ld;
+                    double *SUk = W.SU(k) + off, *Kk = W.K(k) + off;
+                    for (int i = tid; i < n; i += NTA) {
+                        SUk[i] = RS[k * ld + i];
+                        Kk[i] = RH[k * ld + i];
+                    }
+                }
+                __syncthreads();
+            }
+            // columns with nothing left to project are done once their last
+            // vector's images are stored
+            if (tid < O && on(go, tid) && !on(rest, tid)) st[tid].has_fin = 0;
+            if (!rest) continue;
+            // pass 2: S and H of the pending vectors (RS, RH; FP64 values: H only
+            // while block 1 runs)
+            stage_set<O, double, double>(xsd, n, rest, [&](int k) { return W.P(k); });
+            __syncthreads();
+            if (DERIVE || b1)
+                spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS, ld});
+            else
+                spmm_set<O, TM, double, false, true>(S, g, Hv, Sv, xsd, ToRows<O, double, false, true>{RH, RS, ld});
+            __syncthreads();
+            // pass 3: H of the pending chain vectors into RH2 (RH keeps H of the
+            // pending vectors, RS their S)
+            if (ch) {
+                stage_set<O, double, double>(xsd, n, ch, [&](int k) { return W.Z(k); });
+                __syncthreads();
+                spmm_set<O, TM, double, true, false>(S, g, Hv, Sv, xsd,
+                                                     ToRows<O, double, true, false>{RH2, nullptr, ld});
+            }
+            __syncthreads();
+            if (tid < O) {
+                // this step's dot-sweep jobs of column tid
+                const AState &s = st[tid];
+                const bool r = on(rest, tid);
+                const int L = s.L;
+                const int La = r && s.has_pend ? L : 0;
+                const int Lb = r && s.kind != kNone ? L : 0;
+                DotJob &jb = sm.jobs[tid];
+                jb.V = W.SU(tid);
+                jb.LV = La > Lb ? La : Lb;
+                jb.x1 = W.P(tid);
+                jb.x2 = on(ch, tid) ? W.Z(tid) : RH + tid * ld;
+                jb.o1 = W.CA(tid);
+                jb.o2 = W.CB(tid, s.ping);
+                jb.W = W.T(tid);
+                jb.LW = on(ch, tid) ? s.kch : 0;
+                jb.y1 = W.Z(tid);
+                jb.y2 = RH2 + tid * ld;
+                jb.p1 = W.CAT(tid);
+                jb.p2 = W.CTB(tid, s.ping);
+                // and the scalars: pending^T S pending, (S pending)^T candidate
+                // (red[2k], red[2k + 1]); chain^T chain, chain^T (H chain)
+                // (red[32 + 2k], red[33 + 2k])
+                jb.Vx = r ? RS + tid * ld : nullptr;
+                jb.Wx = on(ch, tid) ? W.Z(tid) : nullptr;
+                jb.v1 = sm.red + 2 * tid;
+                jb.v2 = sm.red + 2 * tid + 1;
+                jb.w1 = sm.red + 32 + 2 * tid;
+                jb.w2 = sm.red + 33 + 2 * tid;
+            }
+            __syncthreads();
+            // dots: a = (S U)^T pending, b = (S U)^T candidate; chain a_T, b_T;
+            // the four scalars
+            if constexpr (4 * R <= 16) {
+                dot_sweep_rows<O, 4 * R>(sm.jobs, ld, n);
+            } else {
+                // regions of more than 1,024 rows: the scalars by a workgroup
+                // reduction, then the dot sweep in tasks of four vectors
+                block_reduce<NWA, 32, 2>([&](int grp, double (&v)[32]) __attribute__((always_inline)) {
+    #pragma unroll
+                    for (int k = 0; k < 32; ++k) v[k] = 0.0;
+    #pragma unroll
+                    for (int k = 0; k < O; ++k) {
+                        const DotJob &jb = sm.jobs[k];
+                        const double *X = grp == 0 ? jb.Vx : jb.Wx;
+                        if (!X) continue;
+                        const double *A1 = grp == 0 ? jb.x1 : jb.y1, *A2 = grp == 0 ? jb.x2 : jb.y2;
+                        double x0 = 0.0, x1 = 0.0;
+                        for (int i = tid; i < n; i += NTA) {
+                            const double e = X[i];
+                            x0 += e * A1[i];
+                            x1 += e * A2[i];
+                        }
+                        v[2 * k] = x0;
+                        v[2 * k + 1] = x1;
+                    }
+                }, sm.scratch, sm.red);   // ends with a barrier
+                dot_sweep_cols<O>(sm.jobs, ld, n);
+            }
+            __syncthreads();
+
+            // decisions of column k, by thread k (the workspace kernel's rule)
+            if (tid < O && on(rest, tid)) {
+                AState &s = st[tid];
+                const double *ca = W.CA(tid);
+                const double *cb = W.CB(tid, s.ping), *cp = W.CB(tid, s.ping ^ 1);
+                const double *cat = W.CAT(tid);
+                const double *ctb = W.CTB(tid, s.ping), *ctp = W.CTB(tid, s.ping ^ 1);
+                const double nu_p = sm.red[2 * tid], e_p = sm.red[2 * tid + 1];
+                const double nu_t = sm.red[32 + 2 * tid], e_t = sm.red[33 + 2 * tid];
+                const int L = s.L;
+                bool acc_u = false;
+                double beta = 1.0, f = 0.0;
+                if (s.has_pend) {
+                    double asq = 0.0, tot = 0.0, ab = 0.0;
+                    for (int m = 0; m < L; ++m) {
+                        const double cm = s.cp_scale * cp[m] + ca[m];
+                        asq += ca[m] * ca[m];
+                        tot += cm * cm;
+                        if (s.kind != kNone) ab += ca[m] * cb[m];
+                    }
+                    const double bb = nu_p - asq, b0 = bb + tot;
+                    acc_u = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
+                    if (acc_u) {
+                        beta = sqrt(bb);
+                        f = (e_p - ab) / beta;
+                    }
+                }
+                bool acc_t = false;
+                double eta = 1.0, ft = 0.0;
+                if (s.kind == kChain) {
+                    double asq = 0.0, tot = 0.0, ab = 0.0;
+                    for (int m = 0; m < s.kch; ++m) {
+                        const double cm = s.ctp_scale * ctp[m] + cat[m];
+                        asq += cat[m] * cat[m];
+                        tot += cm * cm;
+                        ab += cat[m] * ctb[m];
+                    }
+                    const double ee = nu_t - asq, e0 = ee + tot;
+                    acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
+                    if (acc_t) {
+                        eta = sqrt(ee);
+                        ft = (e_t - ab) / eta;
+                    }
+                }
+                s.acc_u = acc_u;
+                s.acc_t = acc_t;
+                s.new_pend = (s.kind == kB1 && acc_u) || (s.kind == kChain && acc_t);
+                s.new_chain = s.need_z && acc_t;
+                s.inv_b = 1.0 / beta;
+                s.inv_e = 1.0 / eta;
+                s.f = f;
+                s.ft = ft;
+                s.sc = s.kind == kB1 ? s.inv_b : 1.0;
+            }
+            __syncthreads();
+
+            // update sweep: finish u and t, project the candidates once
+    #pragma unroll 1
+            for (int k = 0; k < O; ++k) {
+                if (!on(rest, k)) continue;
+                const AState &s = st[k];
+                const int L = s.L;
+                const int kk = s.kch;
+                const bool acc_u = s.acc_u, acc_t = s.acc_t, new_pend = s.new_pend,
+                           new_chain = s.new_chain, chain = s.kind == kChain;
+                const double inv_b = s.inv_b, inv_e = s.inv_e, f = s.f, ft = s.ft, sc = s.sc;
+                double *U = W.U(k), *T = W.T(k), *P = W.P(k), *Z = W.Z(k);
+                double *SUd = W.SU(k), *Kd = W.K(k);
+                // H image of the candidate source: H z (chain) or H of the pending vector
+                const double *D = (chain ? RH2 : RH) + k * ld;
+                const double *RSk = RS + k * ld, *RHk = RH + k * ld;
+                double sa[R], sb[R], ta[R], tb[R];
+                comb2_rows<R>(U, ld, (acc_u || new_pend) ? L : 0, W.CA(k), W.CB(k, s.ping), n, sa, sb);
+                comb2_rows<R>(T, ld, acc_t ? kk : 0, W.CAT(k), W.CTB(k, s.ping), n, ta, tb);
+    #pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int i = tid + rr * NTA;
+                    if (i < n) {
+                        const double up = P[i], zt = Z[i], hv = D[i];
+                        const double u = (up - sa[rr]) * inv_b;
+                        const double cand = chain ? zt : hv;
+                        const double nl = (cand - sb[rr] - (acc_u ? f * u : 0.0)) * sc;
+                        const double t = (zt - ta[rr]) * inv_e;
+                        const double nz = (hv - tb[rr] - ft * t) * inv_e;
+                        if (acc_t) T[kk * ld + i] = t;
+                        if (acc_u) {
+                            U[L * ld + i] = u;
+                            if (DERIVE) {
+                                SUd[L * ld + i] = RSk[i] * inv_b;
+                                Kd[L * ld + i] = RHk[i] * inv_b;
+                            }
+                        }
+                        P[i] = new_pend ? nl : 0.0;
+                        if (new_chain) Z[i] = nz;
+                    }
                 }
             }
-            if (s.acc_u) ++s.L;
-            s.cp_scale = s.sc;
-            s.ctp_scale = s.inv_e;
-            s.has_fin = DERIVE ? 0 : s.acc_u;
-            s.has_pend = s.new_pend;
-            s.ping ^= 1;
+            __syncthreads();
+            if (tid < O && on(rest, tid)) {
+                AState &s = st[tid];
+                if (s.acc_u) W.CB(tid, s.ping)[s.L] = s.f;   // coefficient of the new pending vector on u_L
+                if (s.acc_t) W.CTB(tid, s.ping)[s.kch] = s.ft;
+                if (s.kind == kB1) {
+                    if (s.acc_u) ++s.nb1;
+                    else s.b1_live = 0;
+                }
+                if (s.kind == kChain) {
+                    if (s.acc_t) {
+                        ++s.kch;
+                        s.chain_live = s.kch < q;
+                    } else {
+                        s.chain_live = 0;
+                    }
+                }
+                if (s.acc_u) ++s.L;
+                s.cp_scale = s.sc;
+                s.ctp_scale = s.inv_e;
+                s.has_fin = DERIVE ? 0 : s.acc_u;
+                s.has_pend = s.new_pend;
+                s.ping ^= 1;
+            }
         }
     }
     __syncthreads();   // basis writes visible to the whole workgroup
@@ -1207,6 +1662,8 @@ __global__ void __launch_bounds__(NTA, 2) k_basis_a(DevSystem S, DevJob J)
     __shared__ int s_idx;
     __shared__ AState sst[O];
     __shared__ DotJob sjobs[O];
+    __shared__ PJob spjobs[O];
+    __shared__ double spsc[O * 12];
     __shared__ double scratch[NWA * 64];
     __shared__ double red[64];
     SmemA sm;
@@ -1217,6 +1674,8 @@ __global__ void __launch_bounds__(NTA, 2) k_basis_a(DevSystem S, DevJob J)
     sm.red = red;
     sm.st = sst;
     sm.jobs = sjobs;
+    sm.pjobs = spjobs;
+    sm.psc = spsc;
     double *ws = J.ws + (int64_t)blockIdx.x * J.ws_stride;
     drain_queues_raw(J, &s_idx, [&](int idx) __attribute__((always_inline)) {
         basis_atom<O, R, PREC>(S, J, sm, idx, ws);
