@@ -280,20 +280,40 @@ __device__ __forceinline__ void spmm_set(const DevSystem &S, const Col &g, const
     }
 }
 
-// Stage column vectors into xs (LDS [row][column]): xs[i][k] = src(k)[i]
-// for the columns in `mask`, zero for the others (rows read column by
-// column, so the global reads coalesce).
-template <int O, typename TX, typename TS, typename F>
-__device__ __forceinline__ void stage_set(TX *xs, int n, unsigned mask, F &&src)
+// Stage the vectors src(k) of the columns in `mask` into xs as [row][column]
+// (zeros for the other columns).  The thread's rows are i = tid + rr * NTA,
+// rr < R (n <= R * NTA); the loads of KB columns are issued together before
+// their LDS writes, so a batch costs one memory round trip where a loop over
+// the rows of one column after another waits for every load in turn.  `safe`
+// is any readable vector of n entries, read in place of the columns outside
+// the mask (whose src(k) need not be valid).
+template <int O, int R, typename TX, typename TS, typename F>
+__device__ __forceinline__ void stage_set(TX *xs, int n, unsigned mask, const TS *safe, F &&src)
 {
-#pragma unroll 1
-    for (int k = 0; k < O; ++k) {
-        if ((mask >> k) & 1u) {
-            const auto *v = src(k);
-            for (int i = threadIdx.x; i < n; i += NTA) xs[i * O + k] = (TX)v[i];
-        } else {
-            for (int i = threadIdx.x; i < n; i += NTA) xs[i * O + k] = (TX)0;
+    constexpr int KB = 3;
+#pragma unroll
+    for (int k0 = 0; k0 < O; k0 += KB) {
+        TX v[KB][R];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            if (k0 + kk >= O) continue;
+            const int k = k0 + kk;
+            const bool on_k = (mask >> k) & 1u;
+            const TS *p = on_k ? (const TS *)src(k) : safe;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int i = threadIdx.x + rr * NTA;
+                const TS x = p[i < n ? i : 0];
+                v[kk][rr] = (on_k && i < n) ? (TX)x : (TX)0;
+            }
         }
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk)
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int i = threadIdx.x + rr * NTA;
+                if (k0 + kk < O && i < n) xs[i * O + k0 + kk] = v[kk][rr];
+            }
     }
 }
 
@@ -586,7 +606,7 @@ struct SmemA {
 __device__ __forceinline__ bool on(unsigned m, int k) { return (m >> k) & 1u; }
 
 template <int O, int R, int PREC>
-__device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm, int gpos,
+__device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm, int gpos,
                            double *ws)
 {
     using TM = typename std::conditional<PREC != 0, float, double>::type;
@@ -669,7 +689,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
     // FP64 true residual D = e_j - S x of the columns in `mask`; |D|^2 -> red[k]
     auto true_residual = [&](unsigned mask) __attribute__((always_inline)) {
         __syncthreads();
-        stage_set<O, double, double>(xsd, n, mask, [&](int k) { return W.Z(k); });
+        stage_set<O, R, double, double>(xsd, n, mask, W.Z(0), [&](int k) { return W.Z(k); });
         __syncthreads();
         spmm_set<O, double, double, false, true>(S, g, S.Hd, S.Sd, xsd,
                                                  ToRows<O, double, false, true>{RH, RS, ld});
@@ -730,7 +750,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                         sqrt(st[k].rho2) > J.cg_tol)
                         a2 |= 1u << k;
                 if (!a2) break;
-                stage_set<O, double, double>(xsd, n, a2, [&](int k) { return W.P(k); });
+                stage_set<O, R, double, double>(xsd, n, a2, W.Z(0), [&](int k) { return W.P(k); });
                 __syncthreads();
                 spmm_set<O, double, double, false, true>(S, g, S.Hd, S.Sd, xsd,
                                                          ToRows<O, double, false, true>{RH, RS, ld});
@@ -864,16 +884,42 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                     if (on(pm, k) && st[k].status == 0 && st[k].it < n && sqrtf(st[k].rrf) > thr[k])
                         a2 |= 1u << k;
                 if (!a2) break;
-                stage_set<O, float, float>(xsf, n, a2, [&](int k) { return W.F(k, 1); });
+                stage_set<O, R, float, float>(xsf, n, a2, W.F(0, 1), [&](int k) { return W.F(k, 1); });
                 __syncthreads();
                 spmm_set<O, float, float, false, true>(S, g, S.Hf, S.Sf, xsf,
                                                        ToRows<O, float, false, true>{nullptr, RSf, ld});
                 __syncthreads();
-                sum_cols<O>(a2, [&](int k) __attribute__((always_inline)) {
-                    const float *pf = W.F(k, 1);
-                    float acc = 0.0f;
-                    for (int i = tid; i < n; i += NTA) acc += pf[i] * RSf[k * ld + i];
-                    return (double)acc;
+                // p^T q, three columns' loads per round trip
+                block_reduce<NWA, 16, 1>([&](int, double (&w)[16]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) w[k] = 0.0;
+                    constexpr int KB = 3;
+#pragma unroll
+                    for (int k0 = 0; k0 < O; k0 += KB) {
+                        float pv[KB][R], qv[KB][R];
+#pragma unroll
+                        for (int kk = 0; kk < KB; ++kk) {
+                            if (k0 + kk >= O) continue;
+                            const int k = k0 + kk;
+                            const float *pf = W.F(k, 1), *qf = RSf + k * ld;
+#pragma unroll
+                            for (int rr = 0; rr < R; ++rr) {
+                                const int i = tid + rr * NTA, ii = i < n ? i : 0;
+                                pv[kk][rr] = pf[ii];
+                                qv[kk][rr] = qf[ii];
+                            }
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < KB; ++kk) {
+                            if (k0 + kk >= O) continue;
+                            const int k = k0 + kk;
+                            float acc = 0.0f;
+#pragma unroll
+                            for (int rr = 0; rr < R; ++rr)
+                                if (tid + rr * NTA < n) acc += pv[kk][rr] * qv[kk][rr];
+                            w[k] = on(a2, k) ? (double)acc : 0.0;
+                        }
+                    }
                 }, sm.scratch, sm.red);
                 if (tid < O && on(a2, tid)) {
                     AState &s = st[tid];
@@ -886,18 +932,50 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
 #pragma unroll 1
                 for (int k = 0; k < O; ++k)
                     if (on(a2, k) && st[k].status == 0) a3 |= 1u << k;
-                sum_cols<O>(a3, [&](int k) __attribute__((always_inline)) {
-                    float *rf = W.F(k, 0), *df = W.F(k, 2);
-                    const float *pf = W.F(k, 1);
-                    const float al = st[k].alphaf;
-                    float acc = 0.0f;
-                    for (int i = tid; i < n; i += NTA) {
-                        df[i] += al * pf[i];
-                        const float r = rf[i] - al * RSf[k * ld + i];
-                        rf[i] = r;
-                        acc += r * r;
+                // d += alpha p, r -= alpha q, r^T r: three columns' loads per round trip
+                block_reduce<NWA, 16, 1>([&](int, double (&w)[16]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) w[k] = 0.0;
+                    constexpr int KB = 3;
+#pragma unroll
+                    for (int k0 = 0; k0 < O; k0 += KB) {
+                        float dv[KB][R], pv[KB][R], rv[KB][R], qv[KB][R];
+#pragma unroll
+                        for (int kk = 0; kk < KB; ++kk) {
+                            if (k0 + kk >= O) continue;
+                            const int k = k0 + kk;
+                            const float *rf = W.F(k, 0), *pf = W.F(k, 1), *df = W.F(k, 2);
+                            const float *qf = RSf + k * ld;
+#pragma unroll
+                            for (int rr = 0; rr < R; ++rr) {
+                                const int i = tid + rr * NTA, ii = i < n ? i : 0;
+                                dv[kk][rr] = df[ii];
+                                pv[kk][rr] = pf[ii];
+                                rv[kk][rr] = rf[ii];
+                                qv[kk][rr] = qf[ii];
+                            }
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < KB; ++kk) {
+                            if (k0 + kk >= O) continue;
+                            const int k = k0 + kk;
+                            if (!on(a3, k)) continue;
+                            float *rf = W.F(k, 0), *df = W.F(k, 2);
+                            const float al = st[k].alphaf;
+                            float acc = 0.0f;
+#pragma unroll
+                            for (int rr = 0; rr < R; ++rr) {
+                                const int i = tid + rr * NTA;
+                                if (i < n) {
+                                    df[i] = dv[kk][rr] + al * pv[kk][rr];
+                                    const float r = rv[kk][rr] - al * qv[kk][rr];
+                                    rf[i] = r;
+                                    acc += r * r;
+                                }
+                            }
+                            w[k] = (double)acc;
+                        }
                     }
-                    return (double)acc;
                 }, sm.scratch, sm.red);
                 if (tid < O && on(a2, tid) && st[tid].status == 0) {
                     AState &s = st[tid];
@@ -908,14 +986,39 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                     ++s.it;
                 }
                 __syncthreads();
-#pragma unroll 1
-                for (int k = 0; k < O; ++k)
-                    if (on(a2, k) && st[k].status == 0) {
-                        const float *rf = W.F(k, 0);
-                        float *pf = W.F(k, 1);
-                        const float be = st[k].betaf;
-                        for (int i = tid; i < n; i += NTA) pf[i] = rf[i] + be * pf[i];
+                // p = r + beta p, three columns' loads per round trip
+                {
+                    constexpr int KB = 3;
+#pragma unroll
+                    for (int k0 = 0; k0 < O; k0 += KB) {
+                        float rv[KB][R], pv[KB][R];
+#pragma unroll
+                        for (int kk = 0; kk < KB; ++kk) {
+                            if (k0 + kk >= O) continue;
+                            const int k = k0 + kk;
+                            const float *rf = W.F(k, 0), *pf = W.F(k, 1);
+#pragma unroll
+                            for (int rr = 0; rr < R; ++rr) {
+                                const int i = tid + rr * NTA, ii = i < n ? i : 0;
+                                rv[kk][rr] = rf[ii];
+                                pv[kk][rr] = pf[ii];
+                            }
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < KB; ++kk) {
+                            if (k0 + kk >= O) continue;
+                            const int k = k0 + kk;
+                            if (!(on(a2, k) && st[k].status == 0)) continue;
+                            float *pf = W.F(k, 1);
+                            const float be = st[k].betaf;
+#pragma unroll
+                            for (int rr = 0; rr < R; ++rr) {
+                                const int i = tid + rr * NTA;
+                                if (i < n) pf[i] = rv[kk][rr] + be * pv[kk][rr];
+                            }
+                        }
                     }
+                }
             }
             __syncthreads();
 #pragma unroll 1
@@ -1056,20 +1159,20 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             if (!go) break;
             // S and H of the pending vectors (RS, RH; RSb, RHb), H of the chain vectors (RH2)
             if (m1) {
-                stage_set<O, double, double>(xsd, n, m1, [&](int k) { return W.P(k); });
+                stage_set<O, R, double, double>(xsd, n, m1, W.Z(0), [&](int k) { return W.P(k); });
                 __syncthreads();
                 spmm_set<O, float, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS, ld});
                 __syncthreads();
             }
             if (m2) {
-                stage_set<O, double, double>(xsd, n, m2, [&](int k) { return W.P2(k); });
+                stage_set<O, R, double, double>(xsd, n, m2, W.Z(0), [&](int k) { return W.P2(k); });
                 __syncthreads();
                 spmm_set<O, float, double, true, true>(S, g, Hv, Sv, xsd,
                                                        ToRows<O, double, true, true>{RHb, RSb, ld});
                 __syncthreads();
             }
             if (ch) {
-                stage_set<O, double, double>(xsd, n, ch, [&](int k) { return W.Z(k); });
+                stage_set<O, R, double, double>(xsd, n, ch, W.Z(0), [&](int k) { return W.Z(k); });
                 __syncthreads();
                 spmm_set<O, float, double, true, false>(S, g, Hv, Sv, xsd,
                                                         ToRows<O, double, true, false>{RH2, nullptr, ld});
@@ -1106,27 +1209,56 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             dot_sweep_pairs<O, 4 * R>(sm.pjobs, ld, n);
             __syncthreads();
 
+            // the coefficient sums of column k, one wavefront per column:
+            // |a1|^2, |c1|^2, |a2|^2, |c2|^2 (c: first- plus second-pass
+            // coefficients), a1.a2, a1.b3, a2.b3, a1.b4, a2.b4 and, for the
+            // chain, |a_T|^2, |c_T|^2, a_T.b_T -> scratch[16 k + 0..11]
+#pragma unroll 1
+            for (int k = wv; k < O; k += NWA) {
+                const AState &s = st[k];
+                if (!s.live) continue;
+                const double *a1 = W.CA(k), *a2 = W.CA2(k);
+                const double *b3 = W.CB(k, s.ping), *b4 = W.CB4(k, s.ping);
+                const double *cp1 = W.CB(k, s.ping ^ 1), *cp2 = W.CB4(k, s.ping ^ 1);
+                const double *cat = W.CAT(k);
+                const double *ctb = W.CTB(k, s.ping), *ctp = W.CTB(k, s.ping ^ 1);
+                double v[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = 0.0;
+                for (int m = lane; m < s.L; m += 64) {
+                    const double x1 = a1[m], x2 = a2[m], y3 = b3[m], y4 = b4[m];
+                    const double c1 = s.cp_scale * cp1[m] + x1, c2 = s.cp2_scale * cp2[m] + x2;
+                    v[0] += x1 * x1;
+                    v[1] += c1 * c1;
+                    v[2] += x2 * x2;
+                    v[3] += c2 * c2;
+                    v[4] += x1 * x2;
+                    v[5] += x1 * y3;
+                    v[6] += x2 * y3;
+                    v[7] += x1 * y4;
+                    v[8] += x2 * y4;
+                }
+                if (s.chain_live)
+                    for (int m = lane; m < s.kch; m += 64) {
+                        const double x = cat[m], c = s.ctp_scale * ctp[m] + x;
+                        v[9] += x * x;
+                        v[10] += c * c;
+                        v[11] += x * ctb[m];
+                    }
+                wave_transpose_reduce<16>(v);
+                if (tr_writer<16>(lane)) sm.scratch[16 * k + tr_index<16>(lane)] = v[0];
+            }
+            __syncthreads();
+
             // decisions of column k, by thread k
             if (tid < O && st[tid].live) {
                 AState &s = st[tid];
-                const double *sc = sm.psc + 12 * tid;
-                const double *a1 = W.CA(tid), *a2 = W.CA2(tid);
-                const double *b3 = W.CB(tid, s.ping), *b4 = W.CB4(tid, s.ping);
-                const double *cp1 = W.CB(tid, s.ping ^ 1), *cp2 = W.CB4(tid, s.ping ^ 1);
-                const double *cat = W.CAT(tid);
-                const double *ctb = W.CTB(tid, s.ping), *ctp = W.CTB(tid, s.ping ^ 1);
-                const int L = s.L;
+                const double *sc = sm.psc + 12 * tid, *d = sm.scratch + 16 * tid;
                 // the first pending vector: beta1^2 = p1^T S p1 - |a1|^2
                 bool acc1 = false;
                 double ib1 = 1.0;
                 if (s.np >= 1) {
-                    double asq = 0.0, tot = 0.0;
-                    for (int m = 0; m < L; ++m) {
-                        const double cm = s.cp_scale * cp1[m] + a1[m];
-                        asq += a1[m] * a1[m];
-                        tot += cm * cm;
-                    }
-                    const double bb = sc[0] - asq, b0 = bb + tot;
+                    const double bb = sc[0] - d[0], b0 = bb + d[1];
                     acc1 = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
                     if (acc1) ib1 = 1.0 / sqrt(bb);
                 }
@@ -1134,46 +1266,28 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
                 bool acc2 = false;
                 double ib2 = 1.0, gg = 0.0;
                 if (s.np == 2) {
-                    double asq = 0.0, tot = 0.0, x = 0.0;
-                    for (int m = 0; m < L; ++m) {
-                        const double cm = s.cp2_scale * cp2[m] + a2[m];
-                        asq += a2[m] * a2[m];
-                        tot += cm * cm;
-                        x += a1[m] * a2[m];
-                    }
-                    gg = acc1 ? (sc[1] - x) * ib1 : 0.0;
-                    const double bb = sc[5] - asq - gg * gg, b0 = bb + tot + gg * gg;
+                    gg = acc1 ? (sc[1] - d[4]) * ib1 : 0.0;
+                    const double bb = sc[5] - d[2] - gg * gg, b0 = bb + d[3] + gg * gg;
                     acc2 = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
                     if (acc2) ib2 = 1.0 / sqrt(bb);
                 }
                 // the candidates' coefficients on u1 and u2
                 double f[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-                for (int c = 0; c < s.nc; ++c) {
-                    const double *b = c == 0 ? b3 : b4;
-                    double ab1 = 0.0, ab2 = 0.0;
-                    for (int m = 0; m < L; ++m) {
-                        ab1 += a1[m] * b[m];
-                        ab2 += a2[m] * b[m];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (c < s.nc) {
+                        f[c][0] = acc1 ? (sc[2 + c] - d[5 + 2 * c]) * ib1 : 0.0;
+                        f[c][1] = acc2 ? (sc[6 + c] - d[6 + 2 * c] - gg * f[c][0]) * ib2 : 0.0;
                     }
-                    f[c][0] = acc1 ? (sc[2 + c] - ab1) * ib1 : 0.0;
-                    f[c][1] = acc2 ? (sc[6 + c] - ab2 - gg * f[c][0]) * ib2 : 0.0;
-                }
                 // the chain vector
                 bool acc_t = false;
                 double eta = 1.0, ft = 0.0;
                 if (s.chain_live) {
-                    double asq = 0.0, tot = 0.0, ab = 0.0;
-                    for (int m = 0; m < s.kch; ++m) {
-                        const double cm = s.ctp_scale * ctp[m] + cat[m];
-                        asq += cat[m] * cat[m];
-                        tot += cm * cm;
-                        ab += cat[m] * ctb[m];
-                    }
-                    const double ee = sc[8] - asq, e0 = ee + tot;
+                    const double ee = sc[8] - d[9], e0 = ee + d[10];
                     acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
                     if (acc_t) {
                         eta = sqrt(ee);
-                        ft = (sc[9] - ab) / eta;
+                        ft = (sc[9] - d[11]) / eta;
                     }
                 }
                 // a block-1 candidate needs its source accepted, the chain
@@ -1339,7 +1453,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
 
             // pass 1: H and S of the vectors finished in the previous step
             if (!DERIVE && fin) {
-                stage_set<O, double, double>(xsd, n, fin,
+                stage_set<O, R, double, double>(xsd, n, fin, W.Z(0),
                                              [&](int k) { return W.U(k) + (st[k].L - 1) * ld; });
                 __syncthreads();
                 spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd,
@@ -1363,7 +1477,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             if (!rest) continue;
             // pass 2: S and H of the pending vectors (RS, RH; FP64 values: H only
             // while block 1 runs)
-            stage_set<O, double, double>(xsd, n, rest, [&](int k) { return W.P(k); });
+            stage_set<O, R, double, double>(xsd, n, rest, W.Z(0), [&](int k) { return W.P(k); });
             __syncthreads();
             if (DERIVE || b1)
                 spmm_set<O, TM, double, true, true>(S, g, Hv, Sv, xsd, ToRows<O, double, true, true>{RH, RS, ld});
@@ -1373,7 +1487,7 @@ __device__ void basis_atom(const DevSystem &S, const DevJob &J, const SmemA &sm,
             // pass 3: H of the pending chain vectors into RH2 (RH keeps H of the
             // pending vectors, RS their S)
             if (ch) {
-                stage_set<O, double, double>(xsd, n, ch, [&](int k) { return W.Z(k); });
+                stage_set<O, R, double, double>(xsd, n, ch, W.Z(0), [&](int k) { return W.Z(k); });
                 __syncthreads();
                 spmm_set<O, TM, double, true, false>(S, g, Hv, Sv, xsd,
                                                      ToRows<O, double, true, false>{RH2, nullptr, ld});
