@@ -13,8 +13,9 @@
 //           FP64 values only: with FP32 values the images of a finished
 //           vector come from pass 2 over its pending form, see the loop)
 //   pass 2  S and H of the pending vectors (FP64 values: H only while
-//           block 1 runs)
-//   pass 3  H of the pending block-2 chain vectors
+//           block 1 runs; FP32 values: two sets when block 2 finishes two
+//           vectors per step, see the loop)
+//   pass 3  H of the pending chain vectors (the Euclidean chain on s_j)
 //
 // The staged set lives in LDS as [row][column] (o doubles per row); a thread
 // takes two rows of one atom at a time, so the o x o staged entries of a
@@ -706,9 +707,16 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             return a;
         }, sm.scratch, sm.red);
     };
+    // columns whose first residual needs the operator (a given start); with a
+    // zero start it is e_j itself
+    __syncthreads();
+    unsigned given = 0;
+#pragma unroll
+    for (int k = 0; k < O; ++k)
+        if (on(live, k) && st[k].start != 0) given |= 1u << k;
     if (PREC == 0) {
-        true_residual(live);
-        if (tid < O && on(live, tid)) {
+        if (given) true_residual(given);
+        if (tid < O && on(given, tid)) {
             AState &s = st[tid];
             s.rho2 = sm.red[tid];
             ++s.nres;
@@ -717,7 +725,7 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
         __syncthreads();
 #pragma unroll 1
         for (int k = 0; k < O; ++k)
-            if (on(live, k) && (st[k].start == 2 || st[k].start == 4)) {
+            if (on(live, k) && (st[k].start == 0 || st[k].start == 2 || st[k].start == 4)) {
                 double *Z = W.Z(k), *D = W.D(k);
                 for (int i = tid; i < n; i += NTA) {
                     Z[i] = 0.0;
@@ -725,7 +733,8 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                 }
             }
         __syncthreads();
-        if (tid < O && on(live, tid) && (st[tid].start == 2 || st[tid].start == 4)) st[tid].rho2 = 1.0;
+        if (tid < O && on(live, tid) && (st[tid].start == 0 || st[tid].start == 2 || st[tid].start == 4))
+            st[tid].rho2 = 1.0;
         for (int restart = 0; restart <= 3; ++restart) {
             __syncthreads();
             unsigned act = 0;
@@ -827,8 +836,9 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             for (int k = 0; k < O; ++k)
                 if (on(live, k) && st[k].status == 0 && !st[k].conv) jm |= 1u << k;
             if (!jm) break;
-            true_residual(jm);
-            if (tid < O && on(jm, tid)) {
+            const unsigned ev = ref == 0 ? (jm & given) : jm;
+            if (ev) true_residual(ev);
+            if (tid < O && on(ev, tid)) {
                 AState &s = st[tid];
                 s.rho2 = sm.red[tid];
                 ++s.nres;
@@ -837,7 +847,7 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             __syncthreads();
 #pragma unroll 1
             for (int k = 0; k < O; ++k)
-                if (on(jm, k) && ref == 0 && (st[k].start == 2 || st[k].start == 4)) {
+                if (on(jm, k) && ref == 0 && (st[k].start == 0 || st[k].start == 2 || st[k].start == 4)) {
                     double *Z = W.Z(k), *D = W.D(k);
                     for (int i = tid; i < n; i += NTA) {
                         Z[i] = 0.0;
@@ -847,7 +857,7 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             __syncthreads();
             if (tid < O && on(jm, tid)) {
                 AState &s = st[tid];
-                if (ref == 0 && (s.start == 2 || s.start == 4)) s.rho2 = 1.0;
+                if (ref == 0 && (s.start == 0 || s.start == 2 || s.start == 4)) s.rho2 = 1.0;
                 if (sqrt(s.rho2) <= J.cg_tol) s.conv = 1;
                 s.rho = sqrt(s.rho2);
                 s.it = 0;

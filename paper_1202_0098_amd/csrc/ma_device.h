@@ -386,14 +386,21 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
     }
     if (PREC == 0) {
         double r[R], p[R], q[R];
-        // r = e_j - S x
-        store_rows<R, NT, double>(xa, x, n);
-        __syncthreads();
-        spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+        double rho2 = 1.0;
+        if (start == 0) {
+            // zero start: the residual is e_j itself
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
-        double rho2 = block_sum<NWV>(dot_rows<R, NT>(r, r, n), red);
-        ++nres;
+            for (int rr = 0; rr < R; ++rr) r[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+        } else {
+            // r = e_j - S x
+            store_rows<R, NT, double>(xa, x, n);
+            __syncthreads();
+            spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) r[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
+            rho2 = block_sum<NWV>(dot_rows<R, NT>(r, r, n), red);
+            ++nres;
+        }
         if ((start == 1 || start == 3) && !(rho2 < 1.0)) {
             // the residual judge rejects the given start: zero start
             start += 1;
@@ -440,13 +447,20 @@ __device__ void inner_cg(const DevSystem &S, const DevJob &J, const Col &g, int 
     } else {
         double q[R], r64[R];
         for (int ref = 0; ref <= J.max_refine && status == 0; ++ref) {
-            store_rows<R, NT, double>(xa, x, n);
-            __syncthreads();
-            spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+            double rho2 = 1.0;
+            if (ref == 0 && start == 0) {
+                // zero start: the residual is e_j itself
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
-            double rho2 = block_sum<NWV>(dot_rows<R, NT>(r64, r64, n), red);
-            ++nres;
+                for (int rr = 0; rr < R; ++rr) r64[rr] = (tid + rr * NT) == g.jl ? 1.0 : 0.0;
+            } else {
+                store_rows<R, NT, double>(xa, x, n);
+                __syncthreads();
+                spmv_rows<O, R, NT, double, double, false, true, false>(S, g, o, S.Hd, S.Sd, xa, xb, dummy, q, dummy);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) r64[rr] = ((tid + rr * NT) == g.jl ? 1.0 : 0.0) - q[rr];
+                rho2 = block_sum<NWV>(dot_rows<R, NT>(r64, r64, n), red);
+                ++nres;
+            }
             if (ref == 0 && (start == 1 || start == 3) && !(rho2 < 1.0)) {
                 start += 1;
 #pragma unroll
