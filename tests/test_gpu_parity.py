@@ -116,6 +116,28 @@ def test_fp64_random_pencils(ctx, torch_cuda, n_atoms, o, seed, p, q):
         _compare(s, ora, None, gpu, FP64_RHO_TOL, FP64_E_TOL)
 
 
+@pytest.mark.parametrize("n_atoms,o,seed,p,q", [(3, 4, 1, 8, 4), (2, 9, 4, 12, 6), (6, 4, 3, 15, 9),
+                                                (6, 4, 7, 1, 9), (5, 4, 8, 2, 11), (4, 9, 5, 9, 7),
+                                                (6, 4, 9, 7, 0), (3, 4, 2, 6, 12), (2, 4, 6, 3, 8)])
+def test_mixed_atom_random_pencils(ctx, torch_cuda, n_atoms, o, seed, p, q):
+    """The atom kernel with FP32 operator values and FP64 sums, where block 2
+    finishes two vectors per step once the s_j chain runs ahead of it: block 1
+    shorter than half of block 2 (single seeds until the chain is ahead), odd
+    q (a last step with one vector), q = 0, and systems smaller than p + q,
+    whose Krylov spaces run out (breakdowns of either vector of a pair, and of
+    the chain).  Same span as the oracle's Eq. 4 basis: the effective sizes
+    agree exactly and rho to the mixed-mode tolerance."""
+    import oracle
+    s = synth.random_pencil(n_atoms, o, seed=seed)
+    ctx.build_tb(s)
+    ora = oracle.solve(s, mu=0.2, kT=0.25, p=p, q=q)
+    _say(f"pencil n={s.M} o={o} p={p} q={q} (atom basis, mixed_f64acc); oracle nu_eff "
+         f"{ora['raw']['nu_eff'].min()}..{ora['raw']['nu_eff'].max()}")
+    gpu = _gpu_solve(ctx, torch_cuda, s, None, p, q, 0.2, 0.25, precision="mixed_f64acc",
+                     basis_kernel="atom")
+    _compare(s, ora, None, gpu, MIXED_RHO_TOL["mixed_f64acc"], MIXED_E_TOL)
+
+
 @pytest.mark.parametrize("kernel", ["onchip", "workspace", "group", "atom"])
 def test_fp64_q0_generalized_arnoldi(ctx, torch_cuda, kernel):
     """q = 0: the basis is K_p(H; e_j) alone, S-orthonormalised (the
