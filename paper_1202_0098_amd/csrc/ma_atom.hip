@@ -77,8 +77,10 @@ struct AState {
     // c3m/c4m), the second pending vector's acceptance, 1/beta2, its
     // coefficient g on u1, the candidates' coefficients on u1 and u2, and
     // the scale of the second pending vector's first-pass coefficients
-    int np, pk1, tq, nc, nv, c3k, c3m, c4k, c4m, acc2;
+    int np, pk1, tq, nc, nv, c3k, c3m, c4k, c4m, acc2, defer;
     double inv_b2, g, f31, f32, f41, f42, cp2_scale;
+    // three-term chain: |H t|^2 of the last chain vector and of this step's
+    double hn2, hn2_next, eta;
 };
 
 // Column k's vectors in the workgroup's workspace (leading dimension ld).
@@ -479,12 +481,12 @@ __device__ __forceinline__ void dot_sweep_rows(const DotJob *jobs, int64_t ld, i
 // One column's share of the paired dot sweep: V rows against x[0..3] (the
 // pending vectors P1, P2 and the candidates c3, c4; null when absent) into
 // o[0..3], then the extra vectors Vx[0], Vx[1] (S P1, S P2) against the same
-// four into sc[4 e + j]; W rows against y1, y2 into p1, p2, then Wx against
-// them into sc[8], sc[9].
+// four into sc[4 e + j]; W rows against y1, y2 into p1, p2, then the extra
+// vectors Wx[0], Wx[1] against them into sc[8 + 4 e + j].
 struct PJob {
     const double *V, *W;
     const double *x[4], *Vx[2];
-    const double *y1, *y2, *Wx;
+    const double *y1, *y2, *Wx[2];
     double *o[4], *p1, *p2, *sc;
     int LV, LW;
 };
@@ -501,8 +503,8 @@ __device__ __forceinline__ void dot_sweep_pairs(const PJob *jobs, int64_t ld, in
         const int k = first ? task : task - O;
         const PJob &jb = jobs[k];
         const int L = first ? jb.LV : jb.LW;
-        const double *X0 = first ? jb.Vx[0] : jb.Wx;
-        const double *X1 = first ? jb.Vx[1] : nullptr;
+        const double *X0 = first ? jb.Vx[0] : jb.Wx[0];
+        const double *X1 = first ? jb.Vx[1] : jb.Wx[1];
         const int cnt = L + (X0 ? 1 : 0) + (X1 ? 1 : 0);
         if (cnt == 0) continue;
         const double *B = first ? jb.V : jb.W;
@@ -599,7 +601,7 @@ struct SmemA {
     AState *st;          // O column states
     DotJob *jobs;        // O dot-sweep jobs
     PJob *pjobs;         // O paired dot-sweep jobs
-    double *psc;         // 12 scalars per column of the paired dot sweep
+    double *psc;         // 16 scalars per column of the paired dot sweep
     int *srp;            // staged region block index
     int2 *sblk;
 };
@@ -1083,7 +1085,10 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
     // 1,024 rows).  The block-2 seeds come from the Euclidean chain on s_j,
     // which does not depend on the S-orthonormal basis; the chain therefore
     // advances one vector per step from the first step on, runs ahead while
-    // block 1 is built, and block 2 then takes its seeds two at a time.  A
+    // block 1 is built, and block 2 then takes its seeds two at a time.  H is
+    // symmetric, so the chain is the three-term (Lanczos) recurrence: each new
+    // chain vector is orthogonalised against the two before it only, which
+    // spans the same K_q(H; s_j) and needs no sweep over the chain.  A
     // step finishes up to two pending vectors (the second pass of the
     // delayed two-pass Gram-Schmidt, the second also against the first) and
     // projects up to two candidates once, so each dot sweep and each update
@@ -1115,7 +1120,10 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             s.chain_live = q > 0;
             s.np = p > 0 ? 1 : 0;
             s.pk1 = p > 0;
+            s.defer = 0;
             s.cp_scale = s.cp2_scale = s.ctp_scale = 1.0;
+            s.hn2 = s.hn2_next = 1.0;
+            s.eta = 0.0;
         }
         const float *Hv = S.Hf, *Sv = S.Sf;
         auto src = [&](int k, int kind, int m) __attribute__((always_inline)) -> const double * {
@@ -1205,24 +1213,24 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                 jb.Vx[0] = a && s.np >= 1 ? RS + tid * ld : nullptr;
                 jb.Vx[1] = a && s.np == 2 ? RSb + tid * ld : nullptr;
                 jb.W = W.T(tid);
-                jb.LW = a && s.chain_live ? s.kch : 0;
+                jb.LW = 0;
                 jb.y1 = W.Z(tid);
                 jb.y2 = RH2 + tid * ld;
                 jb.p1 = W.CAT(tid);
                 jb.p2 = W.CTB(tid, s.ping);
-                jb.Wx = a && s.chain_live ? W.Z(tid) : nullptr;
-                jb.sc = sm.psc + 12 * tid;
+                jb.Wx[0] = a && s.chain_live ? W.Z(tid) : nullptr;
+                jb.Wx[1] = a && s.chain_live ? RH2 + tid * ld : nullptr;
+                jb.sc = sm.psc + 16 * tid;
             }
             __syncthreads();
-            // a1, a2 = (S U)^T p1, p2; b3, b4 = (S U)^T c3, c4; chain a_T, b_T;
-            // (S p1), (S p2) against p1, p2, c3, c4; z^T z, z^T H z
+            // a1, a2 = (S U)^T p1, p2; b3, b4 = (S U)^T c3, c4; (S p1), (S p2)
+            // against p1, p2, c3, c4; z^T z, z^T H z, (H z)^T (H z)
             dot_sweep_pairs<O, 4 * R>(sm.pjobs, ld, n);
             __syncthreads();
 
             // the coefficient sums of column k, one wavefront per column:
             // |a1|^2, |c1|^2, |a2|^2, |c2|^2 (c: first- plus second-pass
-            // coefficients), a1.a2, a1.b3, a2.b3, a1.b4, a2.b4 and, for the
-            // chain, |a_T|^2, |c_T|^2, a_T.b_T -> scratch[16 k + 0..11]
+            // coefficients), a1.a2, a1.b3, a2.b3, a1.b4, a2.b4 -> scratch[16 k + 0..8]
 #pragma unroll 1
             for (int k = wv; k < O; k += NWA) {
                 const AState &s = st[k];
@@ -1230,8 +1238,6 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                 const double *a1 = W.CA(k), *a2 = W.CA2(k);
                 const double *b3 = W.CB(k, s.ping), *b4 = W.CB4(k, s.ping);
                 const double *cp1 = W.CB(k, s.ping ^ 1), *cp2 = W.CB4(k, s.ping ^ 1);
-                const double *cat = W.CAT(k);
-                const double *ctb = W.CTB(k, s.ping), *ctp = W.CTB(k, s.ping ^ 1);
                 double v[16];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) v[j] = 0.0;
@@ -1248,13 +1254,6 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                     v[7] += x1 * y4;
                     v[8] += x2 * y4;
                 }
-                if (s.chain_live)
-                    for (int m = lane; m < s.kch; m += 64) {
-                        const double x = cat[m], c = s.ctp_scale * ctp[m] + x;
-                        v[9] += x * x;
-                        v[10] += c * c;
-                        v[11] += x * ctb[m];
-                    }
                 wave_transpose_reduce<16>(v);
                 if (tr_writer<16>(lane)) sm.scratch[16 * k + tr_index<16>(lane)] = v[0];
             }
@@ -1263,7 +1262,7 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             // decisions of column k, by thread k
             if (tid < O && st[tid].live) {
                 AState &s = st[tid];
-                const double *sc = sm.psc + 12 * tid, *d = sm.scratch + 16 * tid;
+                const double *sc = sm.psc + 16 * tid, *d = sm.scratch + 16 * tid;
                 // the first pending vector: beta1^2 = p1^T S p1 - |a1|^2
                 bool acc1 = false;
                 double ib1 = 1.0;
@@ -1272,13 +1271,19 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                     acc1 = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
                     if (acc1) ib1 = 1.0 / sqrt(bb);
                 }
-                // the second: g = u1^T S p2, beta2^2 = p2^T S p2 - |a2|^2 - g^2
-                bool acc2 = false;
+                // the second: g = u1^T S p2, beta2^2 = p2^T S p2 - |a2|^2 - g^2.
+                // g is a first-pass coefficient, as large as p2, so this
+                // difference resolves beta2 only to about sqrt(eps) |p2|: when
+                // beta2^2 falls below 1e-8 p2^T S p2, p2 is finished in the next
+                // step instead, from w = p2 - U a2 - g u1, whose second pass
+                // there is small (deferred)
+                bool acc2 = false, defer = false;
                 double ib2 = 1.0, gg = 0.0;
                 if (s.np == 2) {
                     gg = acc1 ? (sc[1] - d[4]) * ib1 : 0.0;
                     const double bb = sc[5] - d[2] - gg * gg, b0 = bb + d[3] + gg * gg;
-                    acc2 = bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
+                    defer = acc1 && !(bb > 1e-8 * sc[5]);
+                    acc2 = !defer && bb > 0.0 && b0 > 0.0 && !(sqrt(bb) <= J.tau * sqrt(b0));
                     if (acc2) ib2 = 1.0 / sqrt(bb);
                 }
                 // the candidates' coefficients on u1 and u2
@@ -1289,24 +1294,30 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                         f[c][0] = acc1 ? (sc[2 + c] - d[5 + 2 * c]) * ib1 : 0.0;
                         f[c][1] = acc2 ? (sc[6 + c] - d[6 + 2 * c] - gg * f[c][0]) * ib2 : 0.0;
                     }
-                // the chain vector
+                // the chain vector z, already orthogonal to the two before it
+                // (three-term recurrence, H symmetric): t = z / eta with
+                // eta = |z|, checked against |H t_prev|, the norm before that
+                // orthogonalisation; alpha = t^T H t; |H t|^2 for the next check
                 bool acc_t = false;
                 double eta = 1.0, ft = 0.0;
                 if (s.chain_live) {
-                    const double ee = sc[8] - d[9], e0 = ee + d[10];
+                    const double ee = sc[8], e0 = s.kch == 0 ? ee : s.hn2;
                     acc_t = ee > 0.0 && sqrt(ee) > J.tau * sqrt(e0);
                     if (acc_t) {
                         eta = sqrt(ee);
-                        ft = (sc[9] - d[11]) / eta;
+                        ft = sc[9] / ee;
+                        s.hn2_next = sc[13] / ee;
                     }
                 }
                 // a block-1 candidate needs its source accepted, the chain
                 // vector of the step its own acceptance
                 int nv = s.nc;
                 if (nv >= 1 && ((s.c3k == kSrcH && !acc1) || (s.c3k == kSrcZ && !acc_t))) nv = 0;
-                if (nv == 2 && s.c4k == kSrcZ && !acc_t) nv = 1;
+                if (nv == 2 && (defer || (s.c4k == kSrcZ && !acc_t))) nv = 1;   // w takes a pending slot
                 s.acc_u = acc1;
                 s.acc2 = acc2;
+                s.defer = defer;
+                s.eta = eta;
                 s.inv_b = ib1;
                 s.inv_b2 = ib2;
                 s.g = gg;
@@ -1329,31 +1340,36 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                 if (!on(go, k)) continue;
                 const AState &s = st[k];
                 const int L = s.L, kk = s.kch, nv = s.nv;
-                const bool acc1 = s.acc_u, acc2 = s.acc2, acc_t = s.acc_t, new_chain = s.new_chain;
+                const bool acc1 = s.acc_u, acc2 = s.acc2, acc_t = s.acc_t, new_chain = s.new_chain,
+                           defer = s.defer;
                 const double ib1 = s.inv_b, ib2 = s.inv_b2, gg = s.g, ie = s.inv_e, ft = s.ft;
+                const double eta = kk > 0 ? s.eta : 0.0;
                 const double f31 = s.f31, f32 = s.f32, f41 = s.f41, f42 = s.f42, sc3 = s.sc;
                 double *U = W.U(k), *T = W.T(k), *P = W.P(k), *P2 = W.P2(k), *Z = W.Z(k);
                 double *SUd = W.SU(k), *Kd = W.K(k);
                 const double *C3 = nv >= 1 ? src(k, s.c3k, s.c3m) : Z;
                 const double *C4 = nv == 2 ? src(k, s.c4k, s.c4m) : Z;
+                const double *Tp = T + (int64_t)(kk > 0 ? kk - 1 : 0) * ld;   // the chain vector before t
                 const double *RSk = RS + k * ld, *RHk = RH + k * ld;
                 const double *RSbk = RSb + k * ld, *RHbk = RHb + k * ld, *RH2k = RH2 + k * ld;
                 const int l2 = L + (acc1 ? 1 : 0);
-                double s1[R], s2[R], s3[R], s4[R], ta[R], tb[R];
+                double s1[R], s2[R], s3[R], s4[R];
                 comb4_rows<R>(U, ld, (acc1 || acc2 || nv > 0) ? L : 0, W.CA(k), W.CA2(k), W.CB(k, s.ping),
                               W.CB4(k, s.ping), n, s1, s2, s3, s4);
-                comb2_rows<R>(T, ld, acc_t ? kk : 0, W.CAT(k), W.CTB(k, s.ping), n, ta, tb);
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr) {
                     const int i = tid + rr * NTA;
                     if (i < n) {
                         const double u1 = acc1 ? (P[i] - s1[rr]) * ib1 : 0.0;
-                        const double u2 = acc2 ? (P2[i] - s2[rr] - gg * u1) * ib2 : 0.0;
+                        const double w2 = P2[i] - s2[rr] - gg * u1;   // p2 against U and u1
+                        const double u2 = acc2 ? w2 * ib2 : 0.0;
                         const double c3 = C3[i], c4 = C4[i], zt = Z[i];
                         const double n1 = (c3 - s3[rr] - f31 * u1 - f32 * u2) * sc3;
                         const double n2 = c4 - s4[rr] - f41 * u1 - f42 * u2;
-                        const double t = (zt - ta[rr]) * ie;
-                        const double nz = (RH2k[i] - tb[rr] - ft * t) * ie;
+                        const double t = zt * ie;
+                        // next chain vector: H t - alpha t - eta t_prev
+                        const double tp = kk > 0 ? Tp[i] : 0.0;
+                        const double nz = RH2k[i] * ie - ft * t - eta * tp;
                         const double rs1 = acc1 ? RSk[i] * ib1 : 0.0, rh1 = acc1 ? RHk[i] * ib1 : 0.0;
                         if (acc_t) T[kk * ld + i] = t;
                         if (acc1) {
@@ -1366,8 +1382,9 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                             SUd[l2 * ld + i] = (RSbk[i] - gg * rs1) * ib2;
                             Kd[l2 * ld + i] = (RHbk[i] - gg * rh1) * ib2;
                         }
-                        P[i] = nv >= 1 ? n1 : 0.0;
-                        P2[i] = nv == 2 ? n2 : 0.0;
+                        // a deferred p2 goes first, as w
+                        P[i] = defer ? w2 : nv >= 1 ? n1 : 0.0;
+                        P2[i] = defer ? (nv >= 1 ? n1 : 0.0) : nv == 2 ? n2 : 0.0;
                         if (new_chain) Z[i] = nz;
                     }
                 }
@@ -1375,20 +1392,34 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
             __syncthreads();
             if (tid < O && st[tid].live) {
                 AState &s = st[tid];
-                // first-pass coefficients of the new pending vectors on u1, u2
+                // first-pass coefficients of the new pending vectors on U
+                // (from the dot sweep) and on u1, u2
                 double *b3 = W.CB(tid, s.ping), *b4 = W.CB4(tid, s.ping);
                 int l = s.L;
-                if (s.acc_u) {
-                    b3[l] = s.f31;
-                    b4[l] = s.f41;
+                if (s.defer) {
+                    // pending 1 is w (p2's coefficients on U from both passes,
+                    // and g on u1), pending 2 the candidate's projection
+                    const double *cp2 = W.CB4(tid, s.ping ^ 1), *a2 = W.CA2(tid);
+                    for (int m = 0; m < l; ++m) {
+                        b4[m] = b3[m];
+                        b3[m] = s.cp2_scale * cp2[m] + a2[m];
+                    }
+                    b3[l] = s.g;
+                    b4[l] = s.f31;
                     ++l;
+                } else {
+                    if (s.acc_u) {
+                        b3[l] = s.f31;
+                        b4[l] = s.f41;
+                        ++l;
+                    }
+                    if (s.acc2) {
+                        b3[l] = s.f32;
+                        b4[l] = s.f42;
+                        ++l;
+                    }
                 }
-                if (s.acc2) {
-                    b3[l] = s.f32;
-                    b4[l] = s.f42;
-                    ++l;
-                }
-                if (s.acc_t) W.CTB(tid, s.ping)[s.kch] = s.ft;
+                if (s.acc_t) s.hn2 = s.hn2_next;
                 if (s.np >= 1 && s.pk1 && s.acc_u) ++s.nb1;   // a rejected block-1 vector ends block 1
                 if (s.c3k == kSrcT || s.c3k == kSrcZ) s.tq += s.nv;
                 if (s.chain_live) {
@@ -1400,11 +1431,10 @@ __device__ __forceinline__ void basis_atom(const DevSystem &S, const DevJob &J, 
                     }
                 }
                 s.L = l;
-                s.cp_scale = s.sc;
-                s.cp2_scale = 1.0;
-                s.ctp_scale = s.inv_e;
-                s.np = s.nv;
-                s.pk1 = s.nv >= 1 && s.c3k == kSrcH;
+                s.cp_scale = s.defer ? 1.0 : s.sc;
+                s.cp2_scale = s.defer ? s.sc : 1.0;
+                s.np = s.defer ? 1 + (s.nv >= 1 ? 1 : 0) : s.nv;
+                s.pk1 = !s.defer && s.nv >= 1 && s.c3k == kSrcH;
                 s.ping ^= 1;
             }
         }
@@ -1787,7 +1817,7 @@ __global__ void __launch_bounds__(NTA, 2) k_basis_a(DevSystem S, DevJob J)
     __shared__ AState sst[O];
     __shared__ DotJob sjobs[O];
     __shared__ PJob spjobs[O];
-    __shared__ double spsc[O * 12];
+    __shared__ double spsc[O * 16];
     __shared__ double scratch[NWA * 64];
     __shared__ double red[64];
     SmemA sm;
