@@ -134,13 +134,20 @@ def main():
         log(f"fixed tuning {tuning}")
     elif not args.no_autotune:
         t0 = time.perf_counter()
-        # large systems: tune on every column of a seeded sample of atoms
-        # (about 65,536 columns; whole atoms, as the atom-lockstep kernels
-        # process all columns of an atom together)
+        # large systems: tune on every column of a compact block of atoms
+        # (about 65,536 columns: the atoms nearest to a seeded atom; whole
+        # atoms, as the atom-lockstep kernels process all columns of an atom
+        # together).  The schedules differ mostly in how much the regions of
+        # the atoms in flight together overlap, which a sample spread over
+        # the cell would not show.
         tcols = None
         if s.M > 65536:
             na = 65536 // o
-            atoms = np.sort(np.random.default_rng(99).choice(s.n_atoms, na, replace=False))
+            box = np.asarray(s.box, float)
+            c = s.pos[np.random.default_rng(99).integers(s.n_atoms)]
+            d = s.pos - c
+            d -= box * np.round(d / box)
+            atoms = np.sort(np.argsort((d * d).sum(1), kind="stable")[:na])
             tcols = (atoms[:, None] * o + np.arange(o)).ravel().astype(np.int32)
         first = ctx.solve_columns(tcols, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
         log(f"first solve {first.elapsed_ms:.1f} ms (mu {first.mu:.6f}); autotuning")

@@ -169,8 +169,13 @@ typedef struct {
  * XCD_INPUT / XCD_LPT: the (caller-ordered or LPT-ordered) list cut into one
  * contiguous chunk per XCD; workgroup b serves chunk b % 8 first (workgroups
  * are dispatched to the 8 XCDs round-robin), then steals from the others, so
- * spatially adjacent columns share an XCD's L2. */
-enum { MA_SCHED_LPT = 0, MA_SCHED_INPUT = 1, MA_SCHED_XCD_INPUT = 2, MA_SCHED_XCD_LPT = 3 };
+ * spatially adjacent columns share an XCD's L2.  SPATIAL: one queue, the atoms
+ * of each chunk in Morton order of their positions (cells of two mean atomic
+ * spacings; index order without positions), so that the columns in flight
+ * together have overlapping regions and share their operator blocks in the
+ * caches (real-space projection, Sec. 3). */
+enum { MA_SCHED_LPT = 0, MA_SCHED_INPUT = 1, MA_SCHED_XCD_INPUT = 2, MA_SCHED_XCD_LPT = 3,
+       MA_SCHED_SPATIAL = 4 };
 
 /* Outputs of ma_solve_columns.  Device pointers are optional (NULL = not
  * written) and owned by the caller. */

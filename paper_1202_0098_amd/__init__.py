@@ -72,7 +72,7 @@ class _Tuning(ctypes.Structure):
                 ("tried_pipeline", ctypes.c_int32 * 64)]
 
 
-SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3}
+SCHEDULES = {"lpt": 0, "input": 1, "xcd_input": 2, "xcd_lpt": 3, "spatial": 4}
 BASIS_KERNELS = {"auto": 0, "onchip": 1, "workspace": 2, "group": 3, "atom": 4}
 
 

@@ -108,6 +108,7 @@ struct ma_ctx {
     int nmax = 0, maxpat = 0, max_nat = 0;
     int64_t max_lnnz = 0;
     std::vector<int32_t> reg_len_of_atom;   // host: region atoms per atom (for ordering)
+    std::vector<int32_t> spatial_rank;      // host: each atom's place in Morton order (MA_SCHED_SPATIAL)
     std::vector<int64_t> lblk_of_atom;      // host: local operator blocks per atom
     std::vector<int32_t> pat_blocks;        // host: blocks in each atom's block-row
 
@@ -526,6 +527,49 @@ MA_API ma_status ma_system_info(const ma_ctx *ctx, int64_t *M, int64_t *nblk, in
     return MA_OK;
 }
 
+// Place of every atom in Morton (Z-order) order of cells of edge two mean
+// atomic spacings, ties by index; the index order without positions.  Atoms
+// that are close in this order are close in space, so workgroups that run
+// them at the same time share much of their region operators in the caches.
+void spatial_order(int n, const double *xyz, const double *box, std::vector<int32_t> &rank)
+{
+    rank.resize(n);
+    std::vector<int32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    if (xyz) {
+        double lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = box ? 0.0 : xyz[d];
+            hi[d] = box ? box[d] : xyz[d];
+        }
+        auto coord = [&](int a, int d) {
+            double v = xyz[3 * a + d];
+            if (box) v -= box[d] * std::floor(v / box[d]);
+            return v;
+        };
+        if (!box)
+            for (int a = 0; a < n; ++a)
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = std::min(lo[d], xyz[3 * a + d]);
+                    hi[d] = std::max(hi[d], xyz[3 * a + d]);
+                }
+        const double vol = std::max(1e-30, (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
+        const double h = std::max(1e-12, 2.0 * std::cbrt(vol / n));
+        std::vector<uint64_t> code(n, 0);
+        for (int a = 0; a < n; ++a) {
+            uint64_t c = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double x = (coord(a, d) - lo[d]) / h;
+                const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(x)));
+                for (int b = 0; b < 21; ++b) c |= ((q >> b) & 1u) << (3 * b + d);
+            }
+            code[a] = c;
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return code[x] < code[y]; });
+    }
+    for (int i = 0; i < n; ++i) rank[idx[i]] = i;
+}
+
 MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_region *reg)
 {
     if (!ctx) return MA_EINVAL;
@@ -812,6 +856,7 @@ MA_API ma_status ma_build_system(ma_ctx *ctx, const ma_system *sys, const ma_reg
         ctx->lblk_of_atom[a] = cnt[h_reg_id[a] + 1];
         ctx->pat_blocks[a] = (int32_t)(bp[a + 1] - bp[a]);
     }
+    spatial_order(n, sys->xyz, sys->box, ctx->spatial_rank);
     ctx->built = true;
     return MA_OK;
 }
@@ -949,7 +994,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     if (opts.keep_sj != 0 && opts.keep_sj != 1) return ctx->fail(MA_EINVAL, "keep_sj must be 0 or 1");
     if (opts.start == MA_START_LEARNED && !(ctx->net.ready && ctx->have_geo))
         return ctx->fail(MA_EINVAL, "learned start needs a start model and positions");
-    if (opts.schedule < -1 || opts.schedule > MA_SCHED_XCD_LPT)
+    if (opts.schedule < -1 || opts.schedule > MA_SCHED_SPATIAL)
         return ctx->fail(MA_EINVAL, "unknown schedule %d", opts.schedule);
     if (cols == nullptr) ncols = ctx->M;
     if (ncols < 1 || ncols > INT_MAX) return ctx->fail(MA_EINVAL, "ncols out of range");
@@ -1080,6 +1125,7 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
     const int nitems = (int)item_start.size() - 1;
     auto item_len = [&](int w) { return item_start[w + 1] - item_start[w]; };
     auto item_region = [&](int w) { return ctx->reg_len_of_atom[P.hcols[item_cols[item_start[w]]] / o]; };
+    auto item_atom = [&](int w) { return P.hcols[item_cols[item_start[w]]] / o; };
 
     // chunks: whole work items, at most the chunk budget of columns each
     J.mid_stride = ma::mid_stride_of(P.nu, ctx->maxpat);
@@ -1143,6 +1189,10 @@ ma_status make_plan(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p, 
         for (int i = 0; i <= J.nqueues; ++i)
             qb[(size_t)k * (J.nqueues + 1) + i] = (int32_t)(w0 + (int64_t)nw * i / J.nqueues);
         if (P.sched == MA_SCHED_LPT) lpt(witem.begin() + w0, witem.begin() + w1);
+        if (P.sched == MA_SCHED_SPATIAL)
+            std::stable_sort(witem.begin() + w0, witem.begin() + w1, [&](int32_t x, int32_t y) {
+                return ctx->spatial_rank[item_atom(x)] < ctx->spatial_rank[item_atom(y)];
+            });
         if (P.sched == MA_SCHED_XCD_LPT)
             for (int i = 0; i < J.nqueues; ++i)
                 lpt(witem.begin() + qb[(size_t)k * (J.nqueues + 1) + i],
@@ -1786,7 +1836,7 @@ MA_API ma_status ma_set_tuning(ma_ctx *ctx, int32_t p, int32_t q, int32_t precis
                                int32_t pipeline)
 {
     if (!ctx) return MA_EINVAL;
-    if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_XCD_LPT ||
+    if (slots_per_cu < 1 || schedule < 0 || schedule > MA_SCHED_SPATIAL ||
         basis_kernel < MA_BASIS_AUTO || basis_kernel > MA_BASIS_ATOM || pipeline < -1)
         return ctx->fail(MA_EINVAL, "invalid tuning");
     for (auto &t : ctx->tunes)
@@ -1875,7 +1925,7 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
         const int max_bpc = std::max(1, P0.slots / std::max(1, ctx->cu_count));
         double kbest = INFINITY;
         int kb_sched = 0, kb_bpc = 1;
-        for (int sched = 0; sched <= MA_SCHED_XCD_LPT; ++sched)
+        for (int sched = 0; sched <= MA_SCHED_SPATIAL; ++sched)
             for (int bpc = 1; bpc <= max_bpc && out->n_tried < 63; ++bpc) {
                 double best;
                 s = trial(kern, sched, bpc, pipe_on, best);

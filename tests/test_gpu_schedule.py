@@ -42,7 +42,7 @@ def test_schedules_give_identical_results(env):
     torch, ma, ctx, s = env
     cols = np.arange(0, s.M, 5, dtype=np.int32)
     ref = None
-    for sched in ["lpt", "input", "xcd_input", "xcd_lpt"]:
+    for sched in ["lpt", "input", "xcd_input", "xcd_lpt", "spatial"]:
         for slots in [1, 3]:
             _say(f"schedule {sched} slots/CU {slots}")
             res, rho = _run(torch, ma, ctx, s, cols, schedule=sched, slots_per_cu=slots,
@@ -51,6 +51,20 @@ def test_schedules_give_identical_results(env):
                 ref = (res, rho)
             assert np.array_equal(rho, ref[1])
             assert res.energy == ref[0].energy and res.mu == ref[0].mu
+
+
+def test_spatial_schedule_atom_kernel(env):
+    """The Morton-ordered queue with the atom kernel (chunks of whole atoms)
+    gives the input-order result bit for bit."""
+    torch, ma, ctx, s = env
+    cols = np.arange(0, s.M, dtype=np.int32)
+    out = {}
+    for sched in ["input", "spatial"]:
+        _say(f"atom kernel, schedule {sched}")
+        out[sched] = _run(torch, ma, ctx, s, cols, schedule=sched, slots_per_cu=2,
+                          basis_kernel="atom", chunk_columns=4000, use_graph=0)
+    assert np.array_equal(out["input"][1], out["spatial"][1])
+    assert out["input"][0].energy == out["spatial"][0].energy
 
 
 def test_graph_replay_matches_eager(env):
