@@ -151,7 +151,7 @@ def main():
             tcols = (atoms[:, None] * o + np.arange(o)).ravel().astype(np.int32)
         first = ctx.solve_columns(tcols, s.p, s.q, mu=math.nan, kT=s.kT, opts=opts)
         log(f"first solve {first.elapsed_ms:.1f} ms (mu {first.mu:.6f}); autotuning")
-        tuning = ctx.autotune(tcols, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=1)
+        tuning = ctx.autotune(tcols, s.p, s.q, mu=first.mu, kT=s.kT, opts=opts, reps=2)
         log(f"autotune ({time.perf_counter() - t0:.1f}s): {tuning['basis_kernel']} basis kernel, "
             f"{tuning['slots_per_cu']} slots/CU, schedule {tuning['schedule']}, pipeline "
             f"{tuning['pipeline']}, {tuning['best_ms']:.2f} ms; tried "

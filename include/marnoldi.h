@@ -417,10 +417,14 @@ MA_API ma_status ma_mlp_train_step(ma_ctx *ctx, const float *x, const float *t, 
  * columns of Sec. 2 independently): time the solve on cols[0..ncols) (NULL = all) for every
  * candidate -- basis kernel (each one that can hold the shape) x
  * slots per CU from 1 to that kernel's occupancy limit x every schedule, with
- * the pipeline option of opts (-1: 4), and each kernel's fastest
- * configuration again with pipelining off --
+ * the pipeline option of opts (-1: 4), and each kernel's fastest slots per
+ * CU again with pipelining off, every schedule --
  * `reps` times each at chemical potential mu (finite), and keep the fastest
- * configuration for this (p, q, opts->precision) in the context; solves with
+ * configuration for this (p, q, opts->precision) in the context, except that
+ * when cols is a proper subset of the columns, among trials of its kernel,
+ * slots and pipelining within 2 % of it the schedule is taken in the order
+ * SPATIAL, INPUT, XCD_INPUT, XCD_LPT, LPT (a sample of the columns cannot
+ * resolve the schedules' cache effects); solves with
  * basis_kernel = MA_BASIS_AUTO, slots_per_cu = 0, schedule = -1 and
  * pipeline = -1 then use it.  Outputs (rho, pi) are not written. */
 MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, int32_t p,

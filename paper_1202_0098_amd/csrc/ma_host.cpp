@@ -1936,12 +1936,39 @@ MA_API ma_status ma_autotune(ma_ctx *ctx, int64_t ncols, const int32_t *cols, in
                     kb_bpc = bpc;
                 }
             }
-        // the kernel's fastest configuration with the chunks in sequence
-        if (pipe_on >= 2 && std::isfinite(kbest) && out->n_tried < 64) {
+        // the kernel's fastest workgroup count with the chunks in sequence,
+        // every schedule
+        for (int sched = 0; pipe_on >= 2 && std::isfinite(kbest) && sched <= MA_SCHED_SPATIAL &&
+                            out->n_tried < 64; ++sched) {
             double best;
-            s = trial(kern, kb_sched, kb_bpc, 0, best);
+            s = trial(kern, sched, kb_bpc, 0, best);
             if (s != MA_OK) return s;
         }
+        (void)kb_sched;
+    }
+    // The schedules differ in how the columns in flight share the caches,
+    // which a trial on a sample of the columns measures only roughly (on the
+    // 262,144-atom cell LPT order is 6 % slower than Morton order, but on a
+    // sample the two can come out within 1 %).  When the trials ran on a
+    // sample, among those with the best one's kernel, workgroups per CU and
+    // pipelining that lie within 2 % of it, the schedule is taken in the order
+    // spatial, input, per-XCD input, per-XCD LPT, LPT.  Trials on every
+    // column measure the solve itself and decide alone.
+    if (cols && ncols < ctx->M) {
+        static const int pref[5] = {4, 1, 2, 3, 0};   // rank of MA_SCHED_LPT .. MA_SCHED_SPATIAL
+        int bi = -1;
+        for (int t = 0; t < out->n_tried; ++t)
+            if (out->tried_kernel[t] == out->basis_kernel && out->tried_slots[t] == out->slots_per_cu &&
+                out->tried_pipeline[t] == out->pipeline && out->tried_schedule[t] == out->schedule)
+                bi = t;
+        const double lim = bi >= 0 ? 1.02 * out->tried_ms[bi] : 0.0;
+        for (int t = 0; bi >= 0 && t < out->n_tried; ++t)
+            if (out->tried_kernel[t] == out->basis_kernel && out->tried_slots[t] == out->slots_per_cu &&
+                out->tried_pipeline[t] == out->pipeline && out->tried_ms[t] <= lim &&
+                pref[out->tried_schedule[t]] < pref[out->schedule]) {
+                out->schedule = out->tried_schedule[t];
+                out->best_ms = out->tried_ms[t];
+            }
     }
     return ma_set_tuning(ctx, p, q, o.precision, out->slots_per_cu, out->schedule,
                          out->basis_kernel, out->pipeline);

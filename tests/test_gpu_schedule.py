@@ -105,9 +105,23 @@ def test_autotune_then_auto_solve(env):
     t = ctx.autotune(cols, s.p, s.q, mu=0.9, kT=s.kT, reps=1)
     _say(f"autotune chose the {t['basis_kernel']} basis kernel, {t['slots_per_cu']} slots/CU, "
          f"schedule {t['schedule']}, {t['best_ms']:.2f} ms of {len(t['tried'])} candidates")
+    # every column: the fastest trial decides alone
+    t_all = ctx.autotune(None, s.p, s.q, mu=0.9, kT=s.kT, reps=1)
+    assert t_all["best_ms"] == min(m for _, _, m, _ in t_all["tried"])
     assert t["slots_per_cu"] >= 1 and len(t["tried"]) >= 8
     assert {k for _, _, _, k in t["tried"]} == {"onchip", "workspace", "group", "atom"}
-    assert t["best_ms"] == min(m for _, _, m, _ in t["tried"])
+    # (tuned on a sample of the columns) the fastest trial, or a schedule
+    # preferred to it among the trials of its kernel, slots and pipelining
+    # within 2 % of it
+    fastest = min(m for _, _, m, _ in t["tried"])
+    assert fastest <= t["best_ms"] <= 1.02 * fastest
+    same = [(sch, m) for (sl, sch, m, k), pl in zip(t["tried"], t["tried_pipeline"])
+            if k == t["basis_kernel"] and sl == t["slots_per_cu"] and pl == t["pipeline"]]
+    assert (t["schedule"], t["best_ms"]) in same
+    order = ["spatial", "input", "xcd_input", "xcd_lpt", "lpt"]
+    best_in_group = min(m for _, m in same)
+    assert best_in_group == fastest
+    assert all(order.index(sch) >= order.index(t["schedule"]) for sch, m in same if m <= 1.02 * fastest)
     res, rho = _run(torch, ma, ctx, s, cols, mu=0.9)
     ref, rho_ref = _run(torch, ma, ctx, s, cols, mu=0.9, schedule="lpt", slots_per_cu=1)
     assert np.array_equal(rho, rho_ref)
