@@ -118,15 +118,18 @@ def test_fp64_random_pencils(ctx, torch_cuda, n_atoms, o, seed, p, q):
 
 @pytest.mark.parametrize("n_atoms,o,seed,p,q", [(3, 4, 1, 8, 4), (2, 9, 4, 12, 6), (6, 4, 3, 15, 9),
                                                 (6, 4, 7, 1, 9), (5, 4, 8, 2, 11), (4, 9, 5, 9, 7),
-                                                (6, 4, 9, 7, 0), (3, 4, 2, 6, 12), (2, 4, 6, 3, 8)])
+                                                (6, 4, 9, 7, 0), (3, 4, 2, 6, 12), (2, 4, 6, 3, 8),
+                                                (1, 9, 3, 4, 20), (2, 4, 11, 2, 20)])
 def test_mixed_atom_random_pencils(ctx, torch_cuda, n_atoms, o, seed, p, q):
     """The atom kernel with FP32 operator values and FP64 sums, where block 2
     finishes two vectors per step once the s_j chain runs ahead of it: block 1
     shorter than half of block 2 (single seeds until the chain is ahead), odd
     q (a last step with one vector), q = 0, and systems smaller than p + q,
     whose Krylov spaces run out (breakdowns of either vector of a pair, and of
-    the chain).  Same span as the oracle's Eq. 4 basis: the effective sizes
-    agree exactly and rho to the mixed-mode tolerance."""
+    the chain; a second vector whose beta cannot be resolved in its pair is
+    finished one step later, e.g. (2, 4, 6, 3, 8) and (1, 9, 3, 4, 20)).  Same
+    span as the oracle's Eq. 4 basis: the effective sizes agree exactly and
+    rho to the mixed-mode tolerance."""
     import oracle
     s = synth.random_pencil(n_atoms, o, seed=seed)
     ctx.build_tb(s)
